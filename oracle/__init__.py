@@ -1,0 +1,236 @@
+"""FP64 CPU oracle of the differentiable Voronoi ray walk (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the
+benchmark's CPU-baseline leg use this package; the GPU library never does.
+The arithmetic lives in ``oracle.c`` (plain C, double precision, pthreads);
+this module only marshals numpy arrays. Every float input is widened to
+float64 exactly before the call.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+BAD_START = -1
+MAX_STEPS = -2
+DEFAULT_EPS = 1e-4
+DEFAULT_MAX_STEPS = 8192
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-pthread",
+                               "-D_GNU_SOURCE", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Scene(ctypes.Structure):
+    _fields_ = [("sites", ctypes.c_void_p), ("off", ctypes.c_void_p), ("idx", ctypes.c_void_p),
+                ("density", ctypes.c_void_p), ("sh", ctypes.c_void_p),
+                ("n_sites", ctypes.c_int64), ("sh_deg", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        lib.orc_sh_basis.argtypes = [ctypes.c_int, P, ctypes.c_int64, P]
+        lib.orc_raygen.argtypes = [P, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P]
+        lib.orc_face_planes.argtypes = [P, P, P, ctypes.c_int64, P]
+        lib.orc_bf16_round.argtypes = [P, P, ctypes.c_int64]
+        lib.orc_bf16_round.restype = None
+        lib.orc_check_csr.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64]
+        lib.orc_forward.argtypes = [ctypes.POINTER(_Scene), P, P, P, P, ctypes.c_int64, ctypes.c_double,
+                                    ctypes.c_int32, ctypes.c_int, P, P, P]
+        lib.orc_trace.argtypes = [ctypes.POINTER(_Scene), P, P, P, P, ctypes.c_int64, ctypes.c_double,
+                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int, P, P, P, P, P, P, P, P, P]
+        lib.orc_backward.argtypes = [ctypes.POINTER(_Scene), P, P, P, P, ctypes.c_int64, ctypes.c_double,
+                                     ctypes.c_int32, P, P, ctypes.c_int, P, P, P]
+        _lib = lib
+    return _lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        raise ValueError(f"oracle {what} rejected its arguments (code {rc})")
+
+
+def default_threads() -> int:
+    return max(1, min(os.cpu_count() or 1, 64))
+
+
+class OracleScene:
+    """Scene arrays widened to float64 and held alive for the C calls."""
+
+    def __init__(self, sites, off, idx, density, sh, sh_deg: int):
+        self.sites = _f64(sites).reshape(-1, 3)
+        self.off = _i32(off)
+        self.idx = _i32(idx)
+        self.density = _f64(density).reshape(-1)
+        b = (sh_deg + 1) ** 2
+        self.sh = _f64(sh).reshape(-1, b, 3)
+        self.sh_deg = int(sh_deg)
+        n = self.sites.shape[0]
+        if self.off.shape[0] != n + 1 or self.density.shape[0] != n or self.sh.shape[0] != n:
+            raise ValueError("scene arrays disagree on the number of sites")
+        self._c = _Scene(_ptr(self.sites), _ptr(self.off), _ptr(self.idx), _ptr(self.density), _ptr(self.sh),
+                         n, self.sh_deg)
+
+    @classmethod
+    def from_scene(cls, scene, density=None, sh=None) -> "OracleScene":
+        return cls(scene.sites, scene.off, scene.idx, scene.density if density is None else density,
+                   scene.sh if sh is None else sh, scene.sh_deg)
+
+    @property
+    def n_sites(self) -> int:
+        return self.sites.shape[0]
+
+    @property
+    def B(self) -> int:
+        return (self.sh_deg + 1) ** 2
+
+
+def sh_basis(deg: int, dirs) -> np.ndarray:
+    """Real SH basis [n, (deg+1)^2] of unit directions [n, 3]."""
+    d = _f64(dirs).reshape(-1, 3)
+    out = np.empty((d.shape[0], (deg + 1) ** 2))
+    _check(_load().orc_sh_basis(deg, _ptr(d), d.shape[0], _ptr(out)), "sh_basis")
+    return out
+
+
+def raygen(pose12, fov_deg: float, width: int, height: int, bound: tuple):
+    """Pinhole rays in 8x8 tile order. Returns (origin, dir, tmax, pixel)."""
+    pose = _f64(pose12).reshape(12)
+    kind, params = encode_bound(bound)
+    R = width * height
+    o = np.empty((R, 3))
+    d = np.empty((R, 3))
+    t = np.empty(R)
+    px = np.empty(R, dtype=np.int32)
+    _check(_load().orc_raygen(_ptr(pose), float(fov_deg), int(width), int(height), kind, _ptr(params),
+                              _ptr(o), _ptr(d), _ptr(t), _ptr(px)), "raygen")
+    return o, d, t, px
+
+
+def encode_bound(bound: tuple):
+    if bound[0] == "box":
+        lo, hi = bound[1], bound[2]
+        lo = np.broadcast_to(np.asarray(lo, dtype=np.float64), (3,))
+        hi = np.broadcast_to(np.asarray(hi, dtype=np.float64), (3,))
+        return 0, _f64(np.concatenate([lo, hi]))
+    if bound[0] == "sphere":
+        return 1, _f64([bound[1], 0, 0, 0, 0, 0])
+    raise ValueError(bound)
+
+
+def face_planes(sites, off, idx) -> np.ndarray:
+    """[E, 4] planes (n = x_j - x_i, c = n.(x_i + x_j)/2) in float64."""
+    s = _f64(sites).reshape(-1, 3)
+    o = _i32(off)
+    i = _i32(idx)
+    out = np.empty((i.shape[0], 4))
+    _check(_load().orc_face_planes(_ptr(s), _ptr(o), _ptr(i), s.shape[0], _ptr(out)), "face_planes")
+    return out
+
+
+def bf16_round(x) -> np.ndarray:
+    """float32 -> bfloat16 bit patterns (uint16), round to nearest even."""
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    out = np.empty(a.shape, dtype=np.uint16)
+    _load().orc_bf16_round(_ptr(a), _ptr(out), a.size)
+    return out
+
+
+def bf16_to_f32(bits) -> np.ndarray:
+    """Exact widening of bfloat16 bit patterns to float32."""
+    b = np.asarray(bits, dtype=np.uint16).astype(np.uint32) << 16
+    return b.view(np.float32)
+
+
+def check_csr(off, idx, n_sites: int) -> bool:
+    o = _i32(off)
+    i = _i32(idx)
+    return _load().orc_check_csr(_ptr(o), _ptr(i), int(n_sites), i.shape[0]) == 0
+
+
+def _rays(o, d, tmax, start):
+    o = _f64(o).reshape(-1, 3)
+    d = _f64(d).reshape(-1, 3)
+    R = d.shape[0]
+    o = np.ascontiguousarray(np.broadcast_to(o, (R, 3)))
+    t = np.ascontiguousarray(np.broadcast_to(_f64(tmax).reshape(-1), (R,)))
+    s = np.ascontiguousarray(np.broadcast_to(_i32(start).reshape(-1), (R,)))
+    return o, d, t, s, R
+
+
+def forward(scene: OracleScene, o, d, tmax, start, eps: float = DEFAULT_EPS,
+            max_steps: int = DEFAULT_MAX_STEPS, threads: Optional[int] = None):
+    """Composited colour [R,3], final transmittance [R], status/visit count [R]."""
+    o, d, t, s, R = _rays(o, d, tmax, start)
+    rgb = np.empty((R, 3))
+    tf = np.empty(R)
+    steps = np.empty(R, dtype=np.int32)
+    _check(_load().orc_forward(ctypes.byref(scene._c), _ptr(o), _ptr(d), _ptr(t), _ptr(s), R, float(eps),
+                               int(max_steps), threads or default_threads(), _ptr(rgb), _ptr(tf), _ptr(steps)),
+           "forward")
+    return rgb, tf, steps
+
+
+def trace(scene: OracleScene, o, d, tmax, start, eps: float = DEFAULT_EPS,
+          max_steps: int = DEFAULT_MAX_STEPS, max_len: int = 1024, threads: Optional[int] = None) -> dict:
+    """Forward plus per-visit cells, exit distances and decision margins."""
+    o, d, t, s, R = _rays(o, d, tmax, start)
+    out = dict(rgb=np.empty((R, 3)), t_final=np.empty(R), steps=np.empty(R, dtype=np.int32),
+               cells=np.full((R, max_len), -1, dtype=np.int32), t_exit=np.full((R, max_len), np.nan),
+               len=np.empty(R, dtype=np.int32), margin=np.empty(R), graze=np.empty(R), term=np.empty(R))
+    _check(_load().orc_trace(ctypes.byref(scene._c), _ptr(o), _ptr(d), _ptr(t), _ptr(s), R, float(eps),
+                             int(max_steps), int(max_len), threads or default_threads(),
+                             *[_ptr(out[k]) for k in ("rgb", "t_final", "steps", "cells", "t_exit", "len",
+                                                      "margin", "graze", "term")]), "trace")
+    return out
+
+
+def backward(scene: OracleScene, o, d, tmax, start, grad_rgb, grad_t=None, eps: float = DEFAULT_EPS,
+             max_steps: int = DEFAULT_MAX_STEPS, threads: Optional[int] = None):
+    """Gradients (sites [N,3], density [N], sh [N,B,3]) of sum(grad_rgb*rgb) + sum(grad_t*T)."""
+    o, d, t, s, R = _rays(o, d, tmax, start)
+    g = _f64(grad_rgb).reshape(R, 3)
+    gt = None if grad_t is None else _f64(grad_t).reshape(R)
+    n = scene.n_sites
+    gs = np.zeros((n, 3))
+    gd = np.zeros(n)
+    gsh = np.zeros((n, scene.B, 3))
+    _check(_load().orc_backward(ctypes.byref(scene._c), _ptr(o), _ptr(d), _ptr(t), _ptr(s), R, float(eps),
+                                int(max_steps), _ptr(g), _ptr(gt), threads or default_threads(),
+                                _ptr(gs), _ptr(gd), _ptr(gsh)), "backward")
+    return gs, gd, gsh

@@ -1,0 +1,629 @@
+/*
+ * FP64 CPU oracle for the differentiable Voronoi ray walk.
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the slow, plain, double-precision
+ * statement of what the GPU path computes. Only the test-suite, the smoke
+ * check and the benchmark's CPU-baseline leg load it. It shares no code,
+ * header, table or constant with the GPU library.
+ *
+ * What it computes (Radiant Foam, Sec. 3):
+ *   - Voronoi cells, eq. (5): cell i is the set of points whose nearest site
+ *     is site i. A ray leaves cell i through the bisector plane of (x_i, x_j)
+ *     for some Delaunay neighbour j (Sec. 3.2, Fig. 2 "ray_tracing").
+ *   - The ray tracing procedure of Algorithm 1 ("Render(o, d)"): start in the
+ *     cell of the origin, repeatedly take the nearest front-facing face, and
+ *     composite the segment with eq. (3)-(4) while transmittance exceeds eps.
+ *   - Colour of a cell: real spherical harmonics of degree <= 3 evaluated at
+ *     the ray direction (Sec. 3.4).
+ *   - The analytic gradient of the composited colour w.r.t. densities, SH
+ *     coefficients and site positions; geometry enters only through the
+ *     segment widths (Sec. 3.1, last paragraph).
+ *
+ * Readings where the paper is silent (each one is listed in the design notes):
+ *   - front face <=> (x_j - x_i) . d > 0 strictly; exit distance
+ *     t = (x_j - x_i).((x_i + x_j)/2 - o) / ((x_j - x_i).d).
+ *   - ties t_j == t_1 keep the first face in CSR order (strict <).
+ *   - transmittance before a segment multiplies the previous segments only
+ *     (Algorithm 1's order); eq. (3)'s stray "dt" is ignored.
+ *   - rays end at t_max: the segment that reaches t_max is clipped and the
+ *     walk stops; a cell with no front face also ends at t_max.
+ *   - the exit is clamped to be >= the entry: te = max(t0, min(t1, t_max)).
+ *   - the face shared with the previous cell is skipped.
+ *   - T > eps is tested before each cell; at most max_steps cells are visited.
+ *   - tau = sigma * delta, with tau = 0 when sigma == 0.
+ *
+ * Per-ray status (steps[]): >= 0 the number of visited cells; -1 the start
+ * cell is out of range; -2 the walk stopped because max_steps cells were
+ * visited while T > eps and the ray had not reached t_max.
+ *
+ * Return codes: 0 ok, 1 invalid argument, 2 out of memory.
+ */
+
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL 1
+#define ORC_ENOMEM 2
+
+#define ORC_BAD_START (-1)
+#define ORC_MAX_STEPS (-2)
+
+typedef struct {
+    const double *sites;   /* [N,3] */
+    const int32_t *off;    /* [N+1] */
+    const int32_t *idx;    /* [E] */
+    const double *density; /* [N] */
+    const double *sh;      /* [N,B,3] */
+    int64_t n_sites;
+    int32_t sh_deg;
+} orc_scene;
+
+/* ------------------------------------------------------------------------ */
+/* Real spherical harmonics, degree <= 3, l-major, m = -l..l.               */
+/* Textbook real form (with the Condon-Shortley phase folded in), written   */
+/* as polynomials of the unit direction (x, y, z).                          */
+/* ------------------------------------------------------------------------ */
+
+static int sh_count(int deg) { return (deg + 1) * (deg + 1); }
+
+static void sh_basis(int deg, const double d[3], double *Y)
+{
+    const double x = d[0], y = d[1], z = d[2];
+    const double pi = M_PI;
+    Y[0] = 0.5 * sqrt(1.0 / pi);
+    if (deg < 1) return;
+    const double k1 = sqrt(3.0 / (4.0 * pi));
+    Y[1] = k1 * y;
+    Y[2] = k1 * z;
+    Y[3] = k1 * x;
+    if (deg < 2) return;
+    Y[4] = 0.5 * sqrt(15.0 / pi) * x * y;
+    Y[5] = 0.5 * sqrt(15.0 / pi) * y * z;
+    Y[6] = 0.25 * sqrt(5.0 / pi) * (3.0 * z * z - 1.0);
+    Y[7] = 0.5 * sqrt(15.0 / pi) * x * z;
+    Y[8] = 0.25 * sqrt(15.0 / pi) * (x * x - y * y);
+    if (deg < 3) return;
+    Y[9] = 0.25 * sqrt(35.0 / (2.0 * pi)) * y * (3.0 * x * x - y * y);
+    Y[10] = 0.5 * sqrt(105.0 / pi) * x * y * z;
+    Y[11] = 0.25 * sqrt(21.0 / (2.0 * pi)) * y * (5.0 * z * z - 1.0);
+    Y[12] = 0.25 * sqrt(7.0 / pi) * z * (5.0 * z * z - 3.0);
+    Y[13] = 0.25 * sqrt(21.0 / (2.0 * pi)) * x * (5.0 * z * z - 1.0);
+    Y[14] = 0.25 * sqrt(105.0 / pi) * z * (x * x - y * y);
+    Y[15] = 0.25 * sqrt(35.0 / (2.0 * pi)) * x * (x * x - 3.0 * y * y);
+}
+
+int orc_sh_basis(int deg, const double *dirs, int64_t n, double *out)
+{
+    if (deg < 0 || deg > 3 || n < 0) return ORC_EINVAL;
+    const int B = sh_count(deg);
+    for (int64_t r = 0; r < n; ++r) sh_basis(deg, dirs + 3 * r, out + B * r);
+    return ORC_OK;
+}
+
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* ------------------------------------------------------------------------ */
+/* Camera rays: pinhole, 8x8 screen tiles in row-major order, pixels        */
+/* row-major inside a tile; partial tiles at the right/bottom edges hold    */
+/* only the pixels inside the image.                                        */
+/* ------------------------------------------------------------------------ */
+
+static void tile_pixel(int64_t r, int W, int H, int *px, int *py)
+{
+    const int64_t band = 8 * (int64_t)W;           /* rays in a full band of tile rows */
+    const int ty = (int)(r / band);
+    int64_t rem = r - (int64_t)ty * band;
+    const int h = (H - 8 * ty) < 8 ? (H - 8 * ty) : 8;
+    const int tx = (int)(rem / (8 * h));
+    rem -= (int64_t)tx * 8 * h;
+    const int w = (W - 8 * tx) < 8 ? (W - 8 * tx) : 8;
+    *py = 8 * ty + (int)(rem / w);
+    *px = 8 * tx + (int)(rem % w);
+}
+
+/* bound_kind 0: axis-aligned box, params = lo[3], hi[3]; 1: sphere about the
+ * world origin, params[0] = radius. The origin must lie inside. */
+static double exit_distance(int bound_kind, const double *bp, const double o[3], const double d[3])
+{
+    if (bound_kind == 0) {
+        double t = INFINITY;
+        for (int a = 0; a < 3; ++a) {
+            if (d[a] > 0.0) t = fmin(t, (bp[3 + a] - o[a]) / d[a]);
+            else if (d[a] < 0.0) t = fmin(t, (bp[a] - o[a]) / d[a]);
+        }
+        return fmax(t, 0.0);
+    }
+    const double b = dot3(o, d);
+    const double c = dot3(o, o) - bp[0] * bp[0];
+    const double disc = b * b - c;
+    return disc > 0.0 ? fmax(-b + sqrt(disc), 0.0) : 0.0;
+}
+
+int orc_raygen(const double *pose, double fov_deg, int W, int H, int bound_kind, const double *bound_params,
+               double *origin, double *dir, double *tmax, int32_t *pixel)
+{
+    if (W <= 0 || H <= 0 || !(fov_deg > 0.0 && fov_deg < 180.0) || bound_kind < 0 || bound_kind > 1)
+        return ORC_EINVAL;
+    const double f = 0.5 * W / tan(0.5 * fov_deg * M_PI / 180.0);
+    const double p[3] = {pose[3], pose[7], pose[11]};
+    const int64_t R = (int64_t)W * H;
+    for (int64_t r = 0; r < R; ++r) {
+        int px, py;
+        tile_pixel(r, W, H, &px, &py);
+        const double cam[3] = {(px + 0.5 - 0.5 * W) / f, (py + 0.5 - 0.5 * H) / f, 1.0};
+        double d[3];
+        for (int a = 0; a < 3; ++a) d[a] = pose[4 * a + 0] * cam[0] + pose[4 * a + 1] * cam[1] + pose[4 * a + 2] * cam[2];
+        const double len = sqrt(dot3(d, d));
+        for (int a = 0; a < 3; ++a) {
+            d[a] /= len;
+            origin[3 * r + a] = p[a];
+            dir[3 * r + a] = d[a];
+        }
+        tmax[r] = exit_distance(bound_kind, bound_params, p, d);
+        pixel[r] = py * W + px;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Face planes of the directed Delaunay edges: n = x_j - x_i and            */
+/* c = n.(x_i + x_j)/2, so that the bisector is {p : n.p = c}.              */
+/* ------------------------------------------------------------------------ */
+
+int orc_face_planes(const double *sites, const int32_t *off, const int32_t *idx, int64_t n_sites, double *planes)
+{
+    for (int64_t i = 0; i < n_sites; ++i) {
+        const double *xi = sites + 3 * i;
+        for (int32_t k = off[i]; k < off[i + 1]; ++k) {
+            const double *xj = sites + 3 * (int64_t)idx[k];
+            double n[3], m[3];
+            for (int a = 0; a < 3; ++a) {
+                n[a] = xj[a] - xi[a];
+                m[a] = 0.5 * (xi[a] + xj[a]);
+            }
+            planes[4 * (int64_t)k + 0] = n[0];
+            planes[4 * (int64_t)k + 1] = n[1];
+            planes[4 * (int64_t)k + 2] = n[2];
+            planes[4 * (int64_t)k + 3] = dot3(n, m);
+        }
+    }
+    return ORC_OK;
+}
+
+/* IEEE binary32 -> bfloat16 with round-to-nearest-even (NaN stays NaN). */
+void orc_bf16_round(const float *in, uint16_t *out, int64_t n)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        uint32_t u;
+        memcpy(&u, &in[k], 4);
+        if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) {
+            out[k] = (uint16_t)((u >> 16) | 0x0040u);
+            continue;
+        }
+        const uint32_t lsb = (u >> 16) & 1u;
+        out[k] = (uint16_t)((u + 0x7fffu + lsb) >> 16);
+    }
+}
+
+int orc_check_csr(const int32_t *off, const int32_t *idx, int64_t n_sites, int64_t n_edges)
+{
+    if (n_sites < 1 || off[0] != 0 || off[n_sites] != n_edges) return ORC_EINVAL;
+    for (int64_t i = 0; i < n_sites; ++i) {
+        if (off[i + 1] < off[i]) return ORC_EINVAL;
+        for (int32_t k = off[i]; k < off[i + 1]; ++k)
+            if (idx[k] < 0 || idx[k] >= n_sites || idx[k] == i) return ORC_EINVAL;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The walk (Algorithm 1) in FP64, with optional per-visit records.         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t cell;      /* i_n */
+    int32_t next;      /* i' (or -1 when no front face) */
+    double t0, t1, te; /* entry, nearest front-face distance, clamped exit */
+    double den;        /* (x_next - x_cell) . d of the exit face */
+    double tau;        /* sigma * delta */
+    double T;          /* transmittance before the segment */
+    double c[3];       /* cell colour along d */
+    int moves;         /* the exit is t1 itself (not clamped, not clipped) */
+} visit_t;
+
+typedef struct {
+    visit_t *v;
+    int64_t len, cap;
+} visit_buf;
+
+typedef struct {
+    double margin;   /* min over decisions of the scaled gap to the runner-up face / t_max */
+    double graze;    /* min |cos| over non-front faces other than the entry face */
+    double term;     /* min |ln T - ln eps| over the transmittance tests */
+} margins_t;
+
+static void push_visit(visit_buf *b, const visit_t *v)
+{
+    if (b->len == b->cap) {
+        int64_t cap = b->cap ? 2 * b->cap : 256;
+        visit_t *p = (visit_t *)realloc(b->v, (size_t)cap * sizeof(visit_t));
+        if (!p) abort(); /* the oracle has no graceful path for exhausted host memory */
+        b->v = p;
+        b->cap = cap;
+    }
+    b->v[b->len++] = *v;
+}
+
+/* Walks one ray. Returns the status code written to steps[]. */
+static int32_t walk_ray(const orc_scene *s, const double o[3], const double d[3], double tmax, int32_t start,
+                        double eps, int32_t max_steps, double rgb[3], double *t_final,
+                        visit_buf *rec, margins_t *mg)
+{
+    const int B = sh_count(s->sh_deg);
+    double Y[16];
+    sh_basis(s->sh_deg, d, Y);
+    rgb[0] = rgb[1] = rgb[2] = 0.0;
+    *t_final = 1.0;
+    if (mg) {
+        mg->margin = INFINITY;
+        mg->graze = INFINITY;
+        mg->term = INFINITY;
+    }
+    if (start < 0 || start >= s->n_sites) return ORC_BAD_START;
+
+    double t0 = 0.0, T = 1.0;
+    int32_t i = start, prev = -1, n = 0, status = 0;
+    const double scale0 = 1.0 + sqrt(dot3(o, o));
+    for (;;) {
+        if (mg && eps > 0.0) mg->term = fmin(mg->term, fabs(log(T) - log(eps)));
+        if (!(T > eps)) break;
+        if (n == max_steps) {
+            status = ORC_MAX_STEPS;
+            break;
+        }
+
+        const double *x = s->sites + 3 * (int64_t)i;
+        double t1 = INFINITY, den1 = 0.0, nlen1 = 1.0;
+        int32_t inext = -1;
+        /* nearest front face; runner-ups are kept for the decision margins */
+        double cand_t[512], cand_cos[512];
+        int ncand = 0, win = -1;
+        for (int32_t k = s->off[i]; k < s->off[i + 1]; ++k) {
+            const int32_t j = s->idx[k];
+            if (j == prev) continue;
+            const double *xj = s->sites + 3 * (int64_t)j;
+            double nv[3], mo[3];
+            for (int a = 0; a < 3; ++a) {
+                nv[a] = xj[a] - x[a];
+                mo[a] = 0.5 * (x[a] + xj[a]) - o[a];
+            }
+            const double den = dot3(nv, d);
+            const double nlen = sqrt(dot3(nv, nv));
+            if (!(den > 0.0)) {
+                if (mg) mg->graze = fmin(mg->graze, fabs(den) / nlen);
+                continue;
+            }
+            const double t = dot3(nv, mo) / den;
+            if (mg && ncand < 512) {
+                cand_t[ncand] = t;
+                cand_cos[ncand] = den / nlen;
+                ++ncand;
+            }
+            if (t < t1) {
+                t1 = t;
+                inext = j;
+                den1 = den;
+                nlen1 = nlen;
+                win = ncand - 1;
+            }
+        }
+
+        const double te = fmax(t0, fmin(t1, tmax));
+        const double delta = te - t0;
+        const double sigma = s->density[i];
+        const double tau = (sigma == 0.0) ? 0.0 : sigma * delta;
+        const double alpha = -expm1(-tau);
+        double c[3] = {0.0, 0.0, 0.0};
+        for (int b = 0; b < B; ++b)
+            for (int ch = 0; ch < 3; ++ch) c[ch] += s->sh[(3 * (int64_t)B) * i + 3 * b + ch] * Y[b];
+        for (int ch = 0; ch < 3; ++ch) rgb[ch] += T * alpha * c[ch];
+
+        const int clipped = (inext < 0) || (t1 >= tmax);
+        if (mg && inext >= 0) {
+            const double scale = scale0 + fabs(t1);
+            const double cos1 = den1 / nlen1;
+            for (int q = 0; q < ncand; ++q) {
+                if (q == win) continue;
+                const double m = (cand_t[q] - t1) / (scale * (1.0 / cos1 + 1.0 / cand_cos[q]));
+                mg->margin = fmin(mg->margin, m);
+            }
+            mg->margin = fmin(mg->margin, fabs(t1 - tmax) * cos1 / scale);
+        }
+        if (rec) {
+            visit_t v;
+            v.cell = i;
+            v.next = inext;
+            v.t0 = t0;
+            v.t1 = t1;
+            v.te = te;
+            v.den = den1;
+            v.tau = tau;
+            v.T = T;
+            v.c[0] = c[0];
+            v.c[1] = c[1];
+            v.c[2] = c[2];
+            v.moves = (!clipped) && (t1 >= t0);
+            push_visit(rec, &v);
+        }
+        T *= exp(-tau);
+        ++n;
+        if (clipped) break;
+        prev = i;
+        i = inext;
+        t0 = te;
+    }
+    *t_final = T;
+    return status ? status : n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Analytic gradient of one ray (from its stored visits).                   */
+/*   w_n = T_n alpha_n, R_n = sum_{k>n} w_k c_k                             */
+/*   dL/dtau_n = g.(T_{n+1} c_n - R_n) - gT T_final                          */
+/*   dL/dsigma_{i_n} += delta_n dL/dtau_n                                   */
+/*   dL/dK_{i_n,b,ch} += g_ch w_n Y_b                                       */
+/*   for an exit that moves with t1:                                        */
+/*     dL/dt_n = sigma_n dL/dtau_n - sigma_{n+1} dL/dtau_{n+1}              */
+/*     dt/dx_{i_n} = (p - x_{i_n})/den, dt/dx_{i_{n+1}} = (x_{i_{n+1}} - p)/den */
+/*     with p = o + t_n d and den = (x_{i_{n+1}} - x_{i_n}).d               */
+/* ------------------------------------------------------------------------ */
+
+static void ray_gradient(const orc_scene *s, const double o[3], const double d[3], const visit_t *v, int64_t nv,
+                         double T_final, const double g[3], double gT, double *gsites, double *gdens, double *gsh)
+{
+    const int B = sh_count(s->sh_deg);
+    double Y[16];
+    sh_basis(s->sh_deg, d, Y);
+    double *R = (double *)malloc((size_t)(nv > 0 ? nv : 1) * 3 * sizeof(double));
+    double *dtau = (double *)malloc((size_t)(nv > 0 ? nv : 1) * sizeof(double));
+    if (!R || !dtau) {
+        free(R);
+        free(dtau);
+        return;
+    }
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t n = nv - 1; n >= 0; --n) {
+        const double w = v[n].T * (-expm1(-v[n].tau));
+        for (int ch = 0; ch < 3; ++ch) {
+            R[3 * n + ch] = acc[ch];
+            acc[ch] += w * v[n].c[ch];
+        }
+    }
+    for (int64_t n = 0; n < nv; ++n) {
+        const double Tn1 = v[n].T * exp(-v[n].tau);
+        double s_ = 0.0;
+        for (int ch = 0; ch < 3; ++ch) s_ += g[ch] * (Tn1 * v[n].c[ch] - R[3 * n + ch]);
+        dtau[n] = s_ - gT * T_final;
+        const int32_t i = v[n].cell;
+        const double w = v[n].T * (-expm1(-v[n].tau));
+        gdens[i] += (v[n].te - v[n].t0) * dtau[n];
+        for (int b = 0; b < B; ++b)
+            for (int ch = 0; ch < 3; ++ch) gsh[(3 * (int64_t)B) * i + 3 * b + ch] += g[ch] * w * Y[b];
+    }
+    for (int64_t n = 0; n < nv; ++n) {
+        if (!v[n].moves) continue;
+        const int32_t i = v[n].cell, j = v[n].next;
+        double gt = s->density[i] * dtau[n];
+        if (n + 1 < nv) gt -= s->density[v[n + 1].cell] * dtau[n + 1];
+        const double *xi = s->sites + 3 * (int64_t)i;
+        const double *xj = s->sites + 3 * (int64_t)j;
+        for (int a = 0; a < 3; ++a) {
+            const double p = o[a] + v[n].t1 * d[a];
+            gsites[3 * (int64_t)i + a] += gt * (p - xi[a]) / v[n].den;
+            gsites[3 * (int64_t)j + a] += gt * (xj[a] - p) / v[n].den;
+        }
+    }
+    free(R);
+    free(dtau);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Threaded drivers.                                                        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    const orc_scene *s;
+    const double *o, *d, *tmax;
+    const int32_t *start;
+    int64_t r0, r1;
+    double eps;
+    int32_t max_steps;
+    /* forward */
+    double *rgb, *t_final;
+    int32_t *steps;
+    /* trace */
+    int32_t max_len;
+    int32_t *cells;
+    double *t_exit;
+    int32_t *len;
+    double *margin, *graze, *term;
+    /* backward */
+    const double *grad_rgb, *grad_t;
+    double *gsites, *gdens, *gsh;
+    int status;
+} job_t;
+
+static int check_inputs(const orc_scene *s, const double *d, int64_t n_rays)
+{
+    if (!s || s->n_sites < 1 || s->sh_deg < 0 || s->sh_deg > 3 || n_rays < 0) return ORC_EINVAL;
+    if (orc_check_csr(s->off, s->idx, s->n_sites, s->off[s->n_sites]) != ORC_OK) return ORC_EINVAL;
+    for (int64_t i = 0; i < s->n_sites; ++i)
+        if (s->off[i + 1] - s->off[i] > 512) return ORC_EINVAL; /* decision-margin buffer */
+    for (int64_t r = 0; r < n_rays; ++r)
+        if (fabs(sqrt(dot3(d + 3 * r, d + 3 * r)) - 1.0) > 1e-5) return ORC_EINVAL;
+    for (int64_t i = 0; i < s->n_sites; ++i)
+        if (!(s->density[i] >= 0.0)) return ORC_EINVAL;
+    return ORC_OK;
+}
+
+static void *forward_worker(void *arg)
+{
+    job_t *j = (job_t *)arg;
+    visit_buf buf = {0, 0, 0};
+    for (int64_t r = j->r0; r < j->r1; ++r) {
+        margins_t mg;
+        const int tracing = j->cells != NULL;
+        buf.len = 0;
+        j->steps[r] = walk_ray(j->s, j->o + 3 * r, j->d + 3 * r, j->tmax[r], j->start[r], j->eps, j->max_steps,
+                               j->rgb + 3 * r, j->t_final + r, tracing ? &buf : NULL, tracing ? &mg : NULL);
+        if (tracing) {
+            const int64_t L = buf.len < j->max_len ? buf.len : j->max_len;
+            for (int64_t n = 0; n < L; ++n) {
+                j->cells[r * j->max_len + n] = buf.v[n].cell;
+                j->t_exit[r * j->max_len + n] = buf.v[n].te;
+            }
+            j->len[r] = (int32_t)buf.len;
+            j->margin[r] = mg.margin;
+            j->graze[r] = mg.graze;
+            j->term[r] = mg.term;
+        }
+    }
+    free(buf.v);
+    return NULL;
+}
+
+static void *backward_worker(void *arg)
+{
+    job_t *j = (job_t *)arg;
+    visit_buf buf = {0, 0, 0};
+    for (int64_t r = j->r0; r < j->r1; ++r) {
+        double rgb[3], tf;
+        buf.len = 0;
+        const int32_t st = walk_ray(j->s, j->o + 3 * r, j->d + 3 * r, j->tmax[r], j->start[r], j->eps, j->max_steps,
+                                    rgb, &tf, &buf, NULL);
+        if (st == ORC_BAD_START) continue;
+        const double gT = j->grad_t ? j->grad_t[r] : 0.0;
+        ray_gradient(j->s, j->o + 3 * r, j->d + 3 * r, buf.v, buf.len, tf, j->grad_rgb + 3 * r, gT, j->gsites,
+                     j->gdens, j->gsh);
+    }
+    free(buf.v);
+    return NULL;
+}
+
+static int run_jobs(job_t *proto, int64_t n_rays, int nthreads, void *(*fn)(void *), int with_grad_buffers)
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if (n_rays < nthreads) nthreads = n_rays > 0 ? (int)n_rays : 1;
+    job_t jobs[256];
+    pthread_t th[256];
+    const int64_t N = proto->s->n_sites;
+    const int64_t B = sh_count(proto->s->sh_deg);
+    const int64_t per = 3 * N + N + 3 * B * N;
+    double *grad_mem = NULL;
+    if (with_grad_buffers && nthreads > 1) {
+        grad_mem = (double *)calloc((size_t)(nthreads - 1) * (size_t)per, sizeof(double));
+        if (!grad_mem) return ORC_ENOMEM;
+    }
+    /* contiguous chunks of screen tiles: chunk boundaries are multiples of 64 rays */
+    int64_t chunk = (n_rays + nthreads - 1) / nthreads;
+    chunk = (chunk + 63) / 64 * 64;
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = *proto;
+        jobs[t].r0 = t * chunk < n_rays ? t * chunk : n_rays;
+        jobs[t].r1 = (t + 1) * chunk < n_rays ? (t + 1) * chunk : n_rays;
+        if (grad_mem && t > 0) {
+            double *base = grad_mem + (int64_t)(t - 1) * per;
+            jobs[t].gsites = base;
+            jobs[t].gdens = base + 3 * N;
+            jobs[t].gsh = base + 4 * N;
+        }
+        pthread_create(&th[t], NULL, fn, &jobs[t]);
+    }
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    if (grad_mem) {
+        for (int t = 1; t < nthreads; ++t) {
+            const double *base = grad_mem + (int64_t)(t - 1) * per;
+            for (int64_t k = 0; k < 3 * N; ++k) proto->gsites[k] += base[k];
+            for (int64_t k = 0; k < N; ++k) proto->gdens[k] += base[3 * N + k];
+            for (int64_t k = 0; k < 3 * B * N; ++k) proto->gsh[k] += base[4 * N + k];
+        }
+        free(grad_mem);
+    }
+    return ORC_OK;
+}
+
+int orc_forward(const orc_scene *s, const double *o, const double *d, const double *tmax, const int32_t *start,
+                int64_t n_rays, double eps, int32_t max_steps, int nthreads, double *rgb, double *t_final,
+                int32_t *steps)
+{
+    if (check_inputs(s, d, n_rays) != ORC_OK || max_steps < 1) return ORC_EINVAL;
+    job_t j;
+    memset(&j, 0, sizeof j);
+    j.s = s;
+    j.o = o;
+    j.d = d;
+    j.tmax = tmax;
+    j.start = start;
+    j.eps = eps;
+    j.max_steps = max_steps;
+    j.rgb = rgb;
+    j.t_final = t_final;
+    j.steps = steps;
+    return run_jobs(&j, n_rays, nthreads, forward_worker, 0);
+}
+
+int orc_trace(const orc_scene *s, const double *o, const double *d, const double *tmax, const int32_t *start,
+              int64_t n_rays, double eps, int32_t max_steps, int32_t max_len, int nthreads, double *rgb,
+              double *t_final, int32_t *steps, int32_t *cells, double *t_exit, int32_t *len, double *margin,
+              double *graze, double *term)
+{
+    if (check_inputs(s, d, n_rays) != ORC_OK || max_steps < 1 || max_len < 1) return ORC_EINVAL;
+    job_t j;
+    memset(&j, 0, sizeof j);
+    j.s = s;
+    j.o = o;
+    j.d = d;
+    j.tmax = tmax;
+    j.start = start;
+    j.eps = eps;
+    j.max_steps = max_steps;
+    j.rgb = rgb;
+    j.t_final = t_final;
+    j.steps = steps;
+    j.max_len = max_len;
+    j.cells = cells;
+    j.t_exit = t_exit;
+    j.len = len;
+    j.margin = margin;
+    j.graze = graze;
+    j.term = term;
+    return run_jobs(&j, n_rays, nthreads, forward_worker, 0);
+}
+
+/* Gradients are accumulated (+=) into the caller's buffers. */
+int orc_backward(const orc_scene *s, const double *o, const double *d, const double *tmax, const int32_t *start,
+                 int64_t n_rays, double eps, int32_t max_steps, const double *grad_rgb, const double *grad_t,
+                 int nthreads, double *grad_sites, double *grad_density, double *grad_sh)
+{
+    if (check_inputs(s, d, n_rays) != ORC_OK || max_steps < 1) return ORC_EINVAL;
+    job_t j;
+    memset(&j, 0, sizeof j);
+    j.s = s;
+    j.o = o;
+    j.d = d;
+    j.tmax = tmax;
+    j.start = start;
+    j.eps = eps;
+    j.max_steps = max_steps;
+    j.grad_rgb = grad_rgb;
+    j.grad_t = grad_t;
+    j.gsites = grad_sites;
+    j.gdens = grad_density;
+    j.gsh = grad_sh;
+    return run_jobs(&j, n_rays, nthreads, backward_worker, 1);
+}
