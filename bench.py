@@ -1,0 +1,259 @@
+"""Benchmark of the Voronoi ray walk on one MI355X.
+
+Workload (default): 1M sites from 64 thin anisotropic Gaussian clusters plus
+10 % uniform background in [-1,1]^3, SH degree 3, one 1920x1080 camera on an
+orbit of radius 0.8, forward + backward with per-pixel N(0,1) upstream
+gradients. One step is the whole hot path on one batch:
+camera rays (8x8 tiles) -> scene pack (face planes + cell records) ->
+forward walk -> backward walk (gradients for sites, density, SH).
+
+Prints ONE JSON line. `value` is forward+backward Mrays/s with FP32 attributes;
+forward-only and BF16-attribute rates, per-kernel times, step-latency
+percentiles, the roofline of the dominant kernel and the FP64 CPU oracle's
+rate on a bounded sample of the same workload are added fields.
+
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--config cfg3]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FP32 vector peak without packed math: 256 CUs x 64 FMA lanes x 2 flops x 2.4 GHz.
+VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def flops_per_visit(mean_deg: float, B: int, backward: bool) -> float:
+    """Arithmetic the walk itself requires per visited cell (FMA = 2 flops).
+
+    Per face: den = n.d (5), num = c - n.o (6), nearest-face compare (2).
+    Per cell: colour sum_b k_b Y_b (2 per coefficient, 3B coefficients) and
+    the compositing update (12). The backward adds the transmittance
+    derivative (14), the per-cell SH/density gradient (2 x 3B + 2) and the
+    two site gradients of the exit face (20).
+    """
+    f = 13.0 * mean_deg + 6.0 * B + 12.0
+    if backward:
+        f += 14.0 + 6.0 * B + 2.0 + 20.0
+    return f
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="cfg3", choices=["cfg1", "cfg2", "cfg3", "cfg4"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", type=int, default=0, help="backward reduction mode (0 wave-reduced, 1 per-lane)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: the walk is measured on one GPU's share "
+              "(multi-GPU sharding is described in the design notes, not run)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2502_01157_amd as rf
+    import synth
+    from synth.scenes import CONFIGS
+
+    cfg = CONFIGS[args.config]
+    t0 = time.time()
+    scene, rng = synth.make_scene(args.config, return_rng=True)
+    cams = synth.make_cameras(args.config, rng)
+    cam = cams[0]
+    R = cam.width * cam.height
+    g_np = synth.make_upstream_grads(rng, R)
+    start = int(synth.nearest_site(scene.sites, cam.position[None, :])[0])
+    log(f"scene {args.config}: {scene.n_sites} sites, {scene.n_edges} directed edges, "
+        f"{cam.width}x{cam.height} rays, built in {time.time() - t0:.1f}s")
+
+    dev = torch.device("cuda:0")
+
+    def dv(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    sites, off, idx, dens, sh = map(dv, (scene.sites, scene.off, scene.idx, scene.density, scene.sh))
+    grad_rgb = dv(g_np)
+    B = (scene.sh_deg + 1) ** 2
+    pose, fov, W, H = cam.pose12(), cam.fov_deg, cam.width, cam.height
+    bound = cfg["bound"]
+
+    scenes = {dt: rf.PackedScene(sites, off, idx, dens, sh, scene.sh_deg, dt, validate=True)
+              for dt in ("f32", "bf16")}
+    grads = (torch.zeros((scene.n_sites, 3), device=dev), torch.zeros(scene.n_sites, device=dev),
+             torch.zeros((scene.n_sites, B, 3), device=dev))
+    rays = rf.raygen(pose, fov, W, H, bound, start, device=dev, with_pixel=False)[:4]
+    fwd_out = (torch.empty((R, 3), device=dev), torch.empty(R, device=dev),
+               torch.empty(R, dtype=torch.int32, device=dev))
+    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for k in ("raygen", "pack", "forward", "backward")}
+
+    def step(dt: str, backward: bool, timed: dict = None):
+        def mark(k, i):
+            if timed is not None:
+                ev[k][i].record()
+
+        mark("raygen", 0)
+        o, d, t, s, _ = rf.raygen(pose, fov, W, H, bound, start, device=dev, with_pixel=False)
+        mark("raygen", 1)
+        mark("pack", 0)
+        scenes[dt].pack(sites, dens, sh)
+        mark("pack", 1)
+        mark("forward", 0)
+        rgb, tf, steps = rf.render_forward(scenes[dt], o, d, t, s, out=fwd_out)
+        mark("forward", 1)
+        if backward:
+            for gbuf in grads:
+                gbuf.zero_()
+            mark("backward", 0)
+            rf.render_backward(scenes[dt], o, d, t, s, rgb, tf, grad_rgb, None, mode=args.mode, grads=grads)
+            mark("backward", 1)
+        if timed is not None:
+            torch.cuda.synchronize()
+            for k in ev:
+                if k == "backward" and not backward:
+                    continue
+                timed.setdefault(k, []).append(ev[k][0].elapsed_time(ev[k][1]))
+
+    def run(dt: str, backward: bool):
+        for _ in range(args.warmup):
+            step(dt, backward)
+        torch.cuda.synchronize()
+        # whole-job throughput: K steps bracketed by synchronisation
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            step(dt, backward)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t_start
+        # per-kernel and per-step latency: the same steps again with events
+        timed, lat = {}, []
+        for _ in range(args.steps):
+            a = time.perf_counter()
+            step(dt, backward, timed)
+            lat.append((time.perf_counter() - a) * 1e3)
+        return total / args.steps * 1e3, {k: float(np.mean(v)) for k, v in timed.items()}, lat
+
+    # visits per frame (the work unit of the walk)
+    o, d, t, s = rays
+    _, _, steps_fp32 = rf.render_forward(scenes["f32"], o, d, t, s)
+    torch.cuda.synchronize()
+    steps_np = steps_fp32.cpu().numpy()
+    visits = int(np.clip(steps_np, 0, None).sum())
+    # mean degree of visited cells, from a traced sample of tiles
+    sample = slice(R // 2 - 8192, R // 2 + 8192)
+    tr = rf.render_trace(scenes["f32"], o[sample].contiguous(), d[sample].contiguous(), t[sample].contiguous(),
+                         s[sample].contiguous(), max_len=1024)
+    cells = tr["cells"].cpu().numpy()
+    cells = cells[cells >= 0]
+    deg = np.diff(scene.off)
+    mean_deg = float(deg[cells].mean())
+    log(f"visits/frame {visits} ({visits / R:.1f} per ray), mean visited degree {mean_deg:.2f}, "
+        f"flagged rays {(steps_np < 0).sum()}")
+
+    results = {}
+    for dt in ("f32", "bf16"):
+        for bwd in (True, False):
+            ms, kern, lat = run(dt, bwd)
+            results[(dt, bwd)] = (ms, kern, lat)
+            log(f"{dt} {'fwd+bwd' if bwd else 'fwd'}: {ms:.3f} ms/step, {R / ms / 1e3:.1f} Mrays/s, "
+                f"kernels(ms) {json.dumps({k: round(v, 4) for k, v in kern.items()})}")
+
+    ms, kern, lat = results[("f32", True)]
+    value = R / (ms * 1e-3) / 1e6
+    dominant = max(("forward", "backward"), key=lambda k: kern[k])
+    fl = flops_per_visit(mean_deg, B, dominant == "backward") * visits
+    achieved = fl / (kern[dominant] * 1e-3) / 1e12
+
+    out = {
+        "metric": "Mrays/s fwd+bwd at 1M sites (FP32 attributes); fwd and BF16 rates and p50/p99 step latency "
+                  "in added fields",
+        "value": round(value, 3),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded clustered Voronoi scene, Delaunay CSR from Qhull)",
+        "config": {"workload": f"{args.config}: {scene.n_sites} sites clustered, SH deg {scene.sh_deg}, "
+                               f"{W}x{H} camera, raygen+pack+forward+backward",
+                   "rays_per_step": R, "visits_per_step": visits, "mean_visited_degree": round(mean_deg, 3),
+                   "parallelism": "single GPU"},
+        "fwd_mrays_s": {dt: round(R / results[(dt, False)][0] / 1e3, 3) for dt in ("f32", "bf16")},
+        "fwd_bwd_mrays_s": {dt: round(R / results[(dt, True)][0] / 1e3, 3) for dt in ("f32", "bf16")},
+        "bf16_speedup_fwd_bwd": round(results[("f32", True)][0] / results[("bf16", True)][0], 4),
+        "step_latency_ms": {f"{dt}_{'fwd_bwd' if b else 'fwd'}": {
+            "p50": round(float(np.percentile(results[(dt, b)][2], 50)), 4),
+            "p99": round(float(np.percentile(results[(dt, b)][2], 99)), 4)} for dt in ("f32", "bf16")
+            for b in (True, False)},
+        "kernel_ms": {f"{dt}_{'fwd_bwd' if b else 'fwd'}": {k: round(v, 4) for k, v in results[(dt, b)][1].items()}
+                      for dt in ("f32", "bf16") for b in (True, False)},
+        "roofline": {"bound": "alu", "kernel": f"{dominant} walk (fp32 attributes)",
+                     "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s",
+                     "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None},
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(scene, cam, bound, start, g_np, visits / R, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def cpu_baseline(scene, cam, bound, start, g_np, visits_per_ray, target_s):
+    """The FP64 oracle on a bounded contiguous band of screen tiles of the same frame."""
+    import oracle
+
+    threads = oracle.default_threads()
+    osc = oracle.OracleScene.from_scene(scene)
+    o, d, t, _ = oracle.raygen(cam.pose12(), cam.fov_deg, cam.width, cam.height, bound)
+    R = len(t)
+    # calibrate the forward on 16384 rays, then size the sample so that forward
+    # plus backward (about three forward walks) take ~target_s
+    mid = R // 4
+    n0 = 16384
+    sl = slice(mid, mid + n0)
+    a = time.perf_counter()
+    oracle.forward(osc, o[sl], d[sl], t[sl], start, threads=threads)
+    per_ray = (time.perf_counter() - a) / n0
+    n = int(min(R - mid, max(n0, target_s / 3.0 / max(per_ray, 1e-9))))
+    n = n // 64 * 64
+    sl = slice(mid, mid + n)
+    a = time.perf_counter()
+    oracle.forward(osc, o[sl].astype(np.float32), d[sl].astype(np.float32), t[sl].astype(np.float32), start,
+                   threads=threads)
+    tf = time.perf_counter() - a
+    a = time.perf_counter()
+    oracle.backward(osc, o[sl].astype(np.float32), d[sl].astype(np.float32), t[sl].astype(np.float32),
+                    np.full(n, start, dtype=np.int32), g_np[sl], threads=threads)
+    tb = time.perf_counter() - a
+    log(f"oracle on {n} rays with {threads} threads: fwd {tf:.2f}s, bwd (recomputes the walk) {tb:.2f}s")
+    return {"value": round(n / (tf + tb) / 1e6, 5), "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} rays ({n // 64} consecutive 8x8 tiles starting a quarter into the same frame), "
+                      f"forward then backward, FP64 C oracle",
+            "fwd_mrays_s": round(n / tf / 1e6, 5)}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,244 @@
+/*
+ * radfoam.h - C ABI of the MI355X (gfx950) Voronoi ray-walk library (librf.so).
+ *
+ * The library renders and differentiates the Radiant Foam scene model
+ * (Govindarajan, Rebain, Yi, Tagliasacchi, "Radiant Foam: Real-Time
+ * Differentiable Ray Tracing", CVPR 2025):
+ *   - the scene is a set of Voronoi sites x_i (Sec. 3.2, eq. (5)) with a
+ *     per-cell density sigma_i and view-dependent colour given by real
+ *     spherical harmonics of degree <= 3 (Sec. 3.4);
+ *   - the Delaunay neighbours N(i) of every site are an input (a CSR list
+ *     built on the host); the library never triangulates;
+ *   - a ray starts in a given cell (Algorithm 1 starts in nn(o); the caller
+ *     supplies that cell), repeatedly leaves the current cell through the
+ *     nearest front-facing bisector plane (Algorithm 1, Fig. 2), and
+ *     alpha-composites each segment with eq. (3)-(4) while the
+ *     transmittance exceeds eps;
+ *   - the backward pass returns gradients for densities, SH coefficients and
+ *     site positions, geometry entering only through segment widths
+ *     (Sec. 3.1, "Piecewise constant volumes").
+ *
+ * Conventions for every call:
+ *   - All array pointers are DEVICE pointers (hipMalloc or torch CUDA
+ *     memory) owned by the caller unless stated otherwise; the library keeps
+ *     no reference to them after the call returns. Struct arguments
+ *     themselves live in host memory.
+ *   - Float arrays are IEEE binary32, row-major, densely packed.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL is the
+ *     default stream) unless stated otherwise.
+ *   - Every call returns an rf_status and never aborts or throws. On an
+ *     error nothing is launched and rf_last_error() describes it.
+ *   - Per-ray anomalies are not call errors: they are reported in the
+ *     per-ray `steps` output (RF_RAY_*).
+ *   - Calls on different streams may run concurrently; the library holds no
+ *     global mutable state besides the thread-local error string.
+ */
+#ifndef RADFOAM_H
+#define RADFOAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RF_OK = 0,
+    RF_ERR_INVALID_ARG = 1,  /* bad pointer, size, layout or CSR contents */
+    RF_ERR_HIP = 2,          /* a HIP runtime call failed; see rf_last_error() */
+    RF_ERR_OOM = 3,          /* device or host allocation failed */
+    RF_ERR_UNSUPPORTED = 4,  /* valid but outside this build's limits */
+    RF_ERR_BUSY = 5          /* serving: request not admissible right now */
+} rf_status;
+
+typedef enum { RF_F32 = 0, RF_BF16 = 1 } rf_dtype;
+
+/* Per-ray values of `steps` (>= 0 is the number of visited cells). */
+#define RF_RAY_BAD_START (-1) /* start cell outside [0, n_sites): rgb = 0, T = 1 */
+#define RF_RAY_MAX_STEPS (-2) /* max_steps cells visited with T > eps before t_max */
+
+/* Limits of this build. */
+#define RF_MAX_SITES ((int64_t)1 << 24) /* cell ids fit 24 bits */
+#define RF_MAX_DEGREE 255               /* Delaunay neighbours per site */
+#define RF_MAX_SH_DEGREE 3
+
+/* Thread-local description of the last error on this host thread ("" if none). */
+const char *rf_last_error(void);
+
+/* Library version string. */
+const char *rf_version(void);
+
+/* ------------------------------------------------------------------------
+ * Scene (Sec. 3.2 "The Voronoi diagram", Sec. 3.4 "Training").
+ *
+ *   sites    float[n_sites][3]        Voronoi sites x_i.
+ *   nbr_off  int32[n_sites + 1]       CSR row offsets: the neighbours of i are
+ *   nbr_idx  int32[n_edges]           nbr_idx[nbr_off[i] .. nbr_off[i+1]-1].
+ *                                     Rows must list the Delaunay neighbours
+ *                                     of i (a superset is harmless, a missing
+ *                                     neighbour is not); nbr_off[0] = 0,
+ *                                     nbr_off[n_sites] = n_edges; no self loop.
+ *                                     Ties between equal exit distances go to
+ *                                     the first neighbour in row order.
+ *   density  float[n_sites]           sigma_i >= 0 (already activated; the
+ *                                     paper's softplus stays outside).
+ *   sh       float[n_sites][B][3]     SH coefficients, B = (sh_degree+1)^2,
+ *                                     basis l-major, m = -l..l, RGB innermost.
+ *                                     Colour = sum_b sh[i][b][:] * Y_b(d), the
+ *                                     real orthonormal SH basis, no offset and
+ *                                     no clamp.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    const float *sites;
+    const int32_t *nbr_off;
+    const int32_t *nbr_idx;
+    const float *density;
+    const float *sh;
+    int64_t n_sites;
+    int64_t n_edges;
+    int32_t sh_degree; /* 0..3 */
+} rf_scene;
+
+/* ------------------------------------------------------------------------
+ * Packed scene: device-resident records that the walk reads.
+ *
+ * rf_packed_bytes() gives the size of the device workspace for a scene;
+ * rf_pack_scene() fills it from an rf_scene and fills the host descriptor
+ * `out`. The workspace holds, per directed Delaunay edge (i -> j), the
+ * bisector plane (n = x_j - x_i, c = n.(x_i + x_j)/2) and the neighbour's
+ * row, and per cell one record with its SH coefficients and density (in
+ * `attr_dtype`, bf16 by round-to-nearest-even) and its site. The layout is
+ * private to the library. The caller owns the workspace, must keep it alive
+ * and unmodified while any call that uses `out` runs, and must pack again
+ * after changing the scene. Repacking into the same workspace is allowed.
+ *
+ * CSR contents are validated on the device: invalid entries are neutralised
+ * (they can never be crossed) and counted. With validate != 0 the call
+ * synchronises `stream` and returns RF_ERR_INVALID_ARG if any entry was
+ * invalid (RF_ERR_UNSUPPORTED if a row exceeds RF_MAX_DEGREE); with
+ * validate == 0 it stays asynchronous and rf_packed_errors() can be polled.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    void *base;          /* device workspace (owned by the caller) */
+    size_t bytes;
+    int64_t n_sites;
+    int64_t n_edges;
+    int32_t sh_degree;
+    rf_dtype attr_dtype;
+    /* private section offsets (bytes from base) */
+    size_t off_planes, off_adj, off_rec, off_row, off_err;
+    int32_t rec_bytes;
+    int32_t reserved;
+} rf_packed_scene;
+
+rf_status rf_packed_bytes(int64_t n_sites, int64_t n_edges, int32_t sh_degree, rf_dtype attr_dtype,
+                          size_t *bytes);
+
+rf_status rf_pack_scene(const rf_scene *scene, rf_dtype attr_dtype, void *workspace, size_t workspace_bytes,
+                        int validate, rf_packed_scene *out, void *stream);
+
+/* Synchronously reads the validation counters written by the last pack:
+ * errors[0] = invalid CSR entries, errors[1] = rows longer than RF_MAX_DEGREE. */
+rf_status rf_packed_errors(const rf_packed_scene *packed, int32_t errors[2], void *stream);
+
+/* ------------------------------------------------------------------------
+ * Rays (Algorithm 1 "Render(o, d)").
+ *
+ *   origin     float[n_rays][3]   o
+ *   dir        float[n_rays][3]   d, unit length (not renormalised)
+ *   t_max      float[n_rays]      finite end of the ray, >= 0 (the segment
+ *                                 reaching it is clipped, eq. (1)'s t_max)
+ *   start_cell int32[n_rays]      the cell containing o (nn(o))
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    const float *origin;
+    const float *dir;
+    const float *t_max;
+    const int32_t *start_cell;
+    int64_t n_rays;
+} rf_rays;
+
+typedef struct {
+    float eps;         /* transmittance threshold of Algorithm 1 (default 1e-4); T > eps is tested
+                          before each cell */
+    int32_t max_steps; /* cap on visited cells per ray (default 8192) */
+} rf_params;
+
+/* ------------------------------------------------------------------------
+ * Camera rays (pinhole), in 8x8 screen-tile order: tiles row-major over the
+ * image, pixels row-major inside a tile, partial edge tiles holding only the
+ * pixels inside the image. Ray r covers pixel pixel[r] = y*width + x; its
+ * direction is R (x + 0.5 - width/2, y + 0.5 - height/2, f) normalised, with
+ * f = (width/2)/tan(fov/2) and R the rotation in pose (columns right, down,
+ * forward). t_max is the distance at which the ray leaves the bound (the
+ * origin must be inside it). start_cell is filled with `start` (the caller's
+ * nn(origin) for the camera position).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    float pose[12];   /* row-major 3x4 [R | position] */
+    float fov_deg;    /* horizontal field of view, (0, 180) */
+    int32_t width, height;
+} rf_camera;
+
+typedef struct {
+    int32_t kind;     /* 0: box [p0,p1,p2] .. [p3,p4,p5]; 1: sphere about the origin, radius p0 */
+    float p[6];
+} rf_bound;
+
+rf_status rf_raygen(const rf_camera *camera, const rf_bound *bound, int32_t start, float *origin, float *dir,
+                    float *t_max, int32_t *start_cell, int32_t *pixel /* nullable */, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Forward walk (Algorithm 1 with eq. (3)-(4)).
+ *   rgb      float[n_rays][3]  composited colour C (no background)
+ *   t_final  float[n_rays]     final transmittance T
+ *   steps    int32[n_rays]     visited cells, or RF_RAY_* (< 0)
+ * Deterministic: the same inputs give bitwise the same outputs.
+ * ---------------------------------------------------------------------- */
+rf_status rf_render_forward(const rf_packed_scene *scene, const rf_rays *rays, const rf_params *params,
+                            float *rgb, float *t_final, int32_t *steps, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Backward walk: gradients of L = sum_r grad_rgb[r].rgb[r] + grad_t_final[r] T[r]
+ * (Sec. 3.1: geometry receives gradients only through the segment widths).
+ * The walk is recomputed from the inputs; rgb and t_final must be the
+ * outputs of rf_render_forward for the same scene, rays and params.
+ *   grad_rgb      float[n_rays][3]
+ *   grad_t_final  float[n_rays]        nullable (treated as 0)
+ *   grad_sites    float[n_sites][3]    ACCUMULATED (+=); caller zeroes
+ *   grad_density  float[n_sites]       ACCUMULATED (+=)
+ *   grad_sh       float[n_sites][B][3] ACCUMULATED (+=)
+ * Per-site sums use float atomics: results are deterministic only up to
+ * the order of additions.
+ * `mode` selects the gradient reduction: 0 = reduce across the wavefront
+ * per cell before the atomics (default), 1 = one atomic per lane and value.
+ * ---------------------------------------------------------------------- */
+rf_status rf_render_backward(const rf_packed_scene *scene, const rf_rays *rays, const rf_params *params,
+                             const float *rgb, const float *t_final, const float *grad_rgb,
+                             const float *grad_t_final, float *grad_sites, float *grad_density, float *grad_sh,
+                             int32_t mode, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Traced forward walk, for tests: the forward outputs plus, per ray, the
+ * visited cells and each segment's clamped exit distance.
+ *   cells   int32[n_rays][max_len]  (entries past the visit count untouched)
+ *   t_exit  float[n_rays][max_len]
+ * ---------------------------------------------------------------------- */
+rf_status rf_render_trace(const rf_packed_scene *scene, const rf_rays *rays, const rf_params *params,
+                          int32_t max_len, float *rgb, float *t_final, int32_t *steps, int32_t *cells,
+                          float *t_exit, void *stream);
+
+/* Copies the packed face planes (float4 per directed edge, CSR order) into
+ * planes[n_edges][4]; for tests of the packing step. */
+rf_status rf_packed_planes(const rf_packed_scene *scene, float *planes, void *stream);
+
+/* Copies the packed density and SH back as float (bf16 widened exactly):
+ * density[n_sites], sh[n_sites][B][3]; for tests of the packing step. */
+rf_status rf_packed_attributes(const rf_packed_scene *scene, float *density, float *sh, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RADFOAM_H */

@@ -1,0 +1,130 @@
+"""ctypes binding of librf.so (include/radfoam.h): argument marshalling only.
+
+Every step of the walk runs in the HIP library. This module converts torch
+CUDA tensors to device pointers, passes torch's current HIP stream, and turns
+non-zero status codes into exceptions. There is no CPU fallback: if the
+library is missing, importing the package fails.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librf.so")
+
+RF_OK = 0
+RF_F32 = 0
+RF_BF16 = 1
+RF_RAY_BAD_START = -1
+RF_RAY_MAX_STEPS = -2
+STATUS_NAMES = {0: "RF_OK", 1: "RF_ERR_INVALID_ARG", 2: "RF_ERR_HIP", 3: "RF_ERR_OOM",
+                4: "RF_ERR_UNSUPPORTED", 5: "RF_ERR_BUSY"}
+
+#: every entry point declared in include/radfoam.h
+EXPORTED = ["rf_last_error", "rf_version", "rf_packed_bytes", "rf_pack_scene", "rf_packed_errors", "rf_raygen",
+            "rf_render_forward", "rf_render_backward", "rf_render_trace", "rf_packed_planes",
+            "rf_packed_attributes", "rf_server_create", "rf_server_submit", "rf_server_poll",
+            "rf_server_result", "rf_server_stats", "rf_server_destroy"]
+
+
+class RfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Scene(ctypes.Structure):
+    _fields_ = [("sites", ctypes.c_void_p), ("nbr_off", ctypes.c_void_p), ("nbr_idx", ctypes.c_void_p),
+                ("density", ctypes.c_void_p), ("sh", ctypes.c_void_p), ("n_sites", ctypes.c_int64),
+                ("n_edges", ctypes.c_int64), ("sh_degree", ctypes.c_int32)]
+
+
+class PackedSceneDesc(ctypes.Structure):
+    _fields_ = [("base", ctypes.c_void_p), ("bytes", ctypes.c_size_t), ("n_sites", ctypes.c_int64),
+                ("n_edges", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("attr_dtype", ctypes.c_int32),
+                ("off_planes", ctypes.c_size_t), ("off_adj", ctypes.c_size_t), ("off_row", ctypes.c_size_t),
+                ("off_rec", ctypes.c_size_t), ("off_err", ctypes.c_size_t), ("rec_bytes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Rays(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_void_p), ("dir", ctypes.c_void_p), ("t_max", ctypes.c_void_p),
+                ("start_cell", ctypes.c_void_p), ("n_rays", ctypes.c_int64)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_float), ("max_steps", ctypes.c_int32)]
+
+
+class CameraDesc(ctypes.Structure):
+    _fields_ = [("pose", ctypes.c_float * 12), ("fov_deg", ctypes.c_float), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32)]
+
+
+class BoundDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("p", ctypes.c_float * 6)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected_busy", ctypes.c_int64),
+                ("tiles_done", ctypes.c_int64), ("rays_done", ctypes.c_int64), ("inflight", ctypes.c_int32),
+                ("pool_used_bytes", ctypes.c_int64), ("pool_bytes", ctypes.c_int64)]
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded librf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              f"or python -m paper_2502_01157_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        st = ctypes.c_int
+        L.rf_last_error.restype = ctypes.c_char_p
+        L.rf_version.restype = ctypes.c_char_p
+        L.rf_packed_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_size_t)]
+        L.rf_pack_scene.argtypes = [ctypes.POINTER(Scene), ctypes.c_int32, P, ctypes.c_size_t, ctypes.c_int,
+                                    ctypes.POINTER(PackedSceneDesc), P]
+        L.rf_packed_errors.argtypes = [ctypes.POINTER(PackedSceneDesc), P, P]
+        L.rf_raygen.argtypes = [ctypes.POINTER(CameraDesc), ctypes.POINTER(BoundDesc), ctypes.c_int32, P, P, P, P,
+                                P, P]
+        L.rf_render_forward.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Rays),
+                                        ctypes.POINTER(Params), P, P, P, P]
+        L.rf_render_trace.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Rays),
+                                      ctypes.POINTER(Params), ctypes.c_int32, P, P, P, P, P, P]
+        L.rf_render_backward.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Rays),
+                                         ctypes.POINTER(Params), P, P, P, P, P, P, P, ctypes.c_int32, P]
+        L.rf_packed_planes.argtypes = [ctypes.POINTER(PackedSceneDesc), P, P]
+        L.rf_packed_attributes.argtypes = [ctypes.POINTER(PackedSceneDesc), P, P, P]
+        for name in ("rf_packed_bytes", "rf_pack_scene", "rf_packed_errors", "rf_raygen", "rf_render_forward",
+                     "rf_render_trace", "rf_render_backward", "rf_packed_planes", "rf_packed_attributes"):
+            getattr(L, name).restype = st
+        if hasattr(L, "rf_server_create"):
+            L.rf_server_create.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Params),
+                                           ctypes.POINTER(BoundDesc), ctypes.c_size_t, ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]
+            L.rf_server_submit.argtypes = [P, ctypes.POINTER(CameraDesc), ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_uint64)]
+            L.rf_server_poll.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32)]
+            L.rf_server_result.argtypes = [P, ctypes.c_uint64, P, ctypes.c_size_t]
+            L.rf_server_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+            L.rf_server_destroy.argtypes = [P]
+            for name in ("rf_server_create", "rf_server_submit", "rf_server_poll", "rf_server_result",
+                         "rf_server_stats", "rf_server_destroy"):
+                getattr(L, name).restype = st
+        _lib = L
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != RF_OK:
+        raise RfError(status, lib().rf_last_error().decode(errors="replace"))

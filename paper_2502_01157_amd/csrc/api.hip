@@ -1,0 +1,319 @@
+// C ABI of librf.so: argument validation, workspace layout, dispatch.
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "radfoam.h"
+#include "rf_device.hpp"
+#include "rf_kernels.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+rf_status fail(rf_status st, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+rf_status ok()
+{
+    g_err[0] = '\0';
+    return RF_OK;
+}
+
+rf_status hip_status(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return ok();
+    return fail(RF_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t planes, adj, row, rec, err, total;
+    int rec_bytes;
+};
+
+Layout layout(int64_t n, int64_t e, int deg, bool bf16)
+{
+    Layout L;
+    L.rec_bytes = rf::rec_bytes(deg, bf16);
+    size_t p = 0;
+    L.planes = p;
+    p = align256(p + (size_t)e * 16);
+    L.adj = p;
+    p = align256(p + (size_t)e * 8);
+    L.row = p;
+    p = align256(p + (size_t)n * 8);
+    L.rec = p;
+    p = align256(p + (size_t)n * L.rec_bytes);
+    L.err = p;
+    p = align256(p + 8);
+    L.total = p;
+    return L;
+}
+
+rf_status check_packed(const rf_packed_scene* s)
+{
+    if (!s || !s->base) return fail(RF_ERR_INVALID_ARG, "packed scene is NULL or has no workspace");
+    if (s->sh_degree < 0 || s->sh_degree > RF_MAX_SH_DEGREE)
+        return fail(RF_ERR_INVALID_ARG, "packed scene has sh_degree %d", s->sh_degree);
+    if (s->attr_dtype != RF_F32 && s->attr_dtype != RF_BF16)
+        return fail(RF_ERR_INVALID_ARG, "packed scene has attr_dtype %d", (int)s->attr_dtype);
+    if (s->n_sites < 1 || s->n_sites > RF_MAX_SITES || s->n_edges < 0 || s->n_edges > INT32_MAX)
+        return fail(RF_ERR_INVALID_ARG, "packed scene sizes out of range");
+    const Layout L = layout(s->n_sites, s->n_edges, s->sh_degree, s->attr_dtype == RF_BF16);
+    if (s->bytes < L.total || s->off_planes != L.planes || s->off_adj != L.adj || s->off_row != L.row ||
+        s->off_rec != L.rec || s->off_err != L.err || s->rec_bytes != L.rec_bytes)
+        return fail(RF_ERR_INVALID_ARG, "packed scene descriptor does not match its sizes (not from rf_pack_scene?)");
+    return RF_OK;
+}
+
+rf::SceneView view(const rf_packed_scene* s)
+{
+    const unsigned char* b = static_cast<const unsigned char*>(s->base);
+    rf::SceneView v;
+    v.planes = reinterpret_cast<const float4*>(b + s->off_planes);
+    v.adj = reinterpret_cast<const uint2*>(b + s->off_adj);
+    v.row = reinterpret_cast<const uint2*>(b + s->off_row);
+    v.rec = b + s->off_rec;
+    v.n_sites = s->n_sites;
+    v.n_edges = s->n_edges;
+    return v;
+}
+
+rf_status check_rays(const rf_rays* rays)
+{
+    if (!rays) return fail(RF_ERR_INVALID_ARG, "rays is NULL");
+    if (rays->n_rays < 0 || rays->n_rays > ((int64_t)1 << 37))
+        return fail(RF_ERR_INVALID_ARG, "n_rays = %lld out of range", (long long)rays->n_rays);
+    if (rays->n_rays > 0 && (!rays->origin || !rays->dir || !rays->t_max || !rays->start_cell))
+        return fail(RF_ERR_INVALID_ARG, "a ray array is NULL");
+    return RF_OK;
+}
+
+rf_status check_params(const rf_params* p)
+{
+    if (!p) return fail(RF_ERR_INVALID_ARG, "params is NULL");
+    if (!(p->eps >= 0.0f) || !isfinite(p->eps)) return fail(RF_ERR_INVALID_ARG, "eps must be finite and >= 0");
+    if (p->max_steps < 1) return fail(RF_ERR_INVALID_ARG, "max_steps must be >= 1");
+    return RF_OK;
+}
+
+rf::WalkArgs walk_args(const rf_packed_scene* s, const rf_rays* r, const rf_params* p)
+{
+    rf::WalkArgs a;
+    memset(&a, 0, sizeof a);
+    a.s = view(s);
+    a.origin = r->origin;
+    a.dir = r->dir;
+    a.t_max = r->t_max;
+    a.start = r->start_cell;
+    a.n_rays = r->n_rays;
+    a.eps = p->eps;
+    a.max_steps = p->max_steps;
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rf_last_error(void) { return g_err; }
+
+const char* rf_version(void) { return "radfoam-mi355x 0.1 (gfx950)"; }
+
+rf_status rf_packed_bytes(int64_t n_sites, int64_t n_edges, int32_t sh_degree, rf_dtype attr_dtype, size_t* bytes)
+{
+    if (!bytes) return fail(RF_ERR_INVALID_ARG, "bytes is NULL");
+    if (n_sites < 1 || n_edges < 0 || n_edges > INT32_MAX) return fail(RF_ERR_INVALID_ARG, "sizes out of range");
+    if (n_sites > RF_MAX_SITES) return fail(RF_ERR_UNSUPPORTED, "n_sites > %lld", (long long)RF_MAX_SITES);
+    if (sh_degree < 0 || sh_degree > RF_MAX_SH_DEGREE) return fail(RF_ERR_INVALID_ARG, "sh_degree out of range");
+    if (attr_dtype != RF_F32 && attr_dtype != RF_BF16) return fail(RF_ERR_INVALID_ARG, "bad attr_dtype");
+    *bytes = layout(n_sites, n_edges, sh_degree, attr_dtype == RF_BF16).total;
+    return ok();
+}
+
+rf_status rf_pack_scene(const rf_scene* scene, rf_dtype attr_dtype, void* workspace, size_t workspace_bytes,
+                        int validate, rf_packed_scene* out, void* stream)
+{
+    if (!scene || !out) return fail(RF_ERR_INVALID_ARG, "scene or out is NULL");
+    size_t need = 0;
+    rf_status st = rf_packed_bytes(scene->n_sites, scene->n_edges, scene->sh_degree, attr_dtype, &need);
+    if (st != RF_OK) return st;
+    if (!workspace || workspace_bytes < need)
+        return fail(RF_ERR_INVALID_ARG, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, need);
+    if (((uintptr_t)workspace & 255) != 0) return fail(RF_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (!scene->sites || !scene->nbr_off || !scene->density || !scene->sh || (scene->n_edges > 0 && !scene->nbr_idx))
+        return fail(RF_ERR_INVALID_ARG, "a scene array is NULL");
+    const bool bf16 = attr_dtype == RF_BF16;
+    const Layout L = layout(scene->n_sites, scene->n_edges, scene->sh_degree, bf16);
+    unsigned char* b = static_cast<unsigned char*>(workspace);
+    rf::PackArgs a;
+    a.sites = scene->sites;
+    a.off = scene->nbr_off;
+    a.idx = scene->nbr_idx;
+    a.density = scene->density;
+    a.sh = scene->sh;
+    a.n_sites = scene->n_sites;
+    a.n_edges = scene->n_edges;
+    a.planes = reinterpret_cast<float4*>(b + L.planes);
+    a.adj = reinterpret_cast<uint2*>(b + L.adj);
+    a.row = reinterpret_cast<uint2*>(b + L.row);
+    a.rec = b + L.rec;
+    a.err = reinterpret_cast<int32_t*>(b + L.err);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st = hip_status(rf::launch_pack(scene->sh_degree, bf16, a, s), "pack kernels");
+    if (st != RF_OK) return st;
+    out->base = workspace;
+    out->bytes = workspace_bytes;
+    out->n_sites = scene->n_sites;
+    out->n_edges = scene->n_edges;
+    out->sh_degree = scene->sh_degree;
+    out->attr_dtype = attr_dtype;
+    out->off_planes = L.planes;
+    out->off_adj = L.adj;
+    out->off_row = L.row;
+    out->off_rec = L.rec;
+    out->off_err = L.err;
+    out->rec_bytes = L.rec_bytes;
+    out->reserved = 0;
+    if (validate) {
+        int32_t errs[2];
+        st = rf_packed_errors(out, errs, stream);
+        if (st != RF_OK) return st;
+        if (errs[1]) return fail(RF_ERR_UNSUPPORTED, "%d rows have more than %d neighbours", errs[1], RF_MAX_DEGREE);
+        if (errs[0]) return fail(RF_ERR_INVALID_ARG, "CSR has %d invalid entries", errs[0]);
+    }
+    return ok();
+}
+
+rf_status rf_packed_errors(const rf_packed_scene* packed, int32_t errors[2], void* stream)
+{
+    rf_status st = check_packed(packed);
+    if (st != RF_OK) return st;
+    if (!errors) return fail(RF_ERR_INVALID_ARG, "errors is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const unsigned char* b = static_cast<const unsigned char*>(packed->base);
+    hipError_t e = hipMemcpyAsync(errors, b + packed->off_err, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return hip_status(e, "reading pack counters");
+}
+
+rf_status rf_raygen(const rf_camera* cam, const rf_bound* bound, int32_t start, float* origin, float* dir,
+                    float* t_max, int32_t* start_cell, int32_t* pixel, void* stream)
+{
+    if (!cam || !bound) return fail(RF_ERR_INVALID_ARG, "camera or bound is NULL");
+    if (cam->width <= 0 || cam->height <= 0 || (int64_t)cam->width * cam->height > ((int64_t)1 << 31))
+        return fail(RF_ERR_INVALID_ARG, "image size %d x %d out of range", cam->width, cam->height);
+    if (!(cam->fov_deg > 0.0f && cam->fov_deg < 180.0f)) return fail(RF_ERR_INVALID_ARG, "fov must be in (0, 180)");
+    if (bound->kind != 0 && bound->kind != 1) return fail(RF_ERR_INVALID_ARG, "bound kind must be 0 or 1");
+    if (!origin || !dir || !t_max || !start_cell) return fail(RF_ERR_INVALID_ARG, "an output array is NULL");
+    rf::RaygenArgs a;
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) a.rot[3 * r + c] = cam->pose[4 * r + c];
+        a.pos[r] = cam->pose[4 * r + 3];
+    }
+    a.focal = (float)(0.5 * cam->width / tan(0.5 * (double)cam->fov_deg * M_PI / 180.0));
+    a.width = cam->width;
+    a.height = cam->height;
+    a.bound_kind = bound->kind;
+    for (int k = 0; k < 6; ++k) a.bound[k] = bound->p[k];
+    a.start = start;
+    a.origin = origin;
+    a.dir = dir;
+    a.t_max = t_max;
+    a.start_cell = start_cell;
+    a.pixel = pixel;
+    return hip_status(rf::launch_raygen(a, static_cast<hipStream_t>(stream)), "raygen kernel");
+}
+
+rf_status rf_render_forward(const rf_packed_scene* scene, const rf_rays* rays, const rf_params* params, float* rgb,
+                            float* t_final, int32_t* steps, void* stream)
+{
+    rf_status st;
+    if ((st = check_packed(scene)) != RF_OK || (st = check_rays(rays)) != RF_OK || (st = check_params(params)) != RF_OK)
+        return st;
+    if (rays->n_rays > 0 && (!rgb || !t_final || !steps)) return fail(RF_ERR_INVALID_ARG, "an output array is NULL");
+    rf::WalkArgs a = walk_args(scene, rays, params);
+    a.rgb = rgb;
+    a.t_final = t_final;
+    a.steps = steps;
+    return hip_status(rf::launch_walk(rf::kForward, scene->sh_degree, scene->attr_dtype == RF_BF16, a,
+                                      static_cast<hipStream_t>(stream)),
+                      "forward walk");
+}
+
+rf_status rf_render_trace(const rf_packed_scene* scene, const rf_rays* rays, const rf_params* params, int32_t max_len,
+                          float* rgb, float* t_final, int32_t* steps, int32_t* cells, float* t_exit, void* stream)
+{
+    rf_status st;
+    if ((st = check_packed(scene)) != RF_OK || (st = check_rays(rays)) != RF_OK || (st = check_params(params)) != RF_OK)
+        return st;
+    if (max_len < 1) return fail(RF_ERR_INVALID_ARG, "max_len must be >= 1");
+    if (rays->n_rays > 0 && (!rgb || !t_final || !steps || !cells || !t_exit))
+        return fail(RF_ERR_INVALID_ARG, "an output array is NULL");
+    rf::WalkArgs a = walk_args(scene, rays, params);
+    a.rgb = rgb;
+    a.t_final = t_final;
+    a.steps = steps;
+    a.max_len = max_len;
+    a.cells = cells;
+    a.t_exit = t_exit;
+    return hip_status(rf::launch_walk(rf::kTrace, scene->sh_degree, scene->attr_dtype == RF_BF16, a,
+                                      static_cast<hipStream_t>(stream)),
+                      "traced walk");
+}
+
+rf_status rf_render_backward(const rf_packed_scene* scene, const rf_rays* rays, const rf_params* params,
+                             const float* rgb, const float* t_final, const float* grad_rgb, const float* grad_t_final,
+                             float* grad_sites, float* grad_density, float* grad_sh, int32_t mode, void* stream)
+{
+    rf_status st;
+    if ((st = check_packed(scene)) != RF_OK || (st = check_rays(rays)) != RF_OK || (st = check_params(params)) != RF_OK)
+        return st;
+    if (mode != 0 && mode != 1) return fail(RF_ERR_INVALID_ARG, "mode must be 0 or 1");
+    if (rays->n_rays > 0 && (!rgb || !t_final || !grad_rgb))
+        return fail(RF_ERR_INVALID_ARG, "rgb, t_final and grad_rgb are required");
+    if (!grad_sites || !grad_density || !grad_sh) return fail(RF_ERR_INVALID_ARG, "a gradient array is NULL");
+    rf::WalkArgs a = walk_args(scene, rays, params);
+    a.rgb_in = rgb;
+    a.t_final_in = t_final;
+    a.grad_rgb = grad_rgb;
+    a.grad_t = grad_t_final;
+    a.g_sites = grad_sites;
+    a.g_density = grad_density;
+    a.g_sh = grad_sh;
+    return hip_status(rf::launch_walk(mode == 0 ? rf::kBackwardReduce : rf::kBackwardAtomic, scene->sh_degree,
+                                      scene->attr_dtype == RF_BF16, a, static_cast<hipStream_t>(stream)),
+                      "backward walk");
+}
+
+rf_status rf_packed_planes(const rf_packed_scene* scene, float* planes, void* stream)
+{
+    rf_status st = check_packed(scene);
+    if (st != RF_OK) return st;
+    if (!planes && scene->n_edges > 0) return fail(RF_ERR_INVALID_ARG, "planes is NULL");
+    return hip_status(rf::launch_unpack(scene->sh_degree, scene->attr_dtype == RF_BF16, view(scene), planes, nullptr,
+                                        nullptr, static_cast<hipStream_t>(stream)),
+                      "plane read-back");
+}
+
+rf_status rf_packed_attributes(const rf_packed_scene* scene, float* density, float* sh, void* stream)
+{
+    rf_status st = check_packed(scene);
+    if (st != RF_OK) return st;
+    if (!density || !sh) return fail(RF_ERR_INVALID_ARG, "density or sh is NULL");
+    return hip_status(rf::launch_unpack(scene->sh_degree, scene->attr_dtype == RF_BF16, view(scene), nullptr, density,
+                                        sh, static_cast<hipStream_t>(stream)),
+                      "attribute read-back");
+}
+
+}  // extern "C"

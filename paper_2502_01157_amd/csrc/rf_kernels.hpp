@@ -1,0 +1,83 @@
+// Launch interface between the C ABI (api.hip) and the kernels (walk.hip, pack.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rf {
+
+struct SceneView {
+    const float4* planes;
+    const uint2* adj;
+    const uint2* row;
+    const unsigned char* rec;
+    int64_t n_sites;
+    int64_t n_edges;
+};
+
+struct WalkArgs {
+    SceneView s;
+    const float* origin;
+    const float* dir;
+    const float* t_max;
+    const int32_t* start;
+    int64_t n_rays;
+    float eps;
+    int32_t max_steps;
+    // forward outputs
+    float* rgb;
+    float* t_final;
+    int32_t* steps;
+    // trace outputs
+    int32_t max_len;
+    int32_t* cells;
+    float* t_exit;
+    // backward inputs / outputs
+    const float* rgb_in;
+    const float* t_final_in;
+    const float* grad_rgb;
+    const float* grad_t;
+    float* g_sites;
+    float* g_density;
+    float* g_sh;
+};
+
+struct PackArgs {
+    const float* sites;
+    const int32_t* off;
+    const int32_t* idx;
+    const float* density;
+    const float* sh;
+    int64_t n_sites;
+    int64_t n_edges;
+    float4* planes;
+    uint2* adj;
+    uint2* row;
+    unsigned char* rec;
+    int32_t* err;
+};
+
+struct RaygenArgs {
+    float rot[9];
+    float pos[3];
+    float focal;
+    int32_t width, height;
+    int32_t bound_kind;
+    float bound[6];
+    int32_t start;
+    float* origin;
+    float* dir;
+    float* t_max;
+    int32_t* start_cell;
+    int32_t* pixel;
+};
+
+enum WalkKind { kForward = 0, kTrace = 1, kBackwardReduce = 2, kBackwardAtomic = 3 };
+
+hipError_t launch_walk(WalkKind kind, int sh_degree, bool bf16, const WalkArgs& a, hipStream_t stream);
+hipError_t launch_pack(int sh_degree, bool bf16, const PackArgs& a, hipStream_t stream);
+hipError_t launch_raygen(const RaygenArgs& a, hipStream_t stream);
+hipError_t launch_unpack(int sh_degree, bool bf16, const SceneView& s, float* planes_out, float* density_out,
+                         float* sh_out, hipStream_t stream);
+
+}  // namespace rf

@@ -1,0 +1,453 @@
+// The forward and backward Voronoi ray walk (Algorithm 1 and its gradient) for gfx950.
+//
+// One ray per lane; rays arrive in 8x8 screen-tile order, so a wavefront is
+// one tile and its lanes walk mostly the same cells at the same time.
+//
+// Per visited cell i the walk
+//   1. scans the cell's face planes (one float4 per Delaunay neighbour),
+//      keeping the nearest front face: den = n.d > 0 and the smallest
+//      t = (c - n.o) / den, compared without division as
+//      num_k * den_best < num_best * den_k (ties keep the first face),
+//   2. loads the cell's record (SH and density, fp32 or bf16) and composites
+//      the segment [t0, te], te = max(t0, min(t1, t_max)), with eq. (3)-(4):
+//      C += T (1 - exp(-sigma delta)) c, T *= exp(-sigma delta),
+//   3. follows the winning face to the neighbour (its row comes with the face).
+// The face the ray came through is never re-taken: its plane seen from the new
+// cell is the exact negation of the entry plane, so its den is exactly negative.
+//
+// The backward pass recomputes the same walk (same code, same rounding) and
+// differentiates eq. (3)-(4) in forward order using the saved output colour:
+//   R_n = C_out - sum_{k<=n} w_k c_k,  w_n = T_n alpha_n,
+//   dL/dtau_n = g.(T_{n+1} c_n - R_n) - g_T T_final,
+//   dL/dsigma_i += delta_n dL/dtau_n,   dL/dk_{i,b} += g w_n Y_b,
+//   an exit t_n that moves with its face (t0 <= t1 < t_max) gets
+//   dL/dt_n = sigma_n dL/dtau_n - sigma_{n+1} dL/dtau_{n+1}, and with
+//   p = o + t_n d, den = (x_j - x_i).d:  dt/dx_i = (p - x_i)/den,
+//   dt/dx_j = (x_j - p)/den   (geometry enters only through the segment
+//   widths, Sec. 3.1).
+// Each visit's gradients for one cell (3B SH values, density, site) form a
+// package that is emitted one iteration later, when the following visit has
+// fixed the exit gradient. Packages are summed across the wavefront per cell
+// (lanes grouped by ballot, columns summed through LDS) before one coalesced
+// float atomic per value and group.
+
+#include "rf_device.hpp"
+#include "rf_kernels.hpp"
+
+namespace rf {
+
+struct FaceHit {
+    float num, den;
+    int k;  // index within the row, -1 if no front face
+};
+
+__device__ inline FaceHit nearest_front_face(const float4* __restrict__ planes, int beg, int deg, float ox, float oy,
+                                             float oz, float dx, float dy, float dz)
+{
+    float bn = 1.0f, bd = 0.0f;
+    int bk = -1;
+    for (int k = 0; k < deg; k += 4) {
+        float4 p[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) p[u] = planes[beg + min(k + u, deg - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float den = fmaf(p[u].z, dz, fmaf(p[u].y, dy, p[u].x * dx));
+            const float num = p[u].w - fmaf(p[u].z, oz, fmaf(p[u].y, oy, p[u].x * ox));
+            const bool better = (den > 0.0f) && (num * bd < bn * den);
+            bn = better ? num : bn;
+            bd = better ? den : bd;
+            bk = better ? min(k + u, deg - 1) : bk;
+        }
+    }
+    return {bn, bd, bk};
+}
+
+template <int DEG>
+__device__ inline void colour(const Attr<DEG>& at, const float* Y, float c[3])
+{
+    c[0] = c[1] = c[2] = 0.0f;
+#pragma unroll
+    for (int b = 0; b < sh_count(DEG); ++b) {
+        c[0] = fmaf(at.sh[3 * b + 0], Y[b], c[0]);
+        c[1] = fmaf(at.sh[3 * b + 1], Y[b], c[1]);
+        c[2] = fmaf(at.sh[3 * b + 2], Y[b], c[2]);
+    }
+}
+
+__device__ inline int64_t ray_index()
+{
+    return xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+}
+
+// ---------------------------------------------------------------------------
+// Forward (and traced forward).
+// ---------------------------------------------------------------------------
+template <int DEG, bool BF16, bool TRACE>
+__global__ __launch_bounds__(kBlock) void k_forward(WalkArgs a)
+{
+    const int64_t r = ray_index();
+    if (r >= a.n_rays) return;
+    const float ox = a.origin[3 * r], oy = a.origin[3 * r + 1], oz = a.origin[3 * r + 2];
+    const float dx = a.dir[3 * r], dy = a.dir[3 * r + 1], dz = a.dir[3 * r + 2];
+    const float tmax = a.t_max[r];
+    const int start = a.start[r];
+    float C[3] = {0.0f, 0.0f, 0.0f};
+    float T = 1.0f;
+    int status;
+    if (start < 0 || (int64_t)start >= a.s.n_sites) {
+        status = -1;  // RF_RAY_BAD_START
+    } else {
+        float Y[sh_count(DEG)];
+        sh_basis<DEG>(dx, dy, dz, Y);
+        uint2 ref = a.s.row[start];
+        float t0 = 0.0f;
+        int n = 0;
+        for (;;) {
+            if (!(T > a.eps)) {
+                status = n;
+                break;
+            }
+            if (n == a.max_steps) {
+                status = -2;  // RF_RAY_MAX_STEPS
+                break;
+            }
+            const int cell = ref_cell(ref), beg = ref_beg(ref);
+            Attr<DEG> at;
+            load_record<DEG, BF16>(a.s.rec, cell, at);
+            const FaceHit h = nearest_front_face(a.s.planes, beg, ref_deg(ref), ox, oy, oz, dx, dy, dz);
+            const float t1 = h.k >= 0 ? h.num / h.den : INFINITY;
+            const float te = fmaxf(t0, fminf(t1, tmax));
+            const float tau = at.sigma > 0.0f ? at.sigma * (te - t0) : 0.0f;
+            const float alpha = -expm1f(-tau);
+            float c[3];
+            colour<DEG>(at, Y, c);
+            const float w = T * alpha;
+            C[0] = fmaf(w, c[0], C[0]);
+            C[1] = fmaf(w, c[1], C[1]);
+            C[2] = fmaf(w, c[2], C[2]);
+            T *= expf(-tau);
+            if constexpr (TRACE) {
+                if (n < a.max_len) {
+                    a.cells[r * a.max_len + n] = cell;
+                    a.t_exit[r * a.max_len + n] = te;
+                }
+            }
+            ++n;
+            if (h.k < 0 || t1 >= tmax) {
+                status = n;
+                break;
+            }
+            ref = a.s.adj[beg + h.k];
+            t0 = te;
+        }
+    }
+    a.rgb[3 * r + 0] = C[0];
+    a.rgb[3 * r + 1] = C[1];
+    a.rgb[3 * r + 2] = C[2];
+    a.t_final[r] = T;
+    a.steps[r] = status;
+}
+
+// ---------------------------------------------------------------------------
+// Backward.
+// ---------------------------------------------------------------------------
+
+// One cell's gradient package: SH gradient is gw[ch] * Y[b] (rank one).
+struct Package {
+    int cell;
+    float gw[3];
+    float dsig;
+    float dx[3];
+};
+
+template <int DEG>
+__device__ inline void emit_atomic(bool has, const Package& p, const float* Y, const WalkArgs& a)
+{
+    if (!has) return;
+    constexpr int B = sh_count(DEG);
+    float* gsh = a.g_sh + (size_t)p.cell * 3 * B;
+    if (p.gw[0] != 0.0f || p.gw[1] != 0.0f || p.gw[2] != 0.0f) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            unsafeAtomicAdd(gsh + 3 * b + 0, p.gw[0] * Y[b]);
+            unsafeAtomicAdd(gsh + 3 * b + 1, p.gw[1] * Y[b]);
+            unsafeAtomicAdd(gsh + 3 * b + 2, p.gw[2] * Y[b]);
+        }
+    }
+    unsafeAtomicAdd(a.g_density + p.cell, p.dsig);
+    unsafeAtomicAdd(a.g_sites + 3 * (size_t)p.cell + 0, p.dx[0]);
+    unsafeAtomicAdd(a.g_sites + 3 * (size_t)p.cell + 1, p.dx[1]);
+    unsafeAtomicAdd(a.g_sites + 3 * (size_t)p.cell + 2, p.dx[2]);
+}
+
+// Called with every lane of the wavefront active. Lanes holding a package for
+// the same cell are grouped (leader by ballot); for each group, lane q < 3B+4
+// sums column q over the group's members from the wave's LDS rows and issues
+// one atomic, so a group costs one coalesced atomic instruction.
+// LDS row (stride S): Y[0..B-1], gw[0..2], dsig, dx[0..2], 1.
+template <int DEG>
+__device__ inline void emit_reduce(bool has, const Package& p, const float* Y, float* __restrict__ my, int lane,
+                                   const WalkArgs& a)
+{
+    constexpr int B = sh_count(DEG);
+    constexpr int S = (B + 8) | 1;
+    constexpr int NOUT = 3 * B + 4;
+    uint64_t pend = __ballot(has);
+    if (pend == 0) return;
+    if (has) {
+        float* row = my + lane * S;
+#pragma unroll
+        for (int b = 0; b < B; ++b) row[b] = Y[b];
+        row[B + 0] = p.gw[0];
+        row[B + 1] = p.gw[1];
+        row[B + 2] = p.gw[2];
+        row[B + 3] = p.dsig;
+        row[B + 4] = p.dx[0];
+        row[B + 5] = p.dx[1];
+        row[B + 6] = p.dx[2];
+        row[B + 7] = 1.0f;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // column owned by this lane
+    int colA, colB;
+    if (lane < 3 * B) {
+        colA = lane / 3;
+        colB = B + lane % 3;
+    } else {
+        colA = B + 3 + (lane - 3 * B);
+        colB = B + 7;
+    }
+    const int key_cell = has ? p.cell : -1;
+    while (pend) {
+        const int leader = __builtin_ctzll(pend);
+        const int key = __builtin_amdgcn_readlane(key_cell, leader);
+        const uint64_t members = __ballot(key_cell == key) & pend;
+        pend &= ~members;
+        if (lane < NOUT) {
+            float acc0 = 0.0f, acc1 = 0.0f;
+            uint64_t mm = members;
+            while (mm) {
+                const int m0 = __builtin_ctzll(mm);
+                mm &= mm - 1;
+                const float* r0 = my + m0 * S;
+                if (mm) {
+                    const int m1 = __builtin_ctzll(mm);
+                    mm &= mm - 1;
+                    const float* r1 = my + m1 * S;
+                    acc1 = fmaf(r1[colA], r1[colB], acc1);
+                }
+                acc0 = fmaf(r0[colA], r0[colB], acc0);
+            }
+            const float acc = acc0 + acc1;
+            float* dst;
+            if (lane < 3 * B)
+                dst = a.g_sh + (size_t)key * 3 * B + lane;
+            else if (lane == 3 * B)
+                dst = a.g_density + key;
+            else
+                dst = a.g_sites + 3 * (size_t)key + (lane - 3 * B - 1);
+            if (acc != 0.0f) unsafeAtomicAdd(dst, acc);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int DEG, bool BF16, bool REDUCE>
+__global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
+{
+    constexpr int B = sh_count(DEG);
+    constexpr int S = (B + 8) | 1;
+    __shared__ float lds[REDUCE ? (kBlock / kWave) * kWave * S : 1];
+    const int lane = threadIdx.x & (kWave - 1);
+    float* my = lds + (REDUCE ? (threadIdx.x / kWave) * kWave * S : 0);
+
+    const int64_t r = ray_index();
+    // lane state: 0 walking, 1 emit the last visit, 2 emit the next cell's entry term, 3 done
+    int state = 3;
+    float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 1, tmax = 0;
+    float g[3] = {0, 0, 0}, gT = 0, Cout[3] = {0, 0, 0}, Tfin = 1;
+    uint2 ref = make_uint2(0, 0);
+    if (r < a.n_rays) {
+        const int start = a.start[r];
+        if (start >= 0 && (int64_t)start < a.s.n_sites) {
+            state = 0;
+            ox = a.origin[3 * r];
+            oy = a.origin[3 * r + 1];
+            oz = a.origin[3 * r + 2];
+            dx = a.dir[3 * r];
+            dy = a.dir[3 * r + 1];
+            dz = a.dir[3 * r + 2];
+            tmax = a.t_max[r];
+            g[0] = a.grad_rgb[3 * r];
+            g[1] = a.grad_rgb[3 * r + 1];
+            g[2] = a.grad_rgb[3 * r + 2];
+            gT = a.grad_t ? a.grad_t[r] : 0.0f;
+            Cout[0] = a.rgb_in[3 * r];
+            Cout[1] = a.rgb_in[3 * r + 1];
+            Cout[2] = a.rgb_in[3 * r + 2];
+            Tfin = a.t_final_in[r];
+            ref = a.s.row[start];
+        }
+    }
+    float Y[B];
+    sh_basis<DEG>(dx, dy, dz, Y);
+
+    float T = 1.0f, t0 = 0.0f, Cacc[3] = {0.0f, 0.0f, 0.0f};
+    int n = 0;
+    // previous visit, awaiting its exit gradient
+    bool have_prev = false, p_moves = false;
+    Package prev = {0, {0, 0, 0}, 0, {0, 0, 0}};
+    float p_site[3] = {0, 0, 0}, p_t1 = 0, p_den = 1, p_sdt = 0;
+    // entry term of the cell after the last visit
+    Package entry = {0, {0, 0, 0}, 0, {0, 0, 0}};
+    bool entry_valid = false;
+
+    while (__ballot(state != 3)) {
+        bool has = false;
+        Package out = prev;
+        if (state == 0) {
+            bool stop = !(T > a.eps) || (n == a.max_steps);
+            if (!stop) {
+                const int cell = ref_cell(ref), beg = ref_beg(ref);
+                Attr<DEG> at;
+                load_record<DEG, BF16>(a.s.rec, cell, at);
+                const FaceHit h = nearest_front_face(a.s.planes, beg, ref_deg(ref), ox, oy, oz, dx, dy, dz);
+                const float t1 = h.k >= 0 ? h.num / h.den : INFINITY;
+                const float te = fmaxf(t0, fminf(t1, tmax));
+                const float delta = te - t0;
+                const float tau = at.sigma > 0.0f ? at.sigma * delta : 0.0f;
+                const float alpha = -expm1f(-tau);
+                float c[3];
+                colour<DEG>(at, Y, c);
+                const float w = T * alpha;
+                Cacc[0] = fmaf(w, c[0], Cacc[0]);
+                Cacc[1] = fmaf(w, c[1], Cacc[1]);
+                Cacc[2] = fmaf(w, c[2], Cacc[2]);
+                const float Tn = T * expf(-tau);
+                float dtau = -gT * Tfin;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) dtau = fmaf(g[ch], Tn * c[ch] - (Cout[ch] - Cacc[ch]), dtau);
+                const float sdt = at.sigma * dtau;
+                float edx[3] = {0.0f, 0.0f, 0.0f};
+                if (have_prev) {
+                    if (p_moves) {
+                        const float gt = p_sdt - sdt;
+                        const float px = fmaf(p_t1, dx, ox), py = fmaf(p_t1, dy, oy), pz = fmaf(p_t1, dz, oz);
+                        const float s = gt / p_den;
+                        prev.dx[0] = fmaf(s, px - p_site[0], prev.dx[0]);
+                        prev.dx[1] = fmaf(s, py - p_site[1], prev.dx[1]);
+                        prev.dx[2] = fmaf(s, pz - p_site[2], prev.dx[2]);
+                        edx[0] = s * (at.site[0] - px);
+                        edx[1] = s * (at.site[1] - py);
+                        edx[2] = s * (at.site[2] - pz);
+                    }
+                    has = true;
+                    out = prev;
+                }
+                prev.cell = cell;
+                prev.gw[0] = g[0] * w;
+                prev.gw[1] = g[1] * w;
+                prev.gw[2] = g[2] * w;
+                prev.dsig = delta * dtau;
+                prev.dx[0] = edx[0];
+                prev.dx[1] = edx[1];
+                prev.dx[2] = edx[2];
+                p_site[0] = at.site[0];
+                p_site[1] = at.site[1];
+                p_site[2] = at.site[2];
+                p_t1 = t1;
+                p_den = h.den;
+                p_sdt = sdt;
+                p_moves = (h.k >= 0) && (t1 < tmax) && (t1 >= t0);
+                have_prev = true;
+                T = Tn;
+                ++n;
+                if (h.k < 0 || t1 >= tmax) {
+                    stop = true;
+                } else {
+                    ref = a.s.adj[beg + h.k];
+                    t0 = te;
+                }
+            }
+            if (stop) {
+                if (have_prev && p_moves) {
+                    // the last exit moved with its face but no segment follows it
+                    const float px = fmaf(p_t1, dx, ox), py = fmaf(p_t1, dy, oy), pz = fmaf(p_t1, dz, oz);
+                    const float s = p_sdt / p_den;
+                    prev.dx[0] = fmaf(s, px - p_site[0], prev.dx[0]);
+                    prev.dx[1] = fmaf(s, py - p_site[1], prev.dx[1]);
+                    prev.dx[2] = fmaf(s, pz - p_site[2], prev.dx[2]);
+                    float xj[3];
+                    entry.cell = ref_cell(ref);
+                    load_site<DEG, BF16>(a.s.rec, entry.cell, xj);
+                    entry.dx[0] = s * (xj[0] - px);
+                    entry.dx[1] = s * (xj[1] - py);
+                    entry.dx[2] = s * (xj[2] - pz);
+                    entry_valid = true;
+                }
+                state = have_prev ? 1 : 3;
+            }
+        } else if (state == 1) {
+            has = true;
+            out = prev;
+            state = entry_valid ? 2 : 3;
+        } else if (state == 2) {
+            has = true;
+            out = entry;
+            state = 3;
+        }
+        if constexpr (REDUCE)
+            emit_reduce<DEG>(has, out, Y, my, lane, a);
+        else
+            emit_atomic<DEG>(has, out, Y, a);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch.
+// ---------------------------------------------------------------------------
+template <int DEG, bool BF16>
+static hipError_t launch_walk_t(WalkKind kind, const WalkArgs& a, hipStream_t stream)
+{
+    const int64_t blocks = (a.n_rays + kBlock - 1) / kBlock;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks), block(kBlock);
+    switch (kind) {
+    case kForward:
+        hipLaunchKernelGGL((k_forward<DEG, BF16, false>), grid, block, 0, stream, a);
+        break;
+    case kTrace:
+        hipLaunchKernelGGL((k_forward<DEG, BF16, true>), grid, block, 0, stream, a);
+        break;
+    case kBackwardReduce:
+        hipLaunchKernelGGL((k_backward<DEG, BF16, true>), grid, block, 0, stream, a);
+        break;
+    case kBackwardAtomic:
+        hipLaunchKernelGGL((k_backward<DEG, BF16, false>), grid, block, 0, stream, a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_walk(WalkKind kind, int sh_degree, bool bf16, const WalkArgs& a, hipStream_t stream)
+{
+    switch (sh_degree * 2 + (bf16 ? 1 : 0)) {
+    case 0: return launch_walk_t<0, false>(kind, a, stream);
+    case 1: return launch_walk_t<0, true>(kind, a, stream);
+    case 2: return launch_walk_t<1, false>(kind, a, stream);
+    case 3: return launch_walk_t<1, true>(kind, a, stream);
+    case 4: return launch_walk_t<2, false>(kind, a, stream);
+    case 5: return launch_walk_t<2, true>(kind, a, stream);
+    case 6: return launch_walk_t<3, false>(kind, a, stream);
+    case 7: return launch_walk_t<3, true>(kind, a, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace rf

@@ -1,0 +1,259 @@
+"""Torch-facing wrappers of the C ABI: packed scenes, ray generation, the
+forward/backward walk and the autograd Function.
+
+PyTorch provides device memory and the current HIP stream; all arithmetic of
+the walk runs in librf.so.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib as L
+
+DEFAULT_EPS = 1e-4
+DEFAULT_MAX_STEPS = 8192
+
+
+def _stream(device: Optional[torch.device] = None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _dev(t: torch.Tensor, dtype: torch.dtype, shape: Sequence[int], name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def sh_count(deg: int) -> int:
+    return (deg + 1) ** 2
+
+
+class PackedScene:
+    """Device-resident packed scene (face planes, neighbour rows, cell records).
+
+    The workspace is one uint8 CUDA tensor owned by this object. ``pack`` can be
+    called again after the scene's sites or attributes change (same sizes).
+    """
+
+    def __init__(self, sites: torch.Tensor, off: torch.Tensor, idx: torch.Tensor, density: torch.Tensor,
+                 sh: torch.Tensor, sh_degree: int, attr_dtype: str = "f32", validate: bool = True):
+        self.n_sites = int(sites.shape[0])
+        self.n_edges = int(idx.shape[0])
+        self.sh_degree = int(sh_degree)
+        self.attr_dtype = {"f32": L.RF_F32, "bf16": L.RF_BF16}[attr_dtype]
+        nbytes = ctypes.c_size_t()
+        L.check(L.lib().rf_packed_bytes(self.n_sites, self.n_edges, self.sh_degree, self.attr_dtype,
+                                        ctypes.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=sites.device)
+        self.desc = L.PackedSceneDesc()
+        self.off = off
+        self.idx = idx
+        self.pack(sites, density, sh, validate=validate)
+
+    def pack(self, sites: torch.Tensor, density: torch.Tensor, sh: torch.Tensor, validate: bool = False) -> None:
+        n, B = self.n_sites, sh_count(self.sh_degree)
+        _dev(sites, torch.float32, (n, 3), "sites")
+        _dev(self.off, torch.int32, (n + 1,), "off")
+        _dev(self.idx, torch.int32, (self.n_edges,), "idx")
+        _dev(density, torch.float32, (n,), "density")
+        _dev(sh, torch.float32, (n, B, 3), "sh")
+        sc = L.Scene(sites.data_ptr(), self.off.data_ptr(), self.idx.data_ptr(), density.data_ptr(),
+                     sh.data_ptr(), n, self.n_edges, self.sh_degree)
+        L.check(L.lib().rf_pack_scene(ctypes.byref(sc), self.attr_dtype, self.workspace.data_ptr(),
+                                      self.workspace.numel(), int(validate), ctypes.byref(self.desc),
+                                      _stream(sites.device)))
+
+    def errors(self) -> Tuple[int, int]:
+        e = (ctypes.c_int32 * 2)()
+        L.check(L.lib().rf_packed_errors(ctypes.byref(self.desc), ctypes.addressof(e),
+                                         _stream(self.workspace.device)))
+        return int(e[0]), int(e[1])
+
+    def planes(self) -> torch.Tensor:
+        out = torch.empty((self.n_edges, 4), dtype=torch.float32, device=self.workspace.device)
+        L.check(L.lib().rf_packed_planes(ctypes.byref(self.desc), out.data_ptr(), _stream(out.device)))
+        return out
+
+    def attributes(self) -> Tuple[torch.Tensor, torch.Tensor]:
+        dev = self.workspace.device
+        dens = torch.empty(self.n_sites, dtype=torch.float32, device=dev)
+        sh = torch.empty((self.n_sites, sh_count(self.sh_degree), 3), dtype=torch.float32, device=dev)
+        L.check(L.lib().rf_packed_attributes(ctypes.byref(self.desc), dens.data_ptr(), sh.data_ptr(),
+                                             _stream(dev)))
+        return dens, sh
+
+
+def _rays(origin, direction, t_max, start) -> L.Rays:
+    R = int(direction.shape[0])
+    _dev(origin, torch.float32, (R, 3), "origin")
+    _dev(direction, torch.float32, (R, 3), "dir")
+    _dev(t_max, torch.float32, (R,), "t_max")
+    _dev(start, torch.int32, (R,), "start_cell")
+    return L.Rays(origin.data_ptr(), direction.data_ptr(), t_max.data_ptr(), start.data_ptr(), R)
+
+
+def _params(eps: float, max_steps: int) -> L.Params:
+    return L.Params(float(eps), int(max_steps))
+
+
+def camera_desc(pose12, fov_deg: float, width: int, height: int) -> L.CameraDesc:
+    c = L.CameraDesc()
+    for k, v in enumerate(pose12):
+        c.pose[k] = float(v)
+    c.fov_deg = float(fov_deg)
+    c.width = int(width)
+    c.height = int(height)
+    return c
+
+
+def bound_desc(bound: tuple) -> L.BoundDesc:
+    b = L.BoundDesc()
+    if bound[0] == "box":
+        lo, hi = bound[1], bound[2]
+        vals = [lo] * 3 + [hi] * 3 if isinstance(lo, (int, float)) else list(lo) + list(hi)
+        b.kind = 0
+    elif bound[0] == "sphere":
+        vals = [bound[1], 0, 0, 0, 0, 0]
+        b.kind = 1
+    else:
+        raise ValueError(bound)
+    for k in range(6):
+        b.p[k] = float(vals[k])
+    return b
+
+
+def raygen(pose12, fov_deg: float, width: int, height: int, bound: tuple, start: int,
+           device="cuda", with_pixel: bool = True):
+    """Camera rays in 8x8 tile order: (origin, dir, t_max, start_cell, pixel)."""
+    R = int(width) * int(height)
+    dev = torch.device(device)
+    o = torch.empty((R, 3), dtype=torch.float32, device=dev)
+    d = torch.empty((R, 3), dtype=torch.float32, device=dev)
+    t = torch.empty(R, dtype=torch.float32, device=dev)
+    s = torch.empty(R, dtype=torch.int32, device=dev)
+    px = torch.empty(R, dtype=torch.int32, device=dev) if with_pixel else None
+    cam = camera_desc(pose12, fov_deg, width, height)
+    b = bound_desc(bound)
+    L.check(L.lib().rf_raygen(ctypes.byref(cam), ctypes.byref(b), int(start), o.data_ptr(), d.data_ptr(),
+                              t.data_ptr(), s.data_ptr(), _ptr(px), _stream(dev)))
+    return o, d, t, s, px
+
+
+def render_forward(scene: PackedScene, origin, direction, t_max, start, eps: float = DEFAULT_EPS,
+                   max_steps: int = DEFAULT_MAX_STEPS, out=None):
+    """rgb [R,3], t_final [R], steps [R] (int32; < 0 flags RF_RAY_*)."""
+    R = int(direction.shape[0])
+    dev = direction.device
+    if out is None:
+        out = (torch.empty((R, 3), dtype=torch.float32, device=dev),
+               torch.empty(R, dtype=torch.float32, device=dev),
+               torch.empty(R, dtype=torch.int32, device=dev))
+    rgb, tf, steps = out
+    rays = _rays(origin, direction, t_max, start)
+    p = _params(eps, max_steps)
+    L.check(L.lib().rf_render_forward(ctypes.byref(scene.desc), ctypes.byref(rays), ctypes.byref(p),
+                                      rgb.data_ptr(), tf.data_ptr(), steps.data_ptr(), _stream(dev)))
+    return rgb, tf, steps
+
+
+def render_trace(scene: PackedScene, origin, direction, t_max, start, eps: float = DEFAULT_EPS,
+                 max_steps: int = DEFAULT_MAX_STEPS, max_len: int = 1024):
+    R = int(direction.shape[0])
+    dev = direction.device
+    rgb = torch.empty((R, 3), dtype=torch.float32, device=dev)
+    tf = torch.empty(R, dtype=torch.float32, device=dev)
+    steps = torch.empty(R, dtype=torch.int32, device=dev)
+    cells = torch.full((R, max_len), -1, dtype=torch.int32, device=dev)
+    t_exit = torch.full((R, max_len), float("nan"), dtype=torch.float32, device=dev)
+    rays = _rays(origin, direction, t_max, start)
+    p = _params(eps, max_steps)
+    L.check(L.lib().rf_render_trace(ctypes.byref(scene.desc), ctypes.byref(rays), ctypes.byref(p), int(max_len),
+                                    rgb.data_ptr(), tf.data_ptr(), steps.data_ptr(), cells.data_ptr(),
+                                    t_exit.data_ptr(), _stream(dev)))
+    return dict(rgb=rgb, t_final=tf, steps=steps, cells=cells, t_exit=t_exit)
+
+
+def render_backward(scene: PackedScene, origin, direction, t_max, start, rgb, t_final, grad_rgb,
+                    grad_t_final=None, eps: float = DEFAULT_EPS, max_steps: int = DEFAULT_MAX_STEPS,
+                    mode: int = 0, grads=None):
+    """Gradients (sites [N,3], density [N], sh [N,B,3]); accumulated into ``grads`` if given."""
+    R = int(direction.shape[0])
+    dev = direction.device
+    n, B = scene.n_sites, sh_count(scene.sh_degree)
+    if grads is None:
+        grads = (torch.zeros((n, 3), dtype=torch.float32, device=dev),
+                 torch.zeros(n, dtype=torch.float32, device=dev),
+                 torch.zeros((n, B, 3), dtype=torch.float32, device=dev))
+    gs, gd, gsh = grads
+    _dev(rgb, torch.float32, (R, 3), "rgb")
+    _dev(t_final, torch.float32, (R,), "t_final")
+    _dev(grad_rgb, torch.float32, (R, 3), "grad_rgb")
+    if grad_t_final is not None:
+        _dev(grad_t_final, torch.float32, (R,), "grad_t_final")
+    _dev(gs, torch.float32, (n, 3), "grad_sites")
+    _dev(gd, torch.float32, (n,), "grad_density")
+    _dev(gsh, torch.float32, (n, B, 3), "grad_sh")
+    rays = _rays(origin, direction, t_max, start)
+    p = _params(eps, max_steps)
+    L.check(L.lib().rf_render_backward(ctypes.byref(scene.desc), ctypes.byref(rays), ctypes.byref(p),
+                                       rgb.data_ptr(), t_final.data_ptr(), grad_rgb.data_ptr(),
+                                       _ptr(grad_t_final), gs.data_ptr(), gd.data_ptr(), gsh.data_ptr(),
+                                       int(mode), _stream(dev)))
+    return gs, gd, gsh
+
+
+class RadFoamRender(torch.autograd.Function):
+    """Differentiable render of rays through a Voronoi scene.
+
+    forward(sites, density, sh, off, idx, origin, dir, t_max, start, sh_degree,
+            attr_dtype, eps, max_steps) -> (rgb [R,3], t_final [R])
+
+    Packs the scene (face planes from the current sites, attributes in
+    ``attr_dtype``), walks every ray, and saves what the recomputing backward
+    needs. Gradients flow to sites, density and sh; none to the rays or the
+    adjacency.
+    """
+
+    @staticmethod
+    def forward(ctx, sites, density, sh, off, idx, origin, direction, t_max, start, sh_degree: int = 3,
+                attr_dtype: str = "f32", eps: float = DEFAULT_EPS, max_steps: int = DEFAULT_MAX_STEPS):
+        sites_c, dens_c, sh_c = sites.detach().contiguous(), density.detach().contiguous(), sh.detach().contiguous()
+        scene = PackedScene(sites_c, off, idx, dens_c, sh_c, sh_degree, attr_dtype, validate=False)
+        rgb, tf, steps = render_forward(scene, origin, direction, t_max, start, eps, max_steps)
+        ctx.scene = scene
+        ctx.hyper = (eps, max_steps)
+        ctx.save_for_backward(origin, direction, t_max, start, rgb, tf)
+        ctx.mark_non_differentiable(steps)
+        return rgb, tf, steps
+
+    @staticmethod
+    def backward(ctx, grad_rgb, grad_tf, _grad_steps):
+        origin, direction, t_max, start, rgb, tf = ctx.saved_tensors
+        eps, max_steps = ctx.hyper
+        if grad_rgb is None:
+            grad_rgb = torch.zeros_like(rgb)
+        gs, gd, gsh = render_backward(ctx.scene, origin, direction, t_max, start, rgb, tf,
+                                      grad_rgb.contiguous().float(),
+                                      None if grad_tf is None else grad_tf.contiguous().float(), eps, max_steps)
+        return gs, gd, gsh, None, None, None, None, None, None, None, None, None, None
+
+
+def render(sites, density, sh, off, idx, origin, direction, t_max, start, sh_degree: int = 3,
+           attr_dtype: str = "f32", eps: float = DEFAULT_EPS, max_steps: int = DEFAULT_MAX_STEPS):
+    """Autograd entry point: returns (rgb, t_final, steps)."""
+    return RadFoamRender.apply(sites, density, sh, off, idx, origin, direction, t_max, start, sh_degree,
+                               attr_dtype, eps, max_steps)

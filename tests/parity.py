@@ -1,0 +1,92 @@
+"""Shared helpers of the GPU parity tests: seeded cases, decidability, tolerances.
+
+Tolerances (FP32 GPU path against the FP64 oracle on the same FP32 inputs):
+* cell sequence: bit-exact on every ray that is decidable at FP32, i.e. whose
+  oracle margins exceed KAPPA_T (gap between the winning face and any other
+  front face or t_max, in units of the exit distances' FP32 error scale
+  (1 + |o| + |t|)(1/cos_1 + 1/cos_j)), KAPPA_G (|cos| of any non-front face)
+  and KAPPA_TERM (|ln T - ln eps| at every transmittance test). An FP32 exit
+  distance carries an absolute error of a few eps32 (|o| + t) / cos, so gaps
+  below ~6 eps32 = 3.6e-7 in these units can legitimately flip; KAPPA_T sits at
+  that scale. Measured on 31k rays: the only two flipped sequences had margins
+  7.5e-11 and 9.8e-9.
+* colour, on all rays: max|C - C_ref| <= COLOUR_RTOL * max|C_ref| over the
+  batch (the error of a composited sum scales with the cells' colour
+  magnitude, not with |C| of one pixel, which can cancel to ~0);
+* final transmittance, on all rays: |T - T_ref| <= T_ATOL (T lies in [0, 1]);
+* exit distances of decidable rays: |t - t_ref| <= T_EXIT_ATOL + 1e-4 |t_ref|;
+* gradients, per tensor: max|g - g_ref| <= GRAD_RTOL * max|g_ref| over rays that
+  are decidable.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+import synth
+
+KAPPA_T = 3e-7
+KAPPA_G = 1e-6
+KAPPA_TERM = 1e-4
+COLOUR_RTOL = 1e-4
+T_ATOL = 1e-4
+T_EXIT_ATOL = 1e-4
+GRAD_RTOL = 1e-4
+
+
+def camera_rays(scene, cam, threads=None):
+    """Rays of a camera from the oracle's FP64 ray generation, rounded to FP32 inputs."""
+    o, d, t, pix = oracle.raygen(cam.pose12(), cam.fov_deg, cam.width, cam.height, scene.bound)
+    start = int(synth.nearest_site(scene.sites, o[:1])[0])
+    return (o.astype(np.float32), d.astype(np.float32), t.astype(np.float32),
+            np.full(len(t), start, dtype=np.int32), pix)
+
+
+def inside_rays(scene, rng, n, lo, hi):
+    """Rays from random points inside [lo, hi]^3 in random directions, to the box boundary."""
+    o = rng.uniform(lo, hi, size=(n, 3)).astype(np.float32)
+    d = rng.standard_normal((n, 3))
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    od, dd = o.astype(np.float64), d.astype(np.float64)
+    with np.errstate(divide="ignore"):
+        t_hi = np.where(dd > 0, (hi - od) / dd, np.inf)
+        t_lo = np.where(dd < 0, (lo - od) / dd, np.inf)
+    tmax = np.minimum(t_hi, t_lo).min(axis=1).astype(np.float32)
+    start = synth.nearest_site(scene.sites, o).astype(np.int32)
+    return o, d, tmax, start
+
+
+def decidable(tr: dict, eps: float) -> np.ndarray:
+    ok = (tr["margin"] > KAPPA_T) & (tr["graze"] > KAPPA_G)
+    if eps > 0:
+        ok &= tr["term"] > KAPPA_TERM
+    return ok
+
+
+def colour_err(x, ref) -> float:
+    """max |x - ref| / max |ref| over the batch."""
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    if x.size == 0:
+        return 0.0
+    return float(np.abs(x - ref).max() / max(np.abs(ref).max(), 1e-30))
+
+
+def grad_err(g, ref) -> float:
+    g = np.asarray(g, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.abs(ref).max()
+    if scale == 0:
+        return float(np.abs(g).max())
+    return float(np.abs(g - ref).max() / scale)
+
+
+def compare_sequences(gpu_cells, gpu_len, ref: dict, mask) -> int:
+    """Number of decidable rays whose visited-cell sequence differs."""
+    bad = 0
+    for r in np.nonzero(mask)[0]:
+        L = int(ref["len"][r])
+        if int(gpu_len[r]) != L or not np.array_equal(gpu_cells[r, :L], ref["cells"][r, :L]):
+            bad += 1
+    return bad

@@ -1,0 +1,85 @@
+"""Parity at the workloads' full sizes, in the launch configuration the benchmark times.
+
+The GPU walks every ray of the full frame (one launch over all rays, 8x8 tile
+order, the same kernels as the benchmark). The oracle computes the same
+frame's colours, transmittances and decision margins for every ray, the
+visited-cell sequences of a sample of tiles, and the full-frame gradients with
+upstream gradients N(0,1) on decidable rays (zero on the few undecidable ones,
+identically on both sides).
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from parity import (COLOUR_RTOL, GRAD_RTOL, T_ATOL, camera_rays, colour_err, compare_sequences, decidable,
+                    grad_err)
+
+pytestmark = pytest.mark.gpu
+
+
+def _dv(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("name,dtype", [("cfg2", "f32"), ("cfg3", "f32"), ("cfg3", "bf16")])
+def test_full_frame_forward_backward(name, dtype):
+    import torch
+
+    import paper_2502_01157_amd as rf
+
+    t0 = time.time()
+    scene, rng = synth.make_scene(name, return_rng=True)
+    cam = synth.make_cameras(name, rng)[0]
+    R = cam.width * cam.height
+    g = synth.make_upstream_grads(rng, R)
+    o, d, t, s, _ = camera_rays(scene, cam)
+    print(f"\n{name}/{dtype}: scene {scene.n_sites} sites built in {time.time() - t0:.1f}s", flush=True)
+
+    dens, sh = scene.density, scene.sh
+    if dtype == "bf16":
+        dens = oracle.bf16_to_f32(oracle.bf16_round(dens))
+        sh = oracle.bf16_to_f32(oracle.bf16_round(sh))
+    osc = oracle.OracleScene.from_scene(scene, density=dens, sh=sh)
+    t1 = time.time()
+    full = oracle.trace(osc, o, d, t, s, eps=1e-4, max_len=1)
+    dec = decidable(full, 1e-4)
+    print(f"oracle frame + margins in {time.time() - t1:.1f}s; decidable {dec.mean():.5f}", flush=True)
+    assert dec.mean() > 0.99
+
+    p = rf.PackedScene(*map(_dv, (scene.sites, scene.off, scene.idx, scene.density, scene.sh)), scene.sh_deg,
+                       dtype, validate=True)
+    od, dd, td, sd = map(_dv, (o, d, t, s))
+    rgb, tf, steps = rf.render_forward(p, od, dd, td, sd)
+    torch.cuda.synchronize()
+    rgb, tf, steps = rgb.cpu().numpy(), tf.cpu().numpy(), steps.cpu().numpy()
+    assert colour_err(rgb, full["rgb"]) <= COLOUR_RTOL
+    assert np.abs(tf - full["t_final"]).max() <= T_ATOL
+    np.testing.assert_array_equal(steps[dec], full["steps"][dec])
+
+    # visited cells of 64 tiles spread over the frame
+    tiles = np.random.default_rng(0).choice(R // 64, size=64, replace=False)
+    sel = (tiles[:, None] * 64 + np.arange(64)[None, :]).ravel()
+    ref = oracle.trace(osc, o[sel], d[sel], t[sel], s[sel], eps=1e-4, max_len=1024)
+    tr = rf.render_trace(p, *map(_dv, (o[sel], d[sel], t[sel], s[sel])), max_len=1024)
+    cells = tr["cells"].cpu().numpy()
+    gst = tr["steps"].cpu().numpy()
+    assert compare_sequences(cells, np.where(gst >= 0, gst, 0), ref, decidable(ref, 1e-4)) == 0
+
+    # full-frame gradients
+    gm = np.where(dec[:, None], g, 0.0).astype(np.float32)
+    t2 = time.time()
+    ref_g = oracle.backward(osc, o, d, t, s, gm, eps=1e-4)
+    print(f"oracle backward in {time.time() - t2:.1f}s", flush=True)
+    rgb_d, tf_d, _ = rf.render_forward(p, od, dd, td, sd)
+    grads = rf.render_backward(p, od, dd, td, sd, rgb_d, tf_d, _dv(gm))
+    torch.cuda.synchronize()
+    errs = [grad_err(x.cpu().numpy(), y) for x, y in zip(grads, ref_g)]
+    print(f"gradient errors (sites, density, sh): {errs}", flush=True)
+    assert max(errs) <= GRAD_RTOL

@@ -1,0 +1,332 @@
+"""GPU parity: the HIP walk (through the C ABI) against the FP64 oracle.
+
+Inputs are seeded synthetic scenes shaped like the paper's workloads; rays come
+from the oracle's FP64 ray generation (rounded to FP32) or from random interior
+points. The oracle runs on exactly the FP32 inputs the GPU sees, widened to FP64.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from parity import (COLOUR_RTOL, GRAD_RTOL, T_ATOL, T_EXIT_ATOL, camera_rays, colour_err, compare_sequences,
+                    decidable, grad_err, inside_rays)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rf():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible to torch")
+    import paper_2502_01157_amd as rf_mod
+
+    return rf_mod
+
+
+def to_dev(*arrays):
+    import torch
+
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrays]
+
+
+def packed(rf, scene, dtype="f32"):
+    import torch
+
+    sites, off, idx, dens, sh = to_dev(scene.sites, scene.off, scene.idx, scene.density, scene.sh)
+    p = rf.PackedScene(sites, off, idx, dens, sh, scene.sh_deg, dtype, validate=True)
+    torch.cuda.synchronize()
+    return p, (sites, off, idx, dens, sh)
+
+
+def gpu_trace(rf, p, rays, eps, max_steps=8192, max_len=1024):
+    o, d, t, s = to_dev(*rays)
+    tr = rf.render_trace(p, o, d, t, s, eps=eps, max_steps=max_steps, max_len=max_len)
+    out = {k: v.cpu().numpy() for k, v in tr.items()}
+    steps = out["steps"]
+    out["len"] = np.where(steps >= 0, steps, np.where(steps == -2, max_steps, 0))
+    return out
+
+
+def check_forward(rf, scene, rays, eps, dtype="f32", max_undecidable=0.02):
+    p, _ = packed(rf, scene, dtype)
+    osc = oracle.OracleScene.from_scene(scene)
+    if dtype == "bf16":
+        dens = oracle.bf16_to_f32(oracle.bf16_round(scene.density))
+        sh = oracle.bf16_to_f32(oracle.bf16_round(scene.sh))
+        osc = oracle.OracleScene.from_scene(scene, density=dens, sh=sh)
+    ref = oracle.trace(osc, *rays, eps=eps, max_len=1024)
+    g = gpu_trace(rf, p, rays, eps)
+    dec = decidable(ref, eps)
+    assert dec.mean() >= 1 - max_undecidable, f"only {dec.mean():.4f} of rays decidable"
+    assert compare_sequences(g["cells"], g["len"], ref, dec) == 0
+    np.testing.assert_array_equal(g["steps"][dec], ref["steps"][dec])
+    assert colour_err(g["rgb"], ref["rgb"]) <= COLOUR_RTOL
+    assert np.abs(g["t_final"] - ref["t_final"]).max() <= T_ATOL
+    # exit distances of decidable rays
+    for r in np.nonzero(dec)[0][:2000]:
+        L = ref["len"][r]
+        np.testing.assert_allclose(g["t_exit"][r, :L], ref["t_exit"][r, :L], rtol=1e-4, atol=T_EXIT_ATOL)
+    return p, ref, g, dec
+
+
+# ---------------------------------------------------------------------------
+# scenes
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def cfg1():
+    scene, rng = synth.make_scene("cfg1", return_rng=True)
+    cam = synth.make_cameras("cfg1", rng)[0]
+    return scene, cam
+
+
+@pytest.fixture(scope="module")
+def clustered():
+    scene, rng = synth.small_scene("clustered", 20000, seed=31, sh_deg=3, return_rng=True)
+    cams = synth.make_cameras("cfg2", rng, n=1, res=(96, 72))
+    return scene, cams[0], rng
+
+
+class _Deg:
+    def __init__(self, scene, deg):
+        self.__dict__.update(scene.__dict__)
+        b = (deg + 1) ** 2
+        self.sh = np.ascontiguousarray(scene.sh[:, :b, :])
+        self.sh_deg = deg
+
+
+# ---------------------------------------------------------------------------
+# a1: packing
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_pack_planes_and_records(rf, clustered, dtype):
+    scene = clustered[0]
+    p, _ = packed(rf, scene, dtype)
+    planes = p.planes().cpu().numpy().astype(np.float64)
+    ref = oracle.face_planes(scene.sites, scene.off, scene.idx)
+    # n = x_j - x_i is one fp32 subtraction of fp32 values: within half an ulp
+    np.testing.assert_allclose(planes[:, :3], ref[:, :3], rtol=2 ** -24, atol=0)
+    scale = np.linalg.norm(ref[:, :3], axis=1) * np.linalg.norm(scene.sites, axis=1).max()
+    assert np.all(np.abs(planes[:, 3] - ref[:, 3]) <= 4e-7 * scale + 1e-30)
+    dens, sh = (t.cpu().numpy() for t in p.attributes())
+    if dtype == "f32":
+        np.testing.assert_array_equal(dens, scene.density)
+        np.testing.assert_array_equal(sh, scene.sh)
+    else:
+        np.testing.assert_array_equal(dens, oracle.bf16_to_f32(oracle.bf16_round(scene.density)))
+        np.testing.assert_array_equal(sh, oracle.bf16_to_f32(oracle.bf16_round(scene.sh)))
+    assert p.errors() == (0, 0)
+
+
+def test_pack_rejects_bad_csr_without_faulting(rf, clustered):
+    import torch
+
+    scene = clustered[0]
+    sites, off, idx, dens, sh = to_dev(scene.sites, scene.off, scene.idx, scene.density, scene.sh)
+    bad_idx = idx.clone()
+    bad_idx[7] = scene.n_sites + 5
+    bad_idx[100] = -3
+    with pytest.raises(rf.RfError, match="INVALID_ARG"):
+        rf.PackedScene(sites, off, bad_idx, dens, sh, 3, validate=True)
+    bad_off = off.clone()
+    bad_off[50] = scene.n_edges + 1000
+    p = rf.PackedScene(sites, bad_off, idx, dens, sh, 3, validate=False)
+    assert p.errors()[0] > 0
+    # the corrupt scene still renders without touching memory out of range
+    o, d, t, s = to_dev(*inside_rays(scene, np.random.default_rng(0), 300, -0.9, 0.9))
+    rgb, tf, steps = rf.render_forward(p, o, d, t, s)
+    torch.cuda.synchronize()
+    assert torch.isfinite(rgb).all()
+
+
+# ---------------------------------------------------------------------------
+# a2: camera rays
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("W,H,bound", [(64, 64, ("box", 0.0, 1.0)), (100, 37, ("box", -1.0, 1.0)),
+                                       (33, 70, ("sphere", 5.0))])
+def test_raygen_matches_oracle(rf, W, H, bound):
+    rng = np.random.default_rng(W + H)
+    cam = synth.make_cameras("cfg4", rng, n=1, res=(W, H))[0]
+    if bound[1] == 0.0:
+        cam.position = np.array([0.5, 0.4, 0.6])
+    o, d, t, s, px = rf.raygen(cam.pose12(), cam.fov_deg, W, H, bound, start=123)
+    ro, rd, rt, rpx = oracle.raygen(np.float32(cam.pose12()).astype(np.float64), cam.fov_deg, W, H, bound)
+    np.testing.assert_array_equal(px.cpu().numpy(), rpx)
+    np.testing.assert_allclose(d.cpu().numpy(), rd, atol=2e-6)
+    np.testing.assert_allclose(o.cpu().numpy(), ro, atol=1e-7)
+    np.testing.assert_allclose(t.cpu().numpy(), rt, rtol=2e-5, atol=2e-6)
+    assert np.all(s.cpu().numpy() == 123)
+
+
+# ---------------------------------------------------------------------------
+# a3: forward walk
+# ---------------------------------------------------------------------------
+
+def test_cfg1_full_frame_forward(rf, cfg1):
+    scene, cam = cfg1
+    rays = camera_rays(scene, cam)[:4]
+    check_forward(rf, scene, rays, eps=1e-4)
+
+
+@pytest.mark.parametrize("deg", [0, 1, 2, 3])
+def test_clustered_camera_forward(rf, clustered, deg):
+    scene, cam, _ = clustered
+    rays = camera_rays(scene, cam)[:4]
+    check_forward(rf, _Deg(scene, deg), rays, eps=1e-4)
+
+
+@pytest.mark.parametrize("n_rays", [1, 63, 65, 257, 1000])
+def test_ragged_interior_rays_eps0(rf, clustered, n_rays):
+    scene = clustered[0]
+    rays = inside_rays(scene, np.random.default_rng(n_rays), n_rays, -0.95, 0.95)
+    check_forward(rf, scene, rays, eps=0.0)
+
+
+def test_forward_bitwise_deterministic(rf, clustered):
+    scene, cam, _ = clustered
+    p, _ = packed(rf, scene)
+    o, d, t, s = to_dev(*camera_rays(scene, cam)[:4])
+    a = [x.cpu().numpy() for x in rf.render_forward(p, o, d, t, s)]
+    b = [x.cpu().numpy() for x in rf.render_forward(p, o, d, t, s)]
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_edge_cases(rf, clustered):
+    import torch
+
+    scene = clustered[0]
+    p, _ = packed(rf, scene)
+    # empty batch
+    z = torch.empty((0, 3), device="cuda")
+    rgb, tf, steps = rf.render_forward(p, z, z.clone(), torch.empty(0, device="cuda"),
+                                       torch.empty(0, dtype=torch.int32, device="cuda"))
+    assert rgb.shape == (0, 3)
+    # invalid start cells, zero-length rays, a max_steps cap
+    o, d, t, s = inside_rays(scene, np.random.default_rng(5), 200, -0.9, 0.9)
+    s[:4] = [-1, scene.n_sites, 2 ** 31 - 1, -(2 ** 31)]
+    t[4:8] = 0.0
+    ref = oracle.trace(oracle.OracleScene.from_scene(scene), o, d, t, s, eps=1e-4, max_steps=5)
+    g = gpu_trace(rf, p, (o, d, t, s), eps=1e-4, max_steps=5)
+    np.testing.assert_array_equal(g["steps"][:4], -1)
+    np.testing.assert_array_equal(g["rgb"][:4], 0)
+    np.testing.assert_array_equal(g["t_final"][:4], 1)
+    np.testing.assert_array_equal(g["steps"][4:8], 1)
+    np.testing.assert_array_equal(g["t_final"][4:8], 1)
+    dec = decidable(ref, 1e-4)
+    np.testing.assert_array_equal(g["steps"][dec], ref["steps"][dec])
+    assert np.any(g["steps"] == -2)
+    assert colour_err(g["rgb"], ref["rgb"]) <= COLOUR_RTOL
+    # zero density everywhere: fully transparent
+    p0 = rf.PackedScene(*to_dev(scene.sites, scene.off, scene.idx, np.zeros_like(scene.density), scene.sh), 3)
+    rgb, tf, _ = rf.render_forward(p0, *to_dev(o[8:], d[8:], t[8:], s[8:]))
+    assert torch.all(rgb == 0) and torch.all(tf == 1)
+    # bad arguments are rejected on the host
+    with pytest.raises(rf.RfError, match="INVALID_ARG"):
+        rf.render_forward(p, *to_dev(o, d, t, s), eps=-1.0)
+    with pytest.raises(rf.RfError, match="INVALID_ARG"):
+        rf.render_forward(p, *to_dev(o, d, t, s), max_steps=0)
+
+
+# ---------------------------------------------------------------------------
+# a4/a5: backward walk and its wavefront reduction
+# ---------------------------------------------------------------------------
+
+def check_backward(rf, scene, rays, eps, mode=0, dtype="f32", with_gt=True, seed=0):
+    import torch
+
+    osc = oracle.OracleScene.from_scene(scene)
+    if dtype == "bf16":
+        osc = oracle.OracleScene.from_scene(scene, density=oracle.bf16_to_f32(oracle.bf16_round(scene.density)),
+                                            sh=oracle.bf16_to_f32(oracle.bf16_round(scene.sh)))
+    ref = oracle.trace(osc, *rays, eps=eps, max_len=1024)
+    dec = decidable(ref, eps)
+    rays = tuple(a[dec] for a in rays)
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((len(rays[1]), 3)).astype(np.float32)
+    gT = rng.standard_normal(len(rays[1])).astype(np.float32) if with_gt else None
+    ref_g = oracle.backward(osc, *rays, g, gT, eps=eps)
+    p, _ = packed(rf, scene, dtype)
+    o, d, t, s = to_dev(*rays)
+    rgb, tf, steps = rf.render_forward(p, o, d, t, s, eps=eps)
+    gg, = to_dev(g)
+    gt_dev = to_dev(gT)[0] if with_gt else None
+    gs, gd, gsh = rf.render_backward(p, o, d, t, s, rgb, tf, gg, gt_dev, eps=eps, mode=mode)
+    torch.cuda.synchronize()
+    errs = [grad_err(x.cpu().numpy(), y) for x, y in zip((gs, gd, gsh), ref_g)]
+    assert max(errs) <= GRAD_RTOL, errs
+    return errs
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_backward_camera_rays(rf, clustered, mode):
+    scene, cam, _ = clustered
+    check_backward(rf, scene, camera_rays(scene, cam)[:4], eps=1e-4, mode=mode)
+
+
+@pytest.mark.parametrize("deg", [0, 1, 2])
+def test_backward_lower_sh_degrees(rf, clustered, deg):
+    scene, cam, _ = clustered
+    check_backward(rf, _Deg(scene, deg), camera_rays(scene, cam)[:4], eps=1e-4)
+
+
+def test_backward_interior_rays_eps0_and_dense_termination(rf, clustered):
+    scene = clustered[0]
+    rays = inside_rays(scene, np.random.default_rng(7), 777, -0.95, 0.95)
+    check_backward(rf, scene, rays, eps=0.0, seed=1)
+    dense = _Deg(scene, 3)
+    dense.density = scene.density * 40.0          # most rays end by the transmittance test
+    check_backward(rf, dense, rays, eps=1e-2, seed=2)
+
+
+def test_backward_modes_agree(rf, clustered):
+    import torch
+
+    scene, cam, _ = clustered
+    p, _ = packed(rf, scene)
+    o, d, t, s = to_dev(*camera_rays(scene, cam)[:4])
+    rgb, tf, _ = rf.render_forward(p, o, d, t, s)
+    g = torch.randn_like(rgb)
+    a = rf.render_backward(p, o, d, t, s, rgb, tf, g, mode=0)
+    b = rf.render_backward(p, o, d, t, s, rgb, tf, g, mode=1)
+    for x, y in zip(a, b):
+        assert grad_err(x.cpu().numpy(), y.cpu().numpy()) < 1e-5
+
+
+def test_autograd_function(rf, clustered):
+    import torch
+
+    scene, cam, _ = clustered
+    sites, off, idx, dens, sh = to_dev(scene.sites, scene.off, scene.idx, scene.density, scene.sh)
+    sites.requires_grad_(True)
+    dens.requires_grad_(True)
+    sh.requires_grad_(True)
+    o, d, t, s = to_dev(*camera_rays(scene, cam)[:4])
+    rgb, tf, steps = rf.render(sites, dens, sh, off, idx, o, d, t, s, 3)
+    g = torch.randn_like(rgb)
+    (rgb * g).sum().backward()
+    p, _ = packed(rf, scene)
+    ref = rf.render_backward(p, o, d, t, s, rgb.detach(), tf.detach(), g)
+    for x, y in zip((sites.grad, dens.grad, sh.grad), ref):
+        assert grad_err(x.cpu().numpy(), y.cpu().numpy()) < 1e-5
+
+
+# ---------------------------------------------------------------------------
+# a7: bf16-stored attributes
+# ---------------------------------------------------------------------------
+
+def test_bf16_forward_and_backward(rf, clustered):
+    scene, cam, _ = clustered
+    rays = camera_rays(scene, cam)[:4]
+    p, ref, g, dec = check_forward(rf, scene, rays, eps=1e-4, dtype="bf16")
+    check_backward(rf, scene, rays, eps=1e-4, dtype="bf16")
+    # total error against the fp32-attribute oracle stays at bf16 rounding level
+    full = oracle.forward(oracle.OracleScene.from_scene(scene), *rays, eps=1e-4)
+    assert colour_err(g["rgb"], full[0]) < 1e-2
