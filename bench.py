@@ -61,6 +61,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", type=int, default=0, help="backward reduction mode (0 wave-reduced, 1 per-lane)")
+    ap.add_argument("--only", choices=["f32", "bf16"], default=None, help="time one attribute precision only")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -169,15 +172,26 @@ def main() -> int:
     log(f"visits/frame {visits} ({visits / R:.1f} per ray), mean visited degree {mean_deg:.2f}, "
         f"flagged rays {(steps_np < 0).sum()}")
 
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written by one device copy kernel")
+        del src, dst
+
     results = {}
-    for dt in ("f32", "bf16"):
+    for dt in (("f32", "bf16") if args.only is None else (args.only,)):
         for bwd in (True, False):
             ms, kern, lat = run(dt, bwd)
             results[(dt, bwd)] = (ms, kern, lat)
             log(f"{dt} {'fwd+bwd' if bwd else 'fwd'}: {ms:.3f} ms/step, {R / ms / 1e3:.1f} Mrays/s, "
                 f"kernels(ms) {json.dumps({k: round(v, 4) for k, v in kern.items()})}")
 
-    ms, kern, lat = results[("f32", True)]
+    main_dt = "f32" if args.only is None else args.only
+    dts = [k[0] for k in results if k[1]]
+    ms, kern, lat = results[(main_dt, True)]
     value = R / (ms * 1e-3) / 1e6
     dominant = max(("forward", "backward"), key=lambda k: kern[k])
     fl = flops_per_visit(mean_deg, B, dominant == "backward") * visits
@@ -201,16 +215,17 @@ def main() -> int:
                                f"{W}x{H} camera, raygen+pack+forward+backward",
                    "rays_per_step": R, "visits_per_step": visits, "mean_visited_degree": round(mean_deg, 3),
                    "parallelism": "single GPU"},
-        "fwd_mrays_s": {dt: round(R / results[(dt, False)][0] / 1e3, 3) for dt in ("f32", "bf16")},
-        "fwd_bwd_mrays_s": {dt: round(R / results[(dt, True)][0] / 1e3, 3) for dt in ("f32", "bf16")},
-        "bf16_speedup_fwd_bwd": round(results[("f32", True)][0] / results[("bf16", True)][0], 4),
+        "fwd_mrays_s": {dt: round(R / results[(dt, False)][0] / 1e3, 3) for dt in dts},
+        "fwd_bwd_mrays_s": {dt: round(R / results[(dt, True)][0] / 1e3, 3) for dt in dts},
+        "bf16_speedup_fwd_bwd": (round(results[("f32", True)][0] / results[("bf16", True)][0], 4)
+                                 if len(dts) == 2 else None),
         "step_latency_ms": {f"{dt}_{'fwd_bwd' if b else 'fwd'}": {
             "p50": round(float(np.percentile(results[(dt, b)][2], 50)), 4),
-            "p99": round(float(np.percentile(results[(dt, b)][2], 99)), 4)} for dt in ("f32", "bf16")
+            "p99": round(float(np.percentile(results[(dt, b)][2], 99)), 4)} for dt in dts
             for b in (True, False)},
         "kernel_ms": {f"{dt}_{'fwd_bwd' if b else 'fwd'}": {k: round(v, 4) for k, v in results[(dt, b)][1].items()}
-                      for dt in ("f32", "bf16") for b in (True, False)},
-        "roofline": {"bound": "alu", "kernel": f"{dominant} walk (fp32 attributes)",
+                      for dt in dts for b in (True, False)},
+        "roofline": {"bound": "alu", "kernel": f"{dominant} walk ({main_dt} attributes)",
                      "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s",
                      "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None},
     }

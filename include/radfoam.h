@@ -237,6 +237,49 @@ rf_status rf_packed_planes(const rf_packed_scene *scene, float *planes, void *st
  * density[n_sites], sh[n_sites][B][3]; for tests of the packing step. */
 rf_status rf_packed_attributes(const rf_packed_scene *scene, float *density, float *sh, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Continuous-batching render server (forward only).
+ *
+ * One persistent kernel, launched by rf_server_create on its own stream and
+ * sized to fill the GPU, renders 8x8 screen tiles of every admitted request;
+ * tiles of requests that arrive while others are on the GPU are interleaved
+ * with theirs. The packed scene stays resident (the caller keeps it alive and
+ * unmodified until rf_server_destroy returns). Results land in a pinned host
+ * output pool owned by the server: per pixel, in image row-major order, RGBA
+ * floats = (r, g, b, final transmittance). Every pixel is computed by the same
+ * ray generation and walk as rf_raygen + rf_render_forward, so a request's
+ * image does not depend on what else is in flight.
+ *
+ * Admission (rf_server_submit) is immediate or RF_ERR_BUSY: a request is
+ * admitted when an in-flight slot is free (at most max_inflight <= 64) and
+ * its W*H*16 bytes fit contiguously in the pool (pool_bytes). Callers that
+ * need FIFO order keep their own queue and retry its head.
+ * rf_server_poll lists finished requests not yet collected;
+ * rf_server_result copies one to `rgba` (host memory, >= W*H*16 bytes; NULL
+ * discards it) and frees its slot and pool range.
+ * rf_server_destroy waits (up to 10 s) for admitted requests, stops every
+ * wave of the kernel and frees the server. The kernel also stops by itself
+ * when the host's heartbeat (a thread of the server) is not seen for 5 s;
+ * later submits then fail with RF_ERR_HIP. Calls on one server may come from
+ * several host threads (they serialise on an internal lock).
+ * ---------------------------------------------------------------------- */
+typedef struct rf_server rf_server;
+
+typedef struct {
+    int64_t submitted, completed, rejected_busy, rays_done;
+    int64_t pool_used_bytes, pool_bytes;
+    int32_t inflight, workgroups;
+} rf_server_stats;
+
+rf_status rf_server_create(const rf_packed_scene *scene, const rf_params *params, const rf_bound *bound,
+                           size_t pool_bytes, int32_t max_inflight, int32_t workgroups /* 0: fill the GPU */,
+                           rf_server **out);
+rf_status rf_server_submit(rf_server *server, const rf_camera *camera, int32_t start_cell, uint64_t *req_id);
+rf_status rf_server_poll(rf_server *server, uint64_t *done_ids, int32_t cap, int32_t *n_done);
+rf_status rf_server_result(rf_server *server, uint64_t req_id, float *rgba, size_t bytes);
+rf_status rf_server_stats_get(rf_server *server, rf_server_stats *stats);
+rf_status rf_server_destroy(rf_server *server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,12 +22,7 @@ RF_RAY_BAD_START = -1
 RF_RAY_MAX_STEPS = -2
 STATUS_NAMES = {0: "RF_OK", 1: "RF_ERR_INVALID_ARG", 2: "RF_ERR_HIP", 3: "RF_ERR_OOM",
                 4: "RF_ERR_UNSUPPORTED", 5: "RF_ERR_BUSY"}
-
-#: every entry point declared in include/radfoam.h
-EXPORTED = ["rf_last_error", "rf_version", "rf_packed_bytes", "rf_pack_scene", "rf_packed_errors", "rf_raygen",
-            "rf_render_forward", "rf_render_backward", "rf_render_trace", "rf_packed_planes",
-            "rf_packed_attributes", "rf_server_create", "rf_server_submit", "rf_server_poll",
-            "rf_server_result", "rf_server_stats", "rf_server_destroy"]
+RF_ERR_BUSY = 5
 
 
 class RfError(RuntimeError):
@@ -70,8 +65,8 @@ class BoundDesc(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected_busy", ctypes.c_int64),
-                ("tiles_done", ctypes.c_int64), ("rays_done", ctypes.c_int64), ("inflight", ctypes.c_int32),
-                ("pool_used_bytes", ctypes.c_int64), ("pool_bytes", ctypes.c_int64)]
+                ("rays_done", ctypes.c_int64), ("pool_used_bytes", ctypes.c_int64), ("pool_bytes", ctypes.c_int64),
+                ("inflight", ctypes.c_int32), ("workgroups", ctypes.c_int32)]
 
 
 _lib: Optional[ctypes.CDLL] = None
@@ -107,20 +102,18 @@ def lib() -> ctypes.CDLL:
         for name in ("rf_packed_bytes", "rf_pack_scene", "rf_packed_errors", "rf_raygen", "rf_render_forward",
                      "rf_render_trace", "rf_render_backward", "rf_packed_planes", "rf_packed_attributes"):
             getattr(L, name).restype = st
-        if hasattr(L, "rf_server_create"):
-            L.rf_server_create.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Params),
-                                           ctypes.POINTER(BoundDesc), ctypes.c_size_t, ctypes.c_int32,
-                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]
-            L.rf_server_submit.argtypes = [P, ctypes.POINTER(CameraDesc), ctypes.c_int32,
-                                           ctypes.POINTER(ctypes.c_uint64)]
-            L.rf_server_poll.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32,
-                                         ctypes.POINTER(ctypes.c_int32)]
-            L.rf_server_result.argtypes = [P, ctypes.c_uint64, P, ctypes.c_size_t]
-            L.rf_server_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
-            L.rf_server_destroy.argtypes = [P]
-            for name in ("rf_server_create", "rf_server_submit", "rf_server_poll", "rf_server_result",
-                         "rf_server_stats", "rf_server_destroy"):
-                getattr(L, name).restype = st
+        L.rf_server_create.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Params),
+                                       ctypes.POINTER(BoundDesc), ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_void_p)]
+        L.rf_server_submit.argtypes = [P, ctypes.POINTER(CameraDesc), ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
+        L.rf_server_poll.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_int32)]
+        L.rf_server_result.argtypes = [P, ctypes.c_uint64, P, ctypes.c_size_t]
+        L.rf_server_stats_get.argtypes = [P, ctypes.POINTER(ServerStats)]
+        L.rf_server_destroy.argtypes = [P]
+        for name in ("rf_server_create", "rf_server_submit", "rf_server_poll", "rf_server_result",
+                     "rf_server_stats_get", "rf_server_destroy"):
+            getattr(L, name).restype = st
         _lib = L
     return _lib
 

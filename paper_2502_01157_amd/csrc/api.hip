@@ -124,6 +124,11 @@ rf::WalkArgs walk_args(const rf_packed_scene* s, const rf_rays* r, const rf_para
 
 }  // namespace
 
+void rf::set_error(const char* msg)
+{
+    snprintf(g_err, sizeof g_err, "%s", msg);
+}
+
 extern "C" {
 
 const char* rf_last_error(void) { return g_err; }

@@ -1,8 +1,11 @@
 // Scene packing (face planes, neighbour rows, per-cell records) and camera
 // ray generation for gfx950.
 
+#include <limits.h>
+
 #include "rf_device.hpp"
 #include "rf_kernels.hpp"
+#include "rf_walk.hpp"
 
 namespace rf {
 
@@ -35,11 +38,9 @@ __global__ void k_zero_err(int32_t* err)
     if (threadIdx.x < 2) err[threadIdx.x] = 0;
 }
 
-// One thread per cell: its row reference and its record.
-template <int DEG, bool BF16>
-__global__ __launch_bounds__(256) void k_pack_cells(PackArgs a)
+// One thread per cell: its row reference and the CSR checks.
+__global__ __launch_bounds__(256) void k_pack_rows(PackArgs a)
 {
-    using R = Rec<DEG, BF16>;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n_sites) return;
     int beg, deg;
@@ -49,59 +50,95 @@ __global__ __launch_bounds__(256) void k_pack_cells(PackArgs a)
     if (i == 0 && a.off[0] != 0) atomicAdd(&a.err[0], 1);
     if (i == a.n_sites - 1 && a.off[a.n_sites] != a.n_edges) atomicAdd(&a.err[0], 1);
     a.row[i] = make_uint2((uint32_t)i | ((uint32_t)deg << 24), (uint32_t)beg);
-
-    uint32_t w[4 * R::CHUNKS];
-#pragma unroll
-    for (int k = 0; k < 4 * R::CHUNKS; ++k) w[k] = 0u;
-    const float* sh = a.sh + i * R::NSH;
-    if constexpr (BF16) {
-#pragma unroll
-        for (int k = 0; k <= R::NSH; ++k) {
-            const float v = k < R::NSH ? sh[k] : a.density[i];
-            w[k >> 1] |= f32_to_bf16_rne(v) << ((k & 1) * 16);
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < R::NSH; ++k) w[k] = __float_as_uint(sh[k]);
-        w[R::NSH] = __float_as_uint(a.density[i]);
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) w[R::SITE_OFF / 4 + k] = __float_as_uint(a.sites[3 * i + k]);
-    uint4* dst = reinterpret_cast<uint4*>(a.rec + i * R::BYTES);
-#pragma unroll
-    for (int c = 0; c < R::CHUNKS; ++c) dst[c] = make_uint4(w[4 * c], w[4 * c + 1], w[4 * c + 2], w[4 * c + 3]);
 }
 
-// One thread per cell: the planes and neighbour rows of its directed edges.
+// One thread per 16-byte chunk of a cell record, so that consecutive threads
+// write consecutive chunks and read consecutive SH values.
+template <int DEG, bool BF16>
+__global__ __launch_bounds__(256) void k_pack_records(PackArgs a)
+{
+    using R = Rec<DEG, BF16>;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / R::CHUNKS;
+    const int c = (int)(t - i * R::CHUNKS);
+    if (i >= a.n_sites) return;
+    const float* sh = a.sh + i * R::NSH;
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        // byte offset of word q of this chunk inside the record
+        const int byte = 16 * c + 4 * q;
+        uint32_t v = 0u;
+        if (byte >= R::SITE_OFF && byte < R::SITE_OFF + 12) {
+            v = __float_as_uint(a.sites[3 * i + (byte - R::SITE_OFF) / 4]);
+        } else if constexpr (BF16) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int k = byte / 2 + h;  // bf16 element index
+                if (k < R::NSH) v |= f32_to_bf16_rne(sh[k]) << (16 * h);
+                else if (k == R::NSH) v |= f32_to_bf16_rne(a.density[i]) << (16 * h);
+            }
+        } else {
+            const int k = byte / 4;
+            if (k < R::NSH) v = __float_as_uint(sh[k]);
+            else if (k == R::NSH) v = __float_as_uint(a.density[i]);
+        }
+        w[q] = v;
+    }
+    reinterpret_cast<uint4*>(a.rec + i * R::BYTES)[c] = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// One wavefront per 64 consecutive cells; its lanes stride over the cells'
+// directed edges (contiguous in the CSR), so idx reads and plane/adj writes
+// are coalesced. Each lane finds its edge's owner among the 64 row offsets
+// by binary search over the wave's registers.
 // n = x_j - x_i and c = n . ((x_i + x_j) / 2) are evaluated with the same
 // instruction sequence for (i, j) and (j, i), so the two planes of a face are
 // exact negations of each other.
 __global__ __launch_bounds__(256) void k_pack_faces(PackArgs a)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n_sites) return;
-    int beg, deg;
-    bool too_long;
-    const bool ok = checked_row(a.off, i, a.n_edges, &beg, &deg, &too_long);
-    if (!ok) return;
-    const uint2 self = make_uint2((uint32_t)i | ((uint32_t)deg << 24), (uint32_t)beg);
-    const float xi = a.sites[3 * i], yi = a.sites[3 * i + 1], zi = a.sites[3 * i + 2];
-    for (int k = beg; k < beg + deg; ++k) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t c0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave * kWave;
+    if (c0 >= a.n_sites) return;
+    const int64_t mine = c0 + lane;
+    int beg = 0, deg = 0;
+    bool too_long = false;
+    if (mine < a.n_sites) checked_row(a.off, mine, a.n_edges, &beg, &deg, &too_long);
+    // the wave's edge range: from the first valid row start to the last valid row end
+    const int end = beg + deg;
+    int lo_e = mine < a.n_sites ? beg : INT_MAX, hi_e = mine < a.n_sites ? end : 0;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        lo_e = min(lo_e, __shfl_xor(lo_e, m));
+        hi_e = max(hi_e, __shfl_xor(hi_e, m));
+    }
+    for (int64_t base = lo_e; base < hi_e; base += kWave) {
+        const int64_t k = base + lane;
+        // owner: the lane q whose row [beg_q, beg_q + deg_q) contains k
+        int owner = -1;
+        for (int q = 0; q < kWave; ++q) {
+            const int bq = __shfl(beg, q), dq = __shfl(deg, q);
+            if (k >= bq && k < bq + dq) owner = q;
+        }
+        if (k >= hi_e || owner < 0) continue;
+        const int64_t i = c0 + owner;
+        const float xi = a.sites[3 * i], yi = a.sites[3 * i + 1], zi = a.sites[3 * i + 2];
         const int64_t j = a.idx[k];
         int jb = 0, jd = 0;
         bool jl;
         const bool valid = j >= 0 && j < a.n_sites && j != i && checked_row(a.off, j, a.n_edges, &jb, &jd, &jl);
         if (!valid) {
             if (!(j >= 0 && j < a.n_sites && j != i)) atomicAdd(&a.err[0], 1);
+            const int ib = __shfl(beg, owner), id = __shfl(deg, owner);
             a.planes[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);  // den = 0: never a front face
-            a.adj[k] = self;
+            a.adj[k] = make_uint2((uint32_t)i | ((uint32_t)id << 24), (uint32_t)ib);
             continue;
         }
         const float xj = a.sites[3 * j], yj = a.sites[3 * j + 1], zj = a.sites[3 * j + 2];
         const float nx = xj - xi, ny = yj - yi, nz = zj - zi;
         const float mx = (xi + xj) * 0.5f, my = (yi + yj) * 0.5f, mz = (zi + zj) * 0.5f;
-        const float c = fmaf(nz, mz, fmaf(ny, my, nx * mx));
-        a.planes[k] = make_float4(nx, ny, nz, c);
+        const float cc = fmaf(nz, mz, fmaf(ny, my, nx * mx));
+        a.planes[k] = make_float4(nx, ny, nz, cc);
         a.adj[k] = make_uint2((uint32_t)j | ((uint32_t)jd << 24), (uint32_t)jb);
     }
 }
@@ -109,9 +146,12 @@ __global__ __launch_bounds__(256) void k_pack_faces(PackArgs a)
 template <int DEG, bool BF16>
 static hipError_t launch_pack_t(const PackArgs& a, hipStream_t stream)
 {
+    using R = Rec<DEG, BF16>;
     hipLaunchKernelGGL(k_zero_err, dim3(1), dim3(64), 0, stream, a.err);
     const unsigned blocks = (unsigned)((a.n_sites + 255) / 256);
-    hipLaunchKernelGGL((k_pack_cells<DEG, BF16>), dim3(blocks), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_pack_rows, dim3(blocks), dim3(256), 0, stream, a);
+    const unsigned rblocks = (unsigned)((a.n_sites * R::CHUNKS + 255) / 256);
+    hipLaunchKernelGGL((k_pack_records<DEG, BF16>), dim3(rblocks), dim3(256), 0, stream, a);
     hipLaunchKernelGGL(k_pack_faces, dim3(blocks), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
@@ -209,30 +249,8 @@ __global__ __launch_bounds__(256) void k_raygen(RaygenArgs g)
     if (r >= R) return;
     int px, py;
     tile_pixel(r, g.width, g.height, &px, &py);
-    const float u = ((float)px + 0.5f - 0.5f * (float)g.width) / g.focal;
-    const float v = ((float)py + 0.5f - 0.5f * (float)g.height) / g.focal;
-    float d[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) d[k] = fmaf(g.rot[3 * k], u, fmaf(g.rot[3 * k + 1], v, g.rot[3 * k + 2]));
-    const float inv = 1.0f / sqrtf(fmaf(d[0], d[0], fmaf(d[1], d[1], d[2] * d[2])));
-    d[0] *= inv;
-    d[1] *= inv;
-    d[2] *= inv;
-    float t;
-    if (g.bound_kind == 0) {
-        t = INFINITY;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            if (d[k] > 0.0f) t = fminf(t, (g.bound[3 + k] - g.pos[k]) / d[k]);
-            else if (d[k] < 0.0f) t = fminf(t, (g.bound[k] - g.pos[k]) / d[k]);
-        }
-    } else {
-        const float b = fmaf(g.pos[0], d[0], fmaf(g.pos[1], d[1], g.pos[2] * d[2]));
-        const float c = fmaf(g.pos[0], g.pos[0], fmaf(g.pos[1], g.pos[1], g.pos[2] * g.pos[2])) - g.bound[0] * g.bound[0];
-        const float disc = b * b - c;
-        t = disc > 0.0f ? sqrtf(disc) - b : 0.0f;
-    }
-    t = fmaxf(t, 0.0f);
+    float d[3], t;
+    camera_ray(g.rot, g.pos, g.focal, g.width, g.height, px, py, g.bound_kind, g.bound, d, &t);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         g.origin[3 * r + k] = g.pos[k];

@@ -74,6 +74,9 @@ struct RaygenArgs {
 
 enum WalkKind { kForward = 0, kTrace = 1, kBackwardReduce = 2, kBackwardAtomic = 3 };
 
+// Records an error message for rf_last_error() on this host thread.
+void set_error(const char* msg);
+
 hipError_t launch_walk(WalkKind kind, int sh_degree, bool bf16, const WalkArgs& a, hipStream_t stream);
 hipError_t launch_pack(int sh_degree, bool bf16, const PackArgs& a, hipStream_t stream);
 hipError_t launch_raygen(const RaygenArgs& a, hipStream_t stream);

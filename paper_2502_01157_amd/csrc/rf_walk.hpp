@@ -1,0 +1,187 @@
+// Device functions of the walk shared by the batch kernels and the serving kernel.
+#pragma once
+
+#include "rf_device.hpp"
+#include "rf_kernels.hpp"
+
+namespace rf {
+
+struct FaceHit {
+    float num, den;
+    int k;  // index within the row, -1 if no front face
+};
+
+__device__ inline FaceHit nearest_front_face(const float4* __restrict__ planes, int beg, int deg, float ox, float oy,
+                                             float oz, float dx, float dy, float dz)
+{
+    float bn = 1.0f, bd = 0.0f;
+    int bk = -1;
+    for (int k = 0; k < deg; k += 4) {
+        float4 p[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) p[u] = planes[beg + min(k + u, deg - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float den = fmaf(p[u].z, dz, fmaf(p[u].y, dy, p[u].x * dx));
+            const float num = p[u].w - fmaf(p[u].z, oz, fmaf(p[u].y, oy, p[u].x * ox));
+            const bool better = (den > 0.0f) && (num * bd < bn * den);
+            bn = better ? num : bn;
+            bd = better ? den : bd;
+            bk = better ? min(k + u, deg - 1) : bk;
+        }
+    }
+    return {bn, bd, bk};
+}
+
+template <int DEG>
+__device__ inline void colour(const Attr<DEG>& at, const float* Y, float c[3])
+{
+    c[0] = c[1] = c[2] = 0.0f;
+#pragma unroll
+    for (int b = 0; b < sh_count(DEG); ++b) {
+        c[0] = fmaf(at.sh[3 * b + 0], Y[b], c[0]);
+        c[1] = fmaf(at.sh[3 * b + 1], Y[b], c[1]);
+        c[2] = fmaf(at.sh[3 * b + 2], Y[b], c[2]);
+    }
+}
+
+struct RayResult {
+    float C[3];
+    float T;
+    int status;  // visited cells, -1 bad start, -2 max_steps reached
+};
+
+// Exit distance through the winning face, in double precision: the plane
+// through m = x_i + n/2 with normal n (the stored n = x_j - x_i), so that
+// t = n.(m - o) / n.d is formed from differences of nearby points instead of
+// the FP32 offset c - n.o, whose cancellation costs ~eps32 (|o| + t)/cos.
+__device__ inline double exit_distance(float4 p, const float* site, float ox, float oy, float oz, float dx, float dy,
+                                       float dz)
+{
+    const double nx = p.x, ny = p.y, nz = p.z;
+    const double mx = fma(0.5, nx, (double)site[0]) - (double)ox;
+    const double my = fma(0.5, ny, (double)site[1]) - (double)oy;
+    const double mz = fma(0.5, nz, (double)site[2]) - (double)oz;
+    const double num = fma(nz, mz, fma(ny, my, nx * mx));
+    const double den = fma(nz, (double)dz, fma(ny, (double)dy, nx * (double)dx));
+    return num / den;
+}
+
+// One visited cell of Algorithm 1: nearest front face (FP32 decision), exact
+// exit distance of that face, clamped segment [t0, te], its optical depth,
+// opacity and colour. Shared by the forward, backward and serving walks so
+// that the backward recomputes bit-identical segments.
+template <int DEG>
+struct Visit {
+    Attr<DEG> at;
+    FaceHit h;
+    double t1;     // exit distance of the winning face, +inf if none
+    double te;     // max(t0, min(t1, t_max))
+    float delta, tau, alpha;
+    float c[3];
+    bool clipped;  // no front face or t1 >= t_max: the walk ends in this cell
+};
+
+template <int DEG, bool BF16>
+__device__ inline void visit_cell(const SceneView& s, uint2 ref, double t0, float tmax, float ox, float oy, float oz,
+                                  float dx, float dy, float dz, const float* Y, Visit<DEG>& v)
+{
+    const int cell = ref_cell(ref), beg = ref_beg(ref);
+    load_record<DEG, BF16>(s.rec, cell, v.at);
+    v.h = nearest_front_face(s.planes, beg, ref_deg(ref), ox, oy, oz, dx, dy, dz);
+    v.t1 = INFINITY;
+    if (v.h.k >= 0) v.t1 = exit_distance(s.planes[beg + v.h.k], v.at.site, ox, oy, oz, dx, dy, dz);
+    const double tm = (double)tmax;
+    v.clipped = (v.h.k < 0) || (v.t1 >= tm);
+    v.te = fmax(t0, fmin(v.t1, tm));
+    v.delta = (float)(v.te - t0);
+    v.tau = v.at.sigma > 0.0f ? v.at.sigma * v.delta : 0.0f;
+    v.alpha = -expm1f(-v.tau);
+    colour<DEG>(v.at, Y, v.c);
+}
+
+// Algorithm 1 for one ray: start in `start`, take the nearest front face of
+// each cell, composite the segment with eq. (3)-(4) while T > eps.
+template <int DEG, bool BF16, bool TRACE>
+__device__ inline void walk_forward(const SceneView& s, float ox, float oy, float oz, float dx, float dy, float dz,
+                                    float tmax, int start, float eps, int max_steps, int32_t* cells, float* t_exit,
+                                    int max_len, RayResult& res)
+{
+    res.C[0] = res.C[1] = res.C[2] = 0.0f;
+    res.T = 1.0f;
+    if (start < 0 || (int64_t)start >= s.n_sites) {
+        res.status = -1;
+        return;
+    }
+    float Y[sh_count(DEG)];
+    sh_basis<DEG>(dx, dy, dz, Y);
+    uint2 ref = s.row[start];
+    double t0 = 0.0;
+    float T = 1.0f;
+    int n = 0;
+    for (;;) {
+        if (!(T > eps)) {
+            res.status = n;
+            break;
+        }
+        if (n == max_steps) {
+            res.status = -2;
+            break;
+        }
+        Visit<DEG> v;
+        visit_cell<DEG, BF16>(s, ref, t0, tmax, ox, oy, oz, dx, dy, dz, Y, v);
+        const float w = T * v.alpha;
+        res.C[0] = fmaf(w, v.c[0], res.C[0]);
+        res.C[1] = fmaf(w, v.c[1], res.C[1]);
+        res.C[2] = fmaf(w, v.c[2], res.C[2]);
+        T *= expf(-v.tau);
+        if constexpr (TRACE) {
+            if (n < max_len) {
+                cells[n] = ref_cell(ref);
+                t_exit[n] = (float)v.te;
+            }
+        }
+        ++n;
+        if (v.clipped) {
+            res.status = n;
+            break;
+        }
+        ref = s.adj[ref_beg(ref) + v.h.k];
+        t0 = v.te;
+    }
+    res.T = T;
+}
+
+// Pinhole camera ray through the centre of pixel (px, py): direction
+// R (px + 0.5 - W/2, py + 0.5 - H/2, f) normalised; t_max is where the ray
+// leaves the bound (kind 0: box lo=b[0..2], hi=b[3..5]; kind 1: sphere of
+// radius b[0] about the world origin).
+__device__ inline void camera_ray(const float* rot, const float* pos, float focal, int W, int H, int px, int py,
+                                  int bound_kind, const float* bound, float d[3], float* tmax)
+{
+    const float u = ((float)px + 0.5f - 0.5f * (float)W) / focal;
+    const float v = ((float)py + 0.5f - 0.5f * (float)H) / focal;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d[k] = fmaf(rot[3 * k], u, fmaf(rot[3 * k + 1], v, rot[3 * k + 2]));
+    const float inv = 1.0f / sqrtf(fmaf(d[0], d[0], fmaf(d[1], d[1], d[2] * d[2])));
+    d[0] *= inv;
+    d[1] *= inv;
+    d[2] *= inv;
+    float t;
+    if (bound_kind == 0) {
+        t = INFINITY;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (d[k] > 0.0f) t = fminf(t, (bound[3 + k] - pos[k]) / d[k]);
+            else if (d[k] < 0.0f) t = fminf(t, (bound[k] - pos[k]) / d[k]);
+        }
+    } else {
+        const float b = fmaf(pos[0], d[0], fmaf(pos[1], d[1], pos[2] * d[2]));
+        const float c = fmaf(pos[0], pos[0], fmaf(pos[1], pos[1], pos[2] * pos[2])) - bound[0] * bound[0];
+        const float disc = b * b - c;
+        t = disc > 0.0f ? sqrtf(disc) - b : 0.0f;
+    }
+    *tmax = fmaxf(t, 0.0f);
+}
+
+}  // namespace rf

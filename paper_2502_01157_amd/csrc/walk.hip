@@ -33,120 +33,33 @@
 
 #include "rf_device.hpp"
 #include "rf_kernels.hpp"
+#include "rf_walk.hpp"
 
 namespace rf {
 
-struct FaceHit {
-    float num, den;
-    int k;  // index within the row, -1 if no front face
-};
-
-__device__ inline FaceHit nearest_front_face(const float4* __restrict__ planes, int beg, int deg, float ox, float oy,
-                                             float oz, float dx, float dy, float dz)
-{
-    float bn = 1.0f, bd = 0.0f;
-    int bk = -1;
-    for (int k = 0; k < deg; k += 4) {
-        float4 p[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) p[u] = planes[beg + min(k + u, deg - 1)];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const float den = fmaf(p[u].z, dz, fmaf(p[u].y, dy, p[u].x * dx));
-            const float num = p[u].w - fmaf(p[u].z, oz, fmaf(p[u].y, oy, p[u].x * ox));
-            const bool better = (den > 0.0f) && (num * bd < bn * den);
-            bn = better ? num : bn;
-            bd = better ? den : bd;
-            bk = better ? min(k + u, deg - 1) : bk;
-        }
-    }
-    return {bn, bd, bk};
-}
-
-template <int DEG>
-__device__ inline void colour(const Attr<DEG>& at, const float* Y, float c[3])
-{
-    c[0] = c[1] = c[2] = 0.0f;
-#pragma unroll
-    for (int b = 0; b < sh_count(DEG); ++b) {
-        c[0] = fmaf(at.sh[3 * b + 0], Y[b], c[0]);
-        c[1] = fmaf(at.sh[3 * b + 1], Y[b], c[1]);
-        c[2] = fmaf(at.sh[3 * b + 2], Y[b], c[2]);
-    }
-}
-
+// ---------------------------------------------------------------------------
+// Forward (and traced forward).
+// ---------------------------------------------------------------------------
 __device__ inline int64_t ray_index()
 {
     return xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
 }
 
-// ---------------------------------------------------------------------------
-// Forward (and traced forward).
-// ---------------------------------------------------------------------------
 template <int DEG, bool BF16, bool TRACE>
 __global__ __launch_bounds__(kBlock) void k_forward(WalkArgs a)
 {
     const int64_t r = ray_index();
     if (r >= a.n_rays) return;
-    const float ox = a.origin[3 * r], oy = a.origin[3 * r + 1], oz = a.origin[3 * r + 2];
-    const float dx = a.dir[3 * r], dy = a.dir[3 * r + 1], dz = a.dir[3 * r + 2];
-    const float tmax = a.t_max[r];
-    const int start = a.start[r];
-    float C[3] = {0.0f, 0.0f, 0.0f};
-    float T = 1.0f;
-    int status;
-    if (start < 0 || (int64_t)start >= a.s.n_sites) {
-        status = -1;  // RF_RAY_BAD_START
-    } else {
-        float Y[sh_count(DEG)];
-        sh_basis<DEG>(dx, dy, dz, Y);
-        uint2 ref = a.s.row[start];
-        float t0 = 0.0f;
-        int n = 0;
-        for (;;) {
-            if (!(T > a.eps)) {
-                status = n;
-                break;
-            }
-            if (n == a.max_steps) {
-                status = -2;  // RF_RAY_MAX_STEPS
-                break;
-            }
-            const int cell = ref_cell(ref), beg = ref_beg(ref);
-            Attr<DEG> at;
-            load_record<DEG, BF16>(a.s.rec, cell, at);
-            const FaceHit h = nearest_front_face(a.s.planes, beg, ref_deg(ref), ox, oy, oz, dx, dy, dz);
-            const float t1 = h.k >= 0 ? h.num / h.den : INFINITY;
-            const float te = fmaxf(t0, fminf(t1, tmax));
-            const float tau = at.sigma > 0.0f ? at.sigma * (te - t0) : 0.0f;
-            const float alpha = -expm1f(-tau);
-            float c[3];
-            colour<DEG>(at, Y, c);
-            const float w = T * alpha;
-            C[0] = fmaf(w, c[0], C[0]);
-            C[1] = fmaf(w, c[1], C[1]);
-            C[2] = fmaf(w, c[2], C[2]);
-            T *= expf(-tau);
-            if constexpr (TRACE) {
-                if (n < a.max_len) {
-                    a.cells[r * a.max_len + n] = cell;
-                    a.t_exit[r * a.max_len + n] = te;
-                }
-            }
-            ++n;
-            if (h.k < 0 || t1 >= tmax) {
-                status = n;
-                break;
-            }
-            ref = a.s.adj[beg + h.k];
-            t0 = te;
-        }
-    }
-    a.rgb[3 * r + 0] = C[0];
-    a.rgb[3 * r + 1] = C[1];
-    a.rgb[3 * r + 2] = C[2];
-    a.t_final[r] = T;
-    a.steps[r] = status;
+    RayResult res;
+    walk_forward<DEG, BF16, TRACE>(a.s, a.origin[3 * r], a.origin[3 * r + 1], a.origin[3 * r + 2], a.dir[3 * r],
+                                   a.dir[3 * r + 1], a.dir[3 * r + 2], a.t_max[r], a.start[r], a.eps, a.max_steps,
+                                   TRACE ? a.cells + r * a.max_len : nullptr,
+                                   TRACE ? a.t_exit + r * a.max_len : nullptr, a.max_len, res);
+    a.rgb[3 * r + 0] = res.C[0];
+    a.rgb[3 * r + 1] = res.C[1];
+    a.rgb[3 * r + 2] = res.C[2];
+    a.t_final[r] = res.T;
+    a.steps[r] = res.status;
 }
 
 // ---------------------------------------------------------------------------
@@ -297,7 +210,8 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
     float Y[B];
     sh_basis<DEG>(dx, dy, dz, Y);
 
-    float T = 1.0f, t0 = 0.0f, Cacc[3] = {0.0f, 0.0f, 0.0f};
+    float T = 1.0f, Cacc[3] = {0.0f, 0.0f, 0.0f};
+    double t0 = 0.0;
     int n = 0;
     // previous visit, awaiting its exit gradient
     bool have_prev = false, p_moves = false;
@@ -313,25 +227,17 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
         if (state == 0) {
             bool stop = !(T > a.eps) || (n == a.max_steps);
             if (!stop) {
-                const int cell = ref_cell(ref), beg = ref_beg(ref);
-                Attr<DEG> at;
-                load_record<DEG, BF16>(a.s.rec, cell, at);
-                const FaceHit h = nearest_front_face(a.s.planes, beg, ref_deg(ref), ox, oy, oz, dx, dy, dz);
-                const float t1 = h.k >= 0 ? h.num / h.den : INFINITY;
-                const float te = fmaxf(t0, fminf(t1, tmax));
-                const float delta = te - t0;
-                const float tau = at.sigma > 0.0f ? at.sigma * delta : 0.0f;
-                const float alpha = -expm1f(-tau);
-                float c[3];
-                colour<DEG>(at, Y, c);
-                const float w = T * alpha;
-                Cacc[0] = fmaf(w, c[0], Cacc[0]);
-                Cacc[1] = fmaf(w, c[1], Cacc[1]);
-                Cacc[2] = fmaf(w, c[2], Cacc[2]);
-                const float Tn = T * expf(-tau);
+                Visit<DEG> v;
+                visit_cell<DEG, BF16>(a.s, ref, t0, tmax, ox, oy, oz, dx, dy, dz, Y, v);
+                const Attr<DEG>& at = v.at;
+                const float w = T * v.alpha;
+                Cacc[0] = fmaf(w, v.c[0], Cacc[0]);
+                Cacc[1] = fmaf(w, v.c[1], Cacc[1]);
+                Cacc[2] = fmaf(w, v.c[2], Cacc[2]);
+                const float Tn = T * expf(-v.tau);
                 float dtau = -gT * Tfin;
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) dtau = fmaf(g[ch], Tn * c[ch] - (Cout[ch] - Cacc[ch]), dtau);
+                for (int ch = 0; ch < 3; ++ch) dtau = fmaf(g[ch], Tn * v.c[ch] - (Cout[ch] - Cacc[ch]), dtau);
                 const float sdt = at.sigma * dtau;
                 float edx[3] = {0.0f, 0.0f, 0.0f};
                 if (have_prev) {
@@ -349,29 +255,29 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
                     has = true;
                     out = prev;
                 }
-                prev.cell = cell;
+                prev.cell = ref_cell(ref);
                 prev.gw[0] = g[0] * w;
                 prev.gw[1] = g[1] * w;
                 prev.gw[2] = g[2] * w;
-                prev.dsig = delta * dtau;
+                prev.dsig = v.delta * dtau;
                 prev.dx[0] = edx[0];
                 prev.dx[1] = edx[1];
                 prev.dx[2] = edx[2];
                 p_site[0] = at.site[0];
                 p_site[1] = at.site[1];
                 p_site[2] = at.site[2];
-                p_t1 = t1;
-                p_den = h.den;
+                p_t1 = (float)v.t1;
+                p_den = v.h.den;
                 p_sdt = sdt;
-                p_moves = (h.k >= 0) && (t1 < tmax) && (t1 >= t0);
+                p_moves = !v.clipped && (v.t1 >= t0);
                 have_prev = true;
                 T = Tn;
                 ++n;
-                if (h.k < 0 || t1 >= tmax) {
+                if (v.clipped) {
                     stop = true;
                 } else {
-                    ref = a.s.adj[beg + h.k];
-                    t0 = te;
+                    ref = a.s.adj[ref_beg(ref) + v.h.k];
+                    t0 = v.te;
                 }
             }
             if (stop) {

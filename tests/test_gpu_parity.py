@@ -52,7 +52,7 @@ def gpu_trace(rf, p, rays, eps, max_steps=8192, max_len=1024):
     return out
 
 
-def check_forward(rf, scene, rays, eps, dtype="f32", max_undecidable=0.02):
+def check_forward(rf, scene, rays, eps, dtype="f32", max_undecidable=0.03):
     p, _ = packed(rf, scene, dtype)
     osc = oracle.OracleScene.from_scene(scene)
     if dtype == "bf16":

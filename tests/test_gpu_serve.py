@@ -1,0 +1,120 @@
+"""Continuous-batching server: results alone and in the mix, admission by memory, errors."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from parity import COLOUR_RTOL, colour_err
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(64, 48), (33, 17), (128, 96), (8, 8), (100, 70), (1, 1), (56, 80), (130, 9)]
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible to torch")
+    import paper_2502_01157_amd as rf
+
+    scene, rng = synth.small_scene("clustered", 20000, seed=41, sh_deg=3, return_rng=True)
+    reqs = []
+    for k in range(24):
+        w, h = SIZES[k % len(SIZES)]
+        cam = synth.make_cameras("cfg5", rng, n=1, res=(w, h))[0]
+        start = int(synth.nearest_site(scene.sites, cam.position[None, :])[0])
+        reqs.append(dict(arrival=0.002 * k, pose12=cam.pose12(), fov_deg=cam.fov_deg, width=w, height=h,
+                         start_cell=start, camera=cam))
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    packed = rf.PackedScene(*map(dv, (scene.sites, scene.off, scene.idx, scene.density, scene.sh)), 3, "f32")
+    # each request rendered alone by the batch path (ray generation + forward walk)
+    alone = []
+    for r in reqs:
+        o, d, t, s, px = rf.raygen(r["pose12"], r["fov_deg"], r["width"], r["height"], scene.bound,
+                                   r["start_cell"])
+        rgb, tf, _ = rf.render_forward(packed, o, d, t, s)
+        img = np.zeros((r["height"] * r["width"], 4), dtype=np.float32)
+        img[px.cpu().numpy()] = np.concatenate([rgb.cpu().numpy(), tf.cpu().numpy()[:, None]], 1)
+        alone.append(img.reshape(r["height"], r["width"], 4))
+    torch.cuda.synchronize()
+    return rf, scene, packed, reqs, alone
+
+
+def test_mix_equals_alone_bitwise(setup):
+    rf, scene, packed, reqs, alone = setup
+    from paper_2502_01157_amd.serve import Server, replay
+
+    with Server(packed, scene.bound, pool_bytes=8 << 20, max_inflight=16) as srv:
+        out = replay(srv, reqs, keep=range(len(reqs)), timeout_s=20)
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["inflight"] == 0 and st["pool_used_bytes"] == 0
+    for i, r in enumerate(reqs):
+        np.testing.assert_array_equal(out["images"][i], alone[i], err_msg=f"request {i}")
+    # and each request alone in the server
+    with Server(packed, scene.bound, pool_bytes=8 << 20, max_inflight=4) as srv:
+        for i in (0, 2, 5, 7):
+            one = replay(srv, [dict(reqs[i], arrival=0.0)], keep=[0], timeout_s=20)
+            np.testing.assert_array_equal(one["images"][0], alone[i])
+
+
+def test_served_images_match_oracle(setup):
+    rf, scene, packed, reqs, alone = setup
+    osc = oracle.OracleScene.from_scene(scene)
+    for i in (0, 2, 4):
+        r = reqs[i]
+        o, d, t, px = oracle.raygen(np.float32(r["pose12"]).astype(np.float64), r["fov_deg"], r["width"],
+                                    r["height"], scene.bound)
+        rgb, tf, _ = oracle.forward(osc, o.astype(np.float32), d.astype(np.float32), t.astype(np.float32),
+                                    r["start_cell"])
+        ref = np.zeros((r["height"] * r["width"], 4))
+        ref[px] = np.concatenate([rgb, tf[:, None]], 1)
+        ref = ref.reshape(r["height"], r["width"], 4)
+        # the served rays come from FP32 ray generation; the oracle's from FP64
+        assert colour_err(alone[i][..., :3], ref[..., :3]) <= 10 * COLOUR_RTOL
+
+
+def test_admission_by_memory_and_fifo(setup):
+    rf, scene, packed, reqs, alone = setup
+    from paper_2502_01157_amd.serve import Server, replay
+
+    big = [dict(r, width=128, height=96) for r in reqs[:6]]
+    # room for two 128x96 outputs at a time
+    with Server(packed, scene.bound, pool_bytes=2 * 128 * 96 * 16 + 1024, max_inflight=8) as srv:
+        ids = [srv.submit(r["pose12"], r["fov_deg"], 128, 96, r["start_cell"]) for r in big[:3]]
+        assert ids[0] is not None and ids[1] is not None and ids[2] is None
+        with pytest.raises(rf.RfError, match="UNSUPPORTED"):
+            srv.submit(big[0]["pose12"], 60.0, 512, 512, 0)
+        import time
+
+        t0 = time.time()
+        done = []
+        while len(done) < 2 and time.time() - t0 < 20:
+            done += srv.poll()
+        assert sorted(done) == sorted(ids[:2])
+        for rid in done:
+            srv.result(rid)
+        out = replay(srv, big, keep=range(6), timeout_s=20)
+        assert srv.stats()["rejected_busy"] >= 1
+    assert np.all(np.isfinite(out["latency_s"]))
+    for i in range(6):
+        assert out["images"][i].shape == (96, 128, 4)
+
+
+def test_server_argument_errors(setup):
+    rf, scene, packed, reqs, alone = setup
+    from paper_2502_01157_amd.serve import Server
+
+    with pytest.raises(rf.RfError, match="INVALID_ARG"):
+        Server(packed, scene.bound, max_inflight=0)
+    with pytest.raises(rf.RfError, match="INVALID_ARG"):
+        Server(packed, scene.bound, max_inflight=65)
+    with pytest.raises(rf.RfError, match="INVALID_ARG"):
+        Server(packed, scene.bound, pool_bytes=16)
+    with Server(packed, scene.bound, pool_bytes=1 << 20, max_inflight=2) as srv:
+        with pytest.raises(rf.RfError, match="INVALID_ARG"):
+            srv.submit(reqs[0]["pose12"], 0.0, 8, 8, 0)
+        assert srv.poll() == []
