@@ -238,42 +238,41 @@ rf_status rf_packed_planes(const rf_packed_scene *scene, float *planes, void *st
 rf_status rf_packed_attributes(const rf_packed_scene *scene, float *density, float *sh, void *stream);
 
 /* ------------------------------------------------------------------------
- * Continuous-batching render server (forward only).
+ * Continuous-batching render server (forward only; the paper's renderer,
+ * Sec. 3.4, measured frame rates with a low-overhead renderer).
  *
- * One persistent kernel, launched by rf_server_create on its own stream and
- * sized to fill the GPU, renders 8x8 screen tiles of every admitted request;
- * tiles of requests that arrive while others are on the GPU are interleaved
- * with theirs. The packed scene stays resident (the caller keeps it alive and
- * unmodified until rf_server_destroy returns). Results land in a pinned host
- * output pool owned by the server: per pixel, in image row-major order, RGBA
+ * The packed scene stays resident (the caller keeps it alive and unmodified
+ * until rf_server_destroy returns). Admitted requests are cut into 8x8
+ * screen tiles. A scheduler thread owned by the server builds each kernel
+ * launch from the pending tiles of all admitted requests (oldest request
+ * first, up to 8192 tiles per launch) and keeps two launches queued on the
+ * server's own stream, so requests that arrive while others are on the GPU
+ * join the next launch and their work overlaps. Results land in a pinned
+ * host output pool owned by the server: per pixel, image row-major, RGBA
  * floats = (r, g, b, final transmittance). Every pixel is computed by the same
  * ray generation and walk as rf_raygen + rf_render_forward, so a request's
  * image does not depend on what else is in flight.
  *
- * Admission (rf_server_submit) is immediate or RF_ERR_BUSY: a request is
- * admitted when an in-flight slot is free (at most max_inflight <= 64) and
- * its W*H*16 bytes fit contiguously in the pool (pool_bytes). Callers that
- * need FIFO order keep their own queue and retry its head.
- * rf_server_poll lists finished requests not yet collected;
- * rf_server_result copies one to `rgba` (host memory, >= W*H*16 bytes; NULL
- * discards it) and frees its slot and pool range.
- * rf_server_destroy waits (up to 10 s) for admitted requests, stops every
- * wave of the kernel and frees the server. The kernel also stops by itself
- * when the host's heartbeat (a thread of the server) is not seen for 5 s;
- * later submits then fail with RF_ERR_HIP. Calls on one server may come from
- * several host threads (they serialise on an internal lock).
+ * rf_server_submit admits a request immediately or returns RF_ERR_BUSY: it
+ * needs a free slot (at most max_inflight <= 64 requests in flight) and W*H*16
+ * contiguous bytes of the pool (pool_bytes). Callers that need FIFO order keep
+ * their own queue and retry its head.
+ * rf_server_poll lists finished requests not yet collected; rf_server_result
+ * copies one into `rgba` (host memory, >= W*H*16 bytes; NULL discards it) and
+ * frees its slot and pool range. rf_server_destroy finishes admitted requests,
+ * stops the scheduler and frees the server. All calls may come from any host
+ * thread; they serialise on the server's lock.
  * ---------------------------------------------------------------------- */
 typedef struct rf_server rf_server;
 
 typedef struct {
     int64_t submitted, completed, rejected_busy, rays_done;
     int64_t pool_used_bytes, pool_bytes;
-    int32_t inflight, workgroups;
+    int64_t launches, inflight;
 } rf_server_stats;
 
 rf_status rf_server_create(const rf_packed_scene *scene, const rf_params *params, const rf_bound *bound,
-                           size_t pool_bytes, int32_t max_inflight, int32_t workgroups /* 0: fill the GPU */,
-                           rf_server **out);
+                           size_t pool_bytes, int32_t max_inflight, rf_server **out);
 rf_status rf_server_submit(rf_server *server, const rf_camera *camera, int32_t start_cell, uint64_t *req_id);
 rf_status rf_server_poll(rf_server *server, uint64_t *done_ids, int32_t cap, int32_t *n_done);
 rf_status rf_server_result(rf_server *server, uint64_t req_id, float *rgba, size_t bytes);

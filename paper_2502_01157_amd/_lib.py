@@ -66,7 +66,7 @@ class BoundDesc(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected_busy", ctypes.c_int64),
                 ("rays_done", ctypes.c_int64), ("pool_used_bytes", ctypes.c_int64), ("pool_bytes", ctypes.c_int64),
-                ("inflight", ctypes.c_int32), ("workgroups", ctypes.c_int32)]
+                ("launches", ctypes.c_int64), ("inflight", ctypes.c_int64)]
 
 
 _lib: Optional[ctypes.CDLL] = None
@@ -103,7 +103,7 @@ def lib() -> ctypes.CDLL:
                      "rf_render_trace", "rf_render_backward", "rf_packed_planes", "rf_packed_attributes"):
             getattr(L, name).restype = st
         L.rf_server_create.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Params),
-                                       ctypes.POINTER(BoundDesc), ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.POINTER(BoundDesc), ctypes.c_size_t, ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_void_p)]
         L.rf_server_submit.argtypes = [P, ctypes.POINTER(CameraDesc), ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
         L.rf_server_poll.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32,

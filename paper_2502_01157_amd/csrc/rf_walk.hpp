@@ -6,20 +6,35 @@
 
 namespace rf {
 
+#ifndef RF_CARRY_ADJ
+#define RF_CARRY_ADJ 0
+#endif
+
 struct FaceHit {
     float num, den;
-    int k;  // index within the row, -1 if no front face
+    int k;      // index within the row, -1 if no front face
+    uint2 next; // the winning neighbour's row (when carried through the scan)
 };
 
-__device__ inline FaceHit nearest_front_face(const float4* __restrict__ planes, int beg, int deg, float ox, float oy,
-                                             float oz, float dx, float dy, float dz)
+// Nearest front face of a cell: den = n.d > 0 and the smallest
+// t = (c - n.o) / den, compared without division (ties keep the first face).
+// With RF_CARRY_ADJ the neighbour rows are read along with the planes so the
+// winner's row is known when the scan ends.
+__device__ inline FaceHit nearest_front_face(const float4* __restrict__ planes, const uint2* __restrict__ adj,
+                                             int beg, int deg, float ox, float oy, float oz, float dx, float dy,
+                                             float dz)
 {
     float bn = 1.0f, bd = 0.0f;
     int bk = -1;
+    uint2 bnext = make_uint2(0u, 0u);
     for (int k = 0; k < deg; k += 4) {
         float4 p[4];
+        uint2 q[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) p[u] = planes[beg + min(k + u, deg - 1)];
+        for (int u = 0; u < 4; ++u) {
+            p[u] = planes[beg + min(k + u, deg - 1)];
+            if (RF_CARRY_ADJ) q[u] = adj[beg + min(k + u, deg - 1)];
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const float den = fmaf(p[u].z, dz, fmaf(p[u].y, dy, p[u].x * dx));
@@ -28,9 +43,13 @@ __device__ inline FaceHit nearest_front_face(const float4* __restrict__ planes, 
             bn = better ? num : bn;
             bd = better ? den : bd;
             bk = better ? min(k + u, deg - 1) : bk;
+            if (RF_CARRY_ADJ) {
+                bnext.x = better ? q[u].x : bnext.x;
+                bnext.y = better ? q[u].y : bnext.y;
+            }
         }
     }
-    return {bn, bd, bk};
+    return {bn, bd, bk, bnext};
 }
 
 template <int DEG>
@@ -88,7 +107,8 @@ __device__ inline void visit_cell(const SceneView& s, uint2 ref, double t0, floa
 {
     const int cell = ref_cell(ref), beg = ref_beg(ref);
     load_record<DEG, BF16>(s.rec, cell, v.at);
-    v.h = nearest_front_face(s.planes, beg, ref_deg(ref), ox, oy, oz, dx, dy, dz);
+    v.h = nearest_front_face(s.planes, s.adj, beg, ref_deg(ref), ox, oy, oz, dx, dy, dz);
+    if (!RF_CARRY_ADJ && v.h.k >= 0) v.h.next = s.adj[beg + v.h.k];
     v.t1 = INFINITY;
     if (v.h.k >= 0) v.t1 = exit_distance(s.planes[beg + v.h.k], v.at.site, ox, oy, oz, dx, dy, dz);
     const double tm = (double)tmax;
@@ -146,7 +166,7 @@ __device__ inline void walk_forward(const SceneView& s, float ox, float oy, floa
             res.status = n;
             break;
         }
-        ref = s.adj[ref_beg(ref) + v.h.k];
+        ref = v.h.next;
         t0 = v.te;
     }
     res.T = T;

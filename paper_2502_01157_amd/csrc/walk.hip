@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
                 if (v.clipped) {
                     stop = true;
                 } else {
-                    ref = a.s.adj[ref_beg(ref) + v.h.k];
+                    ref = v.h.next;
                     t0 = v.te;
                 }
             }

@@ -1,9 +1,10 @@
 """Continuous-batching render server (binding of the rf_server_* C ABI) and a
 request loop that replays a timed stream of render requests.
 
-The server keeps a packed scene resident and runs one persistent kernel that
-renders the screen tiles of every admitted request; requests are admitted
-while others are on the GPU whenever a slot and output-pool memory are free.
+The server keeps a packed scene resident; its scheduler thread builds each
+kernel launch from the pending 8x8 tiles of every admitted request, so
+requests admitted while others are on the GPU share launches with them.
+Requests are admitted whenever a slot and output-pool memory are free.
 """
 
 from __future__ import annotations
@@ -23,13 +24,13 @@ class Server:
     """A running server. Use as a context manager or call ``close()``."""
 
     def __init__(self, scene: PackedScene, bound: tuple, pool_bytes: int = 1 << 30, max_inflight: int = 32,
-                 eps: float = 1e-4, max_steps: int = 8192, workgroups: int = 0):
+                 eps: float = 1e-4, max_steps: int = 8192):
         self.scene = scene  # keeps the packed workspace alive
         self._h = ctypes.c_void_p()
         p = L.Params(float(eps), int(max_steps))
         b = bound_desc(bound)
         L.check(L.lib().rf_server_create(ctypes.byref(scene.desc), ctypes.byref(p), ctypes.byref(b),
-                                         int(pool_bytes), int(max_inflight), int(workgroups), ctypes.byref(self._h)))
+                                         int(pool_bytes), int(max_inflight), ctypes.byref(self._h)))
         self.max_inflight = int(max_inflight)
         self._ids = (ctypes.c_uint64 * self.max_inflight)()
         self.sizes: Dict[int, tuple] = {}
@@ -123,7 +124,10 @@ def replay(server: Server, requests: Sequence[dict], keep: Sequence[int] = (), t
             queue.popleft()
             rid_of[rid] = i
             admitted_at[i] = time.perf_counter() - t0
-        for rid in server.poll():
+        finished = server.poll()
+        if not finished and queue:
+            time.sleep(5e-5)  # the head waits for a slot or pool space
+        for rid in finished:
             i = rid_of.pop(rid)
             t_done = time.perf_counter() - t0
             latency[i] = t_done - requests[i]["arrival"] * time_scale

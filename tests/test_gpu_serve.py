@@ -48,10 +48,19 @@ def test_mix_equals_alone_bitwise(setup):
     rf, scene, packed, reqs, alone = setup
     from paper_2502_01157_amd.serve import Server, replay
 
+    # all requests arrive at once: 16 are admitted together and share launches,
+    # the rest are admitted as slots free up
+    burst = [dict(r, arrival=0.0) for r in reqs]
     with Server(packed, scene.bound, pool_bytes=8 << 20, max_inflight=16) as srv:
-        out = replay(srv, reqs, keep=range(len(reqs)), timeout_s=20)
+        out = replay(srv, burst, keep=range(len(reqs)), timeout_s=20)
         st = srv.stats()
     assert st["completed"] == len(reqs) and st["inflight"] == 0 and st["pool_used_bytes"] == 0
+    assert st["launches"] < len(reqs)
+    for i, r in enumerate(reqs):
+        np.testing.assert_array_equal(out["images"][i], alone[i], err_msg=f"request {i}")
+    # staggered arrivals (2 ms apart)
+    with Server(packed, scene.bound, pool_bytes=8 << 20, max_inflight=16) as srv:
+        out = replay(srv, reqs, keep=range(len(reqs)), timeout_s=20)
     for i, r in enumerate(reqs):
         np.testing.assert_array_equal(out["images"][i], alone[i], err_msg=f"request {i}")
     # and each request alone in the server
@@ -114,6 +123,8 @@ def test_server_argument_errors(setup):
         Server(packed, scene.bound, max_inflight=65)
     with pytest.raises(rf.RfError, match="INVALID_ARG"):
         Server(packed, scene.bound, pool_bytes=16)
+    with pytest.raises(rf.RfError, match="INVALID_ARG"):
+        Server(packed, ("box", 0.0, 1.0), eps=-1.0)
     with Server(packed, scene.bound, pool_bytes=1 << 20, max_inflight=2) as srv:
         with pytest.raises(rf.RfError, match="INVALID_ARG"):
             srv.submit(reqs[0]["pose12"], 0.0, 8, 8, 0)
