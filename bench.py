@@ -18,8 +18,11 @@ Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--config cfg3]
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -35,6 +38,31 @@ HBM_PEAK_GBS = 8000.0
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    """Digest of the HIP sources; HBM traffic figures are only valid for the digest they were taken on."""
+    h = hashlib.sha1()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2502_01157_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
+def measured_traffic(kernel: str, dtype: str):
+    """HBM bytes per launch (read + written) of `kernel` from the committed rocprofv3 PMC summary,
+    or None if that summary was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"walk_kernels_cfg3_{dtype}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel source digest: ([0-9a-f]+)", text)
+    if not m or m.group(1) != kernel_source_digest():
+        return None
+    m = re.search(rf"^\| k_{kernel}\S* \| \d+ \| \d+ \| \d+ \| ([0-9.]+) \| ([0-9.]+) \|", text, re.M)
+    if not m:
+        return None
+    return int(round((float(m.group(1)) + float(m.group(2))) * 1e6))
 
 
 def flops_per_visit(mean_deg: float, B: int, backward: bool) -> float:
@@ -62,6 +90,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", type=int, default=0, help="backward reduction mode (0 wave-reduced, 1 per-lane)")
     ap.add_argument("--only", choices=["f32", "bf16"], default=None, help="time one attribute precision only")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving replay (512 Poisson requests)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -227,13 +256,47 @@ def main() -> int:
                       for dt in dts for b in (True, False)},
         "roofline": {"bound": "alu", "kernel": f"{dominant} walk ({main_dt} attributes)",
                      "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s",
-                     "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None},
+                     "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
+                     "traffic": measured_traffic(dominant, "fp32" if main_dt == "f32" else main_dt)},
+        "kernel_source_digest": kernel_source_digest(),
     }
 
+    if not args.no_serving and args.config == "cfg3":
+        out["serving"] = serving(rf, scenes, scene, bound, dts)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, cam, bound, start, g_np, visits / R, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def serving(rf, packed, scene, bound, dts):
+    """Continuous-batching replay of 512 render requests (exponential inter-arrivals,
+    mean 5 ms; sizes uniform over 256^2, 512^2, 1024^2, 1920x1080; poses inside
+    [-0.8, 0.8]^3) against the resident 1M-site scene, forward only."""
+    import numpy as np
+
+    import synth
+    from paper_2502_01157_amd.serve import Server, replay
+
+    rng = np.random.default_rng(5)
+    reqs = synth.make_serving_requests(rng, n=512, rate_hz=200.0)
+    starts = synth.nearest_site(scene.sites, np.stack([r["camera"].position for r in reqs]))
+    stream = [dict(arrival=r["arrival"], pose12=r["camera"].pose12(), fov_deg=r["camera"].fov_deg,
+                   width=r["camera"].width, height=r["camera"].height, start_cell=int(st))
+              for r, st in zip(reqs, starts)]
+    offered = sum(r["width"] * r["height"] for r in stream) / (stream[-1]["arrival"] - stream[0]["arrival"]) / 1e6
+    res = {"requests": len(stream), "offered_mrays_s": round(offered, 2)}
+    for dt in dts:
+        with Server(packed[dt], bound, pool_bytes=1 << 30, max_inflight=64) as srv:
+            out = replay(srv, stream, timeout_s=120)
+            st = srv.stats()
+        res[dt] = {"p50_ms": round(out["p50_ms"], 3), "p99_ms": round(out["p99_ms"], 3),
+                   "mean_ms": round(out["mean_ms"], 3), "mrays_s": round(out["mrays_per_s"], 2),
+                   "launches": int(st["launches"]), "busy_rejections": int(st["rejected_busy"]),
+                   "copy_out_ms_mean": round(float(np.nanmean(out["copy_ms"])), 3)}
+        log(f"serving {dt}: p50 {out['p50_ms']:.2f} ms, p99 {out['p99_ms']:.2f} ms, "
+            f"{out['mrays_per_s']:.1f} Mrays/s sustained (offered {offered:.1f}), {st['launches']} launches")
+    return res
 
 
 def cpu_baseline(scene, cam, bound, start, g_np, visits_per_ray, target_s):

@@ -47,7 +47,7 @@ Layout layout(int64_t n, int64_t e, int deg, bool bf16)
     L.rec_bytes = rf::rec_bytes(deg, bf16);
     size_t p = 0;
     L.planes = p;
-    p = align256(p + (size_t)e * 16);
+    p = align256(p + ((size_t)e + 4) * 16);  // 4 padding faces: the scan reads in batches of four
     L.adj = p;
     p = align256(p + (size_t)e * 8);
     L.row = p;

