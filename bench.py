@@ -12,7 +12,7 @@ forward-only and BF16-attribute rates, per-kernel times, step-latency
 percentiles, the roofline of the dominant kernel and the FP64 CPU oracle's
 rate on a bounded sample of the same workload are added fields.
 
-Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--config cfg3]
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--config clustered_1m]
 """
 
 from __future__ import annotations
@@ -49,10 +49,10 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:12]
 
 
-def measured_traffic(kernel: str, dtype: str):
+def measured_traffic(kernel: str, workload: str, dtype: str):
     """HBM bytes per launch (read + written) of `kernel` from the committed rocprofv3 PMC summary,
     or None if that summary was taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"walk_kernels_cfg3_{dtype}_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"walk_kernels_{workload}_{dtype}_hbm_traffic.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -85,7 +85,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="cfg3", choices=["cfg1", "cfg2", "cfg3", "cfg4"])
+    ap.add_argument("--config", default="clustered_1m", choices=["uniform_4k", "clustered_200k", "clustered_1m", "shell_3m"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", type=int, default=0, help="backward reduction mode (0 wave-reduced, 1 per-lane)")
@@ -240,7 +240,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded clustered Voronoi scene, Delaunay CSR from Qhull)",
-        "config": {"workload": f"{args.config}: {scene.n_sites} sites clustered, SH deg {scene.sh_deg}, "
+        "config": {"workload": f"{args.config}: {scene.n_sites} sites {synth.CONFIGS[args.config]["kind"]}, SH deg {scene.sh_deg}, "
                                f"{W}x{H} camera, raygen+pack+forward+backward",
                    "rays_per_step": R, "visits_per_step": visits, "mean_visited_degree": round(mean_deg, 3),
                    "parallelism": "single GPU"},
@@ -257,11 +257,11 @@ def main() -> int:
         "roofline": {"bound": "alu", "kernel": f"{dominant} walk ({main_dt} attributes)",
                      "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s",
                      "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
-                     "traffic": measured_traffic(dominant, "fp32" if main_dt == "f32" else main_dt)},
+                     "traffic": measured_traffic(dominant, args.config, "fp32" if main_dt == "f32" else main_dt)},
         "kernel_source_digest": kernel_source_digest(),
     }
 
-    if not args.no_serving and args.config == "cfg3":
+    if not args.no_serving and args.config == "clustered_1m":
         out["serving"] = serving(rf, scenes, scene, bound, dts)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, cam, bound, start, g_np, visits / R, args.cpu_seconds)

@@ -36,19 +36,19 @@ import numpy as np
 #: The five workloads. ``kind`` selects the site distribution; ``bound`` is
 #: the region whose boundary ends each camera ray (``t_max``).
 CONFIGS: Dict[str, dict] = {
-    "cfg1": dict(n_sites=4096, kind="uniform01", sh_deg=0, sh_std=0.5,
+    "uniform_4k": dict(n_sites=4096, kind="uniform01", sh_deg=0, sh_std=0.5,
                  res=[(64, 64)], n_cams=1, camera="cube_centre",
                  bound=("box", 0.0, 1.0), backward=False, seed=1),
-    "cfg2": dict(n_sites=200_000, kind="clustered", sh_deg=3, sh_std=0.3,
+    "clustered_200k": dict(n_sites=200_000, kind="clustered", sh_deg=3, sh_std=0.3,
                  res=[(800, 800)], n_cams=1, camera="orbit",
                  bound=("box", -1.0, 1.0), backward=True, seed=2),
-    "cfg3": dict(n_sites=1_000_000, kind="clustered", sh_deg=3, sh_std=0.3,
+    "clustered_1m": dict(n_sites=1_000_000, kind="clustered", sh_deg=3, sh_std=0.3,
                  res=[(1920, 1080)], n_cams=1, camera="orbit",
                  bound=("box", -1.0, 1.0), backward=True, seed=3),
-    "cfg4": dict(n_sites=3_000_000, kind="clustered_shell", sh_deg=3, sh_std=0.3,
+    "shell_3m": dict(n_sites=3_000_000, kind="clustered_shell", sh_deg=3, sh_std=0.3,
                  res=[(1600, 1066)], n_cams=8, camera="inside",
                  bound=("sphere", 5.0), backward=True, seed=4),
-    "cfg5": dict(n_sites=1_000_000, kind="clustered", sh_deg=3, sh_std=0.3,
+    "serving_1m": dict(n_sites=1_000_000, kind="clustered", sh_deg=3, sh_std=0.3,
                  res=[(256, 256), (512, 512), (1024, 1024), (1920, 1080)],
                  n_cams=512, camera="inside", bound=("box", -1.0, 1.0),
                  backward=False, seed=5, rate_hz=200.0),
@@ -215,7 +215,7 @@ def _assemble(name: str, sites: np.ndarray, rng: np.random.Generator, sh_deg: in
 
 def make_scene(name: str, seed: Optional[int] = None, n_sites: Optional[int] = None,
                return_rng: bool = False):
-    """Scene for workload ``name`` ("cfg1" ... "cfg5").
+    """Scene for workload ``name`` ("uniform_4k" ... "serving_1m").
 
     ``n_sites`` overrides the site count (same distribution, for scaled-down
     tests). The generator is left positioned after the SH draw so that the
@@ -324,7 +324,7 @@ def make_upstream_grads(rng: np.random.Generator, n_rays: int) -> np.ndarray:
 def make_serving_requests(rng: np.random.Generator, n: int = 512, rate_hz: float = 200.0,
                           sizes=None) -> List[dict]:
     """Poisson arrival stream of render requests (arrival time in seconds, camera)."""
-    sizes = sizes or CONFIGS["cfg5"]["res"]
+    sizes = sizes or CONFIGS["serving_1m"]["res"]
     t = np.cumsum(rng.exponential(1.0 / rate_hz, size=n))
     reqs = []
     for k in range(n):

@@ -14,7 +14,7 @@ Tolerances (FP32 GPU path against the FP64 oracle on the same FP32 inputs):
   error of a composited sum scales with the cells' colour magnitude, not with
   |C| of one pixel, which can cancel to ~0); on full frames this holds on
   decidable rays, and every ray stays within 10 * COLOUR_RTOL (a flipped
-  near-tie inserts or drops a sliver segment; measured at cfg3: decidable
+  near-tie inserts or drops a sliver segment; measured at clustered_1m: decidable
   2.1e-6, all rays 1.6e-4);
 * final transmittance, on all rays: |T - T_ref| <= T_ATOL (T lies in [0, 1]);
 * exit distances of decidable rays: |t - t_ref| <= T_EXIT_ATOL + 1e-4 |t_ref|;

@@ -28,7 +28,7 @@ def _dv(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.mark.parametrize("name,dtype", [("cfg2", "f32"), ("cfg3", "f32"), ("cfg3", "bf16")])
+@pytest.mark.parametrize("name,dtype", [("clustered_200k", "f32"), ("clustered_1m", "f32"), ("clustered_1m", "bf16")])
 def test_full_frame_forward_backward(name, dtype):
     import torch
 
@@ -51,7 +51,7 @@ def test_full_frame_forward_backward(name, dtype):
     full = oracle.trace(osc, o, d, t, s, eps=1e-4, max_len=1)
     dec = decidable(full, 1e-4)
     print(f"oracle frame + margins in {time.time() - t1:.1f}s; decidable {dec.mean():.5f}", flush=True)
-    # a cfg3 ray makes ~2000 face decisions; the share of rays with one of them
+    # a clustered_1m ray makes ~2000 face decisions; the share of rays with one of them
     # inside the FP32 error scale is reported, not required to vanish
     assert dec.mean() > 0.85
 

@@ -79,16 +79,16 @@ def check_forward(rf, scene, rays, eps, dtype="f32", max_undecidable=0.03):
 # ---------------------------------------------------------------------------
 
 @pytest.fixture(scope="module")
-def cfg1():
-    scene, rng = synth.make_scene("cfg1", return_rng=True)
-    cam = synth.make_cameras("cfg1", rng)[0]
+def uniform_4k():
+    scene, rng = synth.make_scene("uniform_4k", return_rng=True)
+    cam = synth.make_cameras("uniform_4k", rng)[0]
     return scene, cam
 
 
 @pytest.fixture(scope="module")
 def clustered():
     scene, rng = synth.small_scene("clustered", 20000, seed=31, sh_deg=3, return_rng=True)
-    cams = synth.make_cameras("cfg2", rng, n=1, res=(96, 72))
+    cams = synth.make_cameras("clustered_200k", rng, n=1, res=(96, 72))
     return scene, cams[0], rng
 
 
@@ -153,7 +153,7 @@ def test_pack_rejects_bad_csr_without_faulting(rf, clustered):
                                        (33, 70, ("sphere", 5.0))])
 def test_raygen_matches_oracle(rf, W, H, bound):
     rng = np.random.default_rng(W + H)
-    cam = synth.make_cameras("cfg4", rng, n=1, res=(W, H))[0]
+    cam = synth.make_cameras("shell_3m", rng, n=1, res=(W, H))[0]
     if bound[1] == 0.0:
         cam.position = np.array([0.5, 0.4, 0.6])
     o, d, t, s, px = rf.raygen(cam.pose12(), cam.fov_deg, W, H, bound, start=123)
@@ -169,8 +169,8 @@ def test_raygen_matches_oracle(rf, W, H, bound):
 # a3: forward walk
 # ---------------------------------------------------------------------------
 
-def test_cfg1_full_frame_forward(rf, cfg1):
-    scene, cam = cfg1
+def test_uniform_4k_full_frame_forward(rf, uniform_4k):
+    scene, cam = uniform_4k
     rays = camera_rays(scene, cam)[:4]
     check_forward(rf, scene, rays, eps=1e-4)
 

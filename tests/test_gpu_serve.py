@@ -25,7 +25,7 @@ def setup():
     reqs = []
     for k in range(24):
         w, h = SIZES[k % len(SIZES)]
-        cam = synth.make_cameras("cfg5", rng, n=1, res=(w, h))[0]
+        cam = synth.make_cameras("serving_1m", rng, n=1, res=(w, h))[0]
         start = int(synth.nearest_site(scene.sites, cam.position[None, :])[0])
         reqs.append(dict(arrival=0.002 * k, pose12=cam.pose12(), fov_deg=cam.fov_deg, width=w, height=h,
                          start_cell=start, camera=cam))

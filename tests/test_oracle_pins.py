@@ -192,7 +192,7 @@ def test_csr_check_rejects_bad_adjacency(uniform_scene):
 @pytest.mark.parametrize("W,H", [(64, 64), (20, 13), (1, 1), (9, 17)])
 def test_raygen_projects_back_to_pixel_centres(W, H):
     rng = np.random.default_rng(W * 100 + H)
-    cam = synth.make_cameras("cfg4", rng, n=1, res=(W, H))[0]
+    cam = synth.make_cameras("shell_3m", rng, n=1, res=(W, H))[0]
     o, d, tmax, pix = oracle.raygen(cam.pose12(), cam.fov_deg, W, H, ("box", -1.0, 1.0))
     assert sorted(pix.tolist()) == list(range(W * H))
     np.testing.assert_allclose(np.linalg.norm(d, axis=1), 1.0, atol=1e-15)
@@ -216,7 +216,7 @@ def test_raygen_projects_back_to_pixel_centres(W, H):
 
 def test_raygen_sphere_bound():
     rng = np.random.default_rng(3)
-    cam = synth.make_cameras("cfg4", rng, n=1, res=(16, 8))[0]
+    cam = synth.make_cameras("shell_3m", rng, n=1, res=(16, 8))[0]
     o, d, tmax, _ = oracle.raygen(cam.pose12(), cam.fov_deg, 16, 8, ("sphere", 5.0))
     np.testing.assert_allclose(np.linalg.norm(o + tmax[:, None] * d, axis=1), 5.0, atol=1e-12)
     assert np.all(tmax > 0)

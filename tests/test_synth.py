@@ -33,7 +33,7 @@ def test_interior_mean_degree_matches_poisson_voronoi():
 
 def test_cameras_and_requests():
     rng = np.random.default_rng(0)
-    cams = synth.make_cameras("cfg3", rng)
+    cams = synth.make_cameras("clustered_1m", rng)
     assert len(cams) == 1 and (cams[0].width, cams[0].height) == (1920, 1080)
     np.testing.assert_allclose(np.linalg.norm(cams[0].position), 0.8, rtol=1e-6)
     R = cams[0].rotation
