@@ -240,7 +240,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded clustered Voronoi scene, Delaunay CSR from Qhull)",
-        "config": {"workload": f"{args.config}: {scene.n_sites} sites {synth.CONFIGS[args.config]["kind"]}, SH deg {scene.sh_deg}, "
+        "config": {"workload": f"{args.config}: {scene.n_sites} sites {synth.CONFIGS[args.config]['kind']}, SH deg {scene.sh_deg}, "
                                f"{W}x{H} camera, raygen+pack+forward+backward",
                    "rays_per_step": R, "visits_per_step": visits, "mean_visited_degree": round(mean_deg, 3),
                    "parallelism": "single GPU"},
