@@ -89,3 +89,79 @@ def test_full_frame_forward_backward(name, dtype):
     errs = [grad_err(x.cpu().numpy(), y) for x, y in zip(grads, ref_g)]
     print(f"gradient errors (sites, density, sh): {errs}", flush=True)
     assert max(errs) <= GRAD_RTOL
+
+
+def test_shell_3m_eight_cameras_sampled():
+    """The 3M-site shell scene (BF16 attributes), all eight cameras' rays in one launch.
+
+    The oracle checks a sample of 8x8 tiles per camera one ray at a time:
+    colour, transmittance and steps on decidable rays, the visited cells of a
+    sub-sample, and the gradients of a backward launch over every ray whose
+    upstream gradient is non-zero only on the sampled decidable rays (so the
+    accumulated sums are exactly those of the sample).
+    """
+    import torch
+
+    import paper_2502_01157_amd as rf
+
+    t0 = time.time()
+    scene, rng = synth.make_scene("shell_3m", return_rng=True)
+    cams = synth.make_cameras("shell_3m", rng)
+    print(f"\nshell_3m: scene {scene.n_sites} sites built in {time.time() - t0:.1f}s", flush=True)
+    per_cam = [camera_rays(scene, c) for c in cams]
+    o, d, t, s = (np.concatenate([r[k] for r in per_cam]) for k in range(4))
+    R = len(t)
+    assert R == sum(c.width * c.height for c in cams)
+
+    dens = oracle.bf16_to_f32(oracle.bf16_round(scene.density))
+    sh = oracle.bf16_to_f32(oracle.bf16_round(scene.sh))
+    osc = oracle.OracleScene.from_scene(scene, density=dens, sh=sh)
+
+    # 96 wave-sized blocks of 64 consecutive rays (one 8x8 tile where the tile is
+    # whole) per camera; a camera's last block may be short
+    srng = np.random.default_rng(4)
+    sel = []
+    base = 0
+    for c in cams:
+        n = c.width * c.height
+        for tile in srng.choice((n + 63) // 64, size=96, replace=False):
+            sel.append(base + tile * 64 + np.arange(64)[: max(0, min(64, n - tile * 64))])
+        base += n
+    sel = np.concatenate(sel)
+    t1 = time.time()
+    ref = oracle.trace(osc, o[sel], d[sel], t[sel], s[sel], eps=1e-4, max_len=1)
+    dec = decidable(ref, 1e-4)
+    print(f"oracle on {len(sel)} sampled rays in {time.time() - t1:.1f}s; decidable {dec.mean():.5f}", flush=True)
+    assert dec.mean() > 0.85
+
+    p = rf.PackedScene(*map(_dv, (scene.sites, scene.off, scene.idx, scene.density, scene.sh)), scene.sh_deg,
+                       "bf16", validate=True)
+    od, dd, td, sd = map(_dv, (o, d, t, s))
+    rgb_d, tf_d, steps_d = rf.render_forward(p, od, dd, td, sd)
+    torch.cuda.synchronize()
+    rgb, tf, steps = (x.cpu().numpy()[sel] for x in (rgb_d, tf_d, steps_d))
+    assert (steps_d.cpu().numpy() >= 0).all()
+    scale = np.abs(ref["rgb"]).max()
+    assert np.abs(rgb[dec] - ref["rgb"][dec]).max() <= COLOUR_RTOL * scale
+    assert colour_err(rgb, ref["rgb"]) <= 10 * COLOUR_RTOL
+    assert np.abs(tf[dec] - ref["t_final"][dec]).max() <= T_ATOL
+    np.testing.assert_array_equal(steps[dec], ref["steps"][dec])
+
+    sub = sel[: 64 * 32]
+    tr = rf.render_trace(p, *map(_dv, (o[sub], d[sub], t[sub], s[sub])), max_len=1024)
+    ref_sub = oracle.trace(osc, o[sub], d[sub], t[sub], s[sub], eps=1e-4, max_len=1024)
+    gst = tr["steps"].cpu().numpy()
+    assert compare_sequences(tr["cells"].cpu().numpy(), np.where(gst >= 0, gst, 0), ref_sub,
+                             decidable(ref_sub, 1e-4)) == 0
+
+    g = np.zeros((R, 3), dtype=np.float32)
+    g_sel = synth.make_upstream_grads(rng, len(sel))
+    g[sel[dec]] = g_sel[dec]
+    t2 = time.time()
+    ref_g = oracle.backward(osc, o[sel], d[sel], t[sel], s[sel], g[sel], eps=1e-4)
+    print(f"oracle backward on the sample in {time.time() - t2:.1f}s", flush=True)
+    grads = rf.render_backward(p, od, dd, td, sd, rgb_d, tf_d, _dv(g))
+    torch.cuda.synchronize()
+    errs = [grad_err(x.cpu().numpy(), y) for x, y in zip(grads, ref_g)]
+    print(f"gradient errors (sites, density, sh): {errs}", flush=True)
+    assert max(errs) <= GRAD_RTOL
