@@ -65,19 +65,21 @@ def measured_traffic(kernel: str, workload: str, dtype: str):
     return int(round((float(m.group(1)) + float(m.group(2))) * 1e6))
 
 
-def flops_per_visit(mean_deg: float, B: int, backward: bool) -> float:
+def flops_per_visit(mean_deg: float, B: int, kernel: str) -> float:
     """Arithmetic the walk itself requires per visited cell (FMA = 2 flops).
 
-    Per face: den = n.d (5), num = c - n.o (6), nearest-face compare (2).
-    Per cell: colour sum_b k_b Y_b (2 per coefficient, 3B coefficients) and
-    the compositing update (12). The backward adds the transmittance
-    derivative (14), the per-cell SH/density gradient (2 x 3B + 2) and the
-    two site gradients of the exit face (20).
+    Forward: per face den = n.d (5), num = c - n.o (6) and the nearest-face
+    compare (2); per cell the colour sum_b k_b Y_b (2 per coefficient, 3B
+    coefficients) and the compositing update (12). The backward adds the
+    transmittance derivative (14), the per-cell SH/density gradient
+    (2 x 3B + 2) and the two site gradients of the exit face (20); a backward
+    that reads the visits from the forward's log does no face tests, one that
+    recomputes the walk does them again.
     """
-    f = 13.0 * mean_deg + 6.0 * B + 12.0
-    if backward:
-        f += 14.0 + 6.0 * B + 2.0 + 20.0
-    return f
+    scan = 13.0 * mean_deg
+    cell = 6.0 * B + 12.0
+    grad = 14.0 + 6.0 * B + 2.0 + 20.0
+    return {"forward": scan + cell, "backward": cell + grad, "backward_recompute": scan + cell + grad}[kernel]
 
 
 def main() -> int:
@@ -89,6 +91,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", type=int, default=0, help="backward reduction mode (0 wave-reduced, 1 per-lane)")
+    ap.add_argument("--recompute", action="store_true",
+                    help="backward recomputes every walk instead of reading the forward's walk log")
+    ap.add_argument("--log-capacity", type=int, default=256, help="visits per ray kept in the walk log")
     ap.add_argument("--only", choices=["f32", "bf16"], default=None, help="time one attribute precision only")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving replay (512 Poisson requests)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -136,6 +141,7 @@ def main() -> int:
     rays = rf.raygen(pose, fov, W, H, bound, start, device=dev, with_pixel=False)[:4]
     fwd_out = (torch.empty((R, 3), device=dev), torch.empty(R, device=dev),
                torch.empty(R, dtype=torch.int32, device=dev))
+    walk_log = None if args.recompute else rf.WalkLog(R, args.log_capacity, dev)
     ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for k in ("raygen", "pack", "forward", "backward")}
 
@@ -151,13 +157,16 @@ def main() -> int:
         scenes[dt].pack(sites, dens, sh)
         mark("pack", 1)
         mark("forward", 0)
-        rgb, tf, steps = rf.render_forward(scenes[dt], o, d, t, s, out=fwd_out)
+        # a training step's forward keeps the walk log for its backward
+        log = walk_log if backward else None
+        rgb, tf, steps = rf.render_forward(scenes[dt], o, d, t, s, out=fwd_out, log=log)
         mark("forward", 1)
         if backward:
             for gbuf in grads:
                 gbuf.zero_()
             mark("backward", 0)
-            rf.render_backward(scenes[dt], o, d, t, s, rgb, tf, grad_rgb, None, mode=args.mode, grads=grads)
+            rf.render_backward(scenes[dt], o, d, t, s, rgb, tf, grad_rgb, None, mode=args.mode, grads=grads,
+                               log=log)
             mark("backward", 1)
         if timed is not None:
             torch.cuda.synchronize()
@@ -223,7 +232,8 @@ def main() -> int:
     ms, kern, lat = results[(main_dt, True)]
     value = R / (ms * 1e-3) / 1e6
     dominant = max(("forward", "backward"), key=lambda k: kern[k])
-    fl = flops_per_visit(mean_deg, B, dominant == "backward") * visits
+    fl = flops_per_visit(mean_deg, B, dominant if dominant == "forward" or not args.recompute
+                         else "backward_recompute") * visits
     achieved = fl / (kern[dominant] * 1e-3) / 1e12
 
     out = {
@@ -241,7 +251,9 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic (seeded clustered Voronoi scene, Delaunay CSR from Qhull)",
         "config": {"workload": f"{args.config}: {scene.n_sites} sites {synth.CONFIGS[args.config]['kind']}, SH deg {scene.sh_deg}, "
-                               f"{W}x{H} camera, raygen+pack+forward+backward",
+                               f"{W}x{H} camera, raygen+pack+forward+backward"
+                               + (" (backward recomputes the walks)" if args.recompute
+                                  else f" (forward logs up to {args.log_capacity} visits per ray for the backward)"),
                    "rays_per_step": R, "visits_per_step": visits, "mean_visited_degree": round(mean_deg, 3),
                    "parallelism": "single GPU"},
         "fwd_mrays_s": {dt: round(R / results[(dt, False)][0] / 1e3, 3) for dt in dts},

@@ -202,8 +202,9 @@ rf_status rf_render_forward(const rf_packed_scene *scene, const rf_rays *rays, c
 /* ------------------------------------------------------------------------
  * Backward walk: gradients of L = sum_r grad_rgb[r].rgb[r] + grad_t_final[r] T[r]
  * (Sec. 3.1: geometry receives gradients only through the segment widths).
- * The walk is recomputed from the inputs; rgb and t_final must be the
- * outputs of rf_render_forward for the same scene, rays and params.
+ * The walk is recomputed from the inputs (rf_render_backward_logged reads
+ * it from a walk log instead); rgb and t_final must be the outputs of
+ * rf_render_forward for the same scene, rays and params.
  *   grad_rgb      float[n_rays][3]
  *   grad_t_final  float[n_rays]        nullable (treated as 0)
  *   grad_sites    float[n_sites][3]    ACCUMULATED (+=); caller zeroes
@@ -218,6 +219,46 @@ rf_status rf_render_backward(const rf_packed_scene *scene, const rf_rays *rays, 
                              const float *rgb, const float *t_final, const float *grad_rgb,
                              const float *grad_t_final, float *grad_sites, float *grad_density, float *grad_sh,
                              int32_t mode, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Walk log: what the backward needs of each visit, saved by the forward so
+ * that the backward (Sec. 3.1 gradients, in the forward order of Algorithm 1)
+ * does not repeat the face scans. Step-major: visit n (0-based) of ray r is
+ * entry n * n_rays + r, for n < capacity.
+ *   code    uint32[capacity][n_rays]  visited cell | exit-moves << 31 |
+ *                                     walk-ended-here << 30 (the exit moves
+ *                                     with its face when t0 <= t1 < t_max)
+ *   t_exit  double[capacity][n_rays]  the visit's clamped exit distance te
+ *   tail    int32[n_rays][4]          the packed row reference (2 words) of
+ *                                     the cell after the logged visits, the
+ *                                     number of visited cells, 0
+ * A ray with more than `capacity` visits logs the first `capacity`; the
+ * backward recomputes the rest of its walk from the tail. Memory:
+ * n_rays * (12 * capacity + 16) bytes, device, owned by the caller; t_exit
+ * 8-byte, code 4-byte and tail 16-byte aligned. A log is valid only with the
+ * scene, rays and params of the forward that wrote it, until the scene is
+ * packed again.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    uint32_t *code;
+    double *t_exit;
+    int32_t *tail;
+    int32_t capacity;  /* >= 0; 0 logs nothing (the backward recomputes every visit) */
+} rf_walk_log;
+
+/* rf_render_forward that also writes `log`. Same outputs, bit for bit. */
+rf_status rf_render_forward_logged(const rf_packed_scene *scene, const rf_rays *rays, const rf_params *params,
+                                   float *rgb, float *t_final, int32_t *steps, const rf_walk_log *log,
+                                   void *stream);
+
+/* rf_render_backward reading the visits from `log` (written by
+ * rf_render_forward_logged for the same scene, rays and params) instead of
+ * recomputing them. Same gradients as rf_render_backward up to the order of
+ * the float atomic additions. */
+rf_status rf_render_backward_logged(const rf_packed_scene *scene, const rf_rays *rays, const rf_params *params,
+                                    const float *rgb, const float *t_final, const float *grad_rgb,
+                                    const float *grad_t_final, const rf_walk_log *log, float *grad_sites,
+                                    float *grad_density, float *grad_sh, int32_t mode, void *stream);
 
 /* ------------------------------------------------------------------------
  * Traced forward walk, for tests: the forward outputs plus, per ray, the

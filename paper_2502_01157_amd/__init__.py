@@ -13,9 +13,11 @@ _lib.lib()  # fail loudly when the HIP library has not been built
 
 from .ops import (  # noqa: E402,F401
     DEFAULT_EPS,
+    DEFAULT_LOG_CAPACITY,
     DEFAULT_MAX_STEPS,
     PackedScene,
     RadFoamRender,
+    WalkLog,
     raygen,
     render,
     render_backward,

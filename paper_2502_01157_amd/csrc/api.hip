@@ -301,6 +301,72 @@ rf_status rf_render_backward(const rf_packed_scene* scene, const rf_rays* rays, 
                       "backward walk");
 }
 
+static rf_status check_log(const rf_walk_log* log, int64_t n_rays)
+{
+    if (!log) return fail(RF_ERR_INVALID_ARG, "log is NULL");
+    if (log->capacity < 0) return fail(RF_ERR_INVALID_ARG, "log capacity must be >= 0");
+    if (n_rays > 0 && !log->tail) return fail(RF_ERR_INVALID_ARG, "log tail is NULL");
+    if (n_rays > 0 && log->capacity > 0 && (!log->code || !log->t_exit))
+        return fail(RF_ERR_INVALID_ARG, "log code or t_exit is NULL");
+    if ((reinterpret_cast<uintptr_t>(log->t_exit) & 7) || (reinterpret_cast<uintptr_t>(log->code) & 3) ||
+        (reinterpret_cast<uintptr_t>(log->tail) & 15))
+        return fail(RF_ERR_INVALID_ARG, "log arrays must be aligned to their element size (tail: 16 bytes)");
+    return RF_OK;
+}
+
+static void set_log(rf::WalkArgs& a, const rf_walk_log* log)
+{
+    a.log_code = log->code;
+    a.log_te = log->t_exit;
+    a.log_tail = reinterpret_cast<int4*>(log->tail);
+    a.log_cap = log->capacity;
+}
+
+rf_status rf_render_forward_logged(const rf_packed_scene* scene, const rf_rays* rays, const rf_params* params,
+                                   float* rgb, float* t_final, int32_t* steps, const rf_walk_log* log, void* stream)
+{
+    rf_status st;
+    if ((st = check_packed(scene)) != RF_OK || (st = check_rays(rays)) != RF_OK || (st = check_params(params)) != RF_OK)
+        return st;
+    if (rays->n_rays > 0 && (!rgb || !t_final || !steps)) return fail(RF_ERR_INVALID_ARG, "an output array is NULL");
+    if ((st = check_log(log, rays->n_rays)) != RF_OK) return st;
+    rf::WalkArgs a = walk_args(scene, rays, params);
+    a.rgb = rgb;
+    a.t_final = t_final;
+    a.steps = steps;
+    set_log(a, log);
+    return hip_status(rf::launch_walk(rf::kForwardLog, scene->sh_degree, scene->attr_dtype == RF_BF16, a,
+                                      static_cast<hipStream_t>(stream)),
+                      "logged forward walk");
+}
+
+rf_status rf_render_backward_logged(const rf_packed_scene* scene, const rf_rays* rays, const rf_params* params,
+                                    const float* rgb, const float* t_final, const float* grad_rgb,
+                                    const float* grad_t_final, const rf_walk_log* log, float* grad_sites,
+                                    float* grad_density, float* grad_sh, int32_t mode, void* stream)
+{
+    rf_status st;
+    if ((st = check_packed(scene)) != RF_OK || (st = check_rays(rays)) != RF_OK || (st = check_params(params)) != RF_OK)
+        return st;
+    if (mode != 0 && mode != 1) return fail(RF_ERR_INVALID_ARG, "mode must be 0 or 1");
+    if (rays->n_rays > 0 && (!rgb || !t_final || !grad_rgb))
+        return fail(RF_ERR_INVALID_ARG, "rgb, t_final and grad_rgb are required");
+    if (!grad_sites || !grad_density || !grad_sh) return fail(RF_ERR_INVALID_ARG, "a gradient array is NULL");
+    if ((st = check_log(log, rays->n_rays)) != RF_OK) return st;
+    rf::WalkArgs a = walk_args(scene, rays, params);
+    a.rgb_in = rgb;
+    a.t_final_in = t_final;
+    a.grad_rgb = grad_rgb;
+    a.grad_t = grad_t_final;
+    a.g_sites = grad_sites;
+    a.g_density = grad_density;
+    a.g_sh = grad_sh;
+    set_log(a, log);
+    return hip_status(rf::launch_walk(mode == 0 ? rf::kBackwardLogReduce : rf::kBackwardLogAtomic, scene->sh_degree,
+                                      scene->attr_dtype == RF_BF16, a, static_cast<hipStream_t>(stream)),
+                      "logged backward walk");
+}
+
 rf_status rf_packed_planes(const rf_packed_scene* scene, float* planes, void* stream)
 {
     rf_status st = check_packed(scene);

@@ -40,6 +40,11 @@ struct WalkArgs {
     float* g_sites;
     float* g_density;
     float* g_sh;
+    // walk log: written by a logged forward, read by a logged backward
+    uint32_t* log_code;  // [log_cap][n_rays] cell | moves << 31 | clipped << 30
+    double* log_te;      // [log_cap][n_rays] clamped exit distance of the visit
+    int4* log_tail;      // [n_rays] (row of the cell after the logged visits, visited cells, 0)
+    int32_t log_cap;
 };
 
 struct PackArgs {
@@ -72,7 +77,15 @@ struct RaygenArgs {
     int32_t* pixel;
 };
 
-enum WalkKind { kForward = 0, kTrace = 1, kBackwardReduce = 2, kBackwardAtomic = 3 };
+enum WalkKind {
+    kForward = 0,
+    kTrace = 1,
+    kBackwardReduce = 2,
+    kBackwardAtomic = 3,
+    kForwardLog = 4,
+    kBackwardLogReduce = 5,
+    kBackwardLogAtomic = 6
+};
 
 // Records an error message for rf_last_error() on this host thread.
 void set_error(const char* msg);

@@ -89,6 +89,17 @@ struct Visit {
     bool clipped;  // no front face or t1 >= t_max: the walk ends in this cell
 };
 
+// The segment of a visit whose clamped exit te is known: width, optical depth,
+// opacity and colour (eq. (3)-(4)).
+template <int DEG>
+__device__ inline void segment(double t0, const float* Y, Visit<DEG>& v)
+{
+    v.delta = (float)(v.te - t0);
+    v.tau = v.at.sigma > 0.0f ? v.at.sigma * v.delta : 0.0f;
+    v.alpha = -expm1f(-v.tau);
+    colour<DEG>(v.at, Y, v.c);
+}
+
 template <int DEG, bool BF16>
 __device__ inline void visit_cell(const SceneView& s, uint2 ref, double t0, float tmax, float ox, float oy, float oz,
                                   float dx, float dy, float dz, const float* Y, Visit<DEG>& v)
@@ -108,28 +119,52 @@ __device__ inline void visit_cell(const SceneView& s, uint2 ref, double t0, floa
     const double tm = (double)tmax;
     v.clipped = (v.h.k < 0) || (v.t1 >= tm);
     v.te = fmax(t0, fmin(v.t1, tm));
-    v.delta = (float)(v.te - t0);
-    v.tau = v.at.sigma > 0.0f ? v.at.sigma * v.delta : 0.0f;
-    v.alpha = -expm1f(-v.tau);
-    colour<DEG>(v.at, Y, v.c);
+    segment<DEG>(t0, Y, v);
 }
+
+// n.d of the face between cells with sites xi and xj, n = xj - xi: the same
+// rounding as the packed plane's normal and the scan's dot product.
+__device__ inline float face_den(const float* xi, const float* xj, float dx, float dy, float dz)
+{
+    const float nx = xj[0] - xi[0], ny = xj[1] - xi[1], nz = xj[2] - xi[2];
+    return fmaf(nz, dz, fmaf(ny, dy, nx * dx));
+}
+
+// Where a logged walk records its visits: visit n of ray r at [n * stride + r]
+// (step-major, so the lanes of a wavefront, which advance in lock step, write
+// contiguous words), the first `cap` visits only; tail[r] holds the row of the
+// cell after the last logged visit (where a longer walk resumes, or the cell
+// whose site the last exit gradient needs) and the number of visited cells.
+struct LogView {
+    uint32_t* code;
+    double* te;
+    int4* tail;
+    int32_t cap;
+    int64_t stride;
+};
+
+constexpr uint32_t kLogMoves = 1u << 31;    // the exit moves with its face (t0 <= t1 < t_max)
+constexpr uint32_t kLogClipped = 1u << 30;  // no front face or t1 >= t_max: the walk ended here
+constexpr uint32_t kLogCell = kLogClipped - 1u;
 
 // Algorithm 1 for one ray: start in `start`, take the nearest front face of
 // each cell, composite the segment with eq. (3)-(4) while T > eps.
-template <int DEG, bool BF16, bool TRACE>
+template <int DEG, bool BF16, bool TRACE, bool LOG = false>
 __device__ inline void walk_forward(const SceneView& s, float ox, float oy, float oz, float dx, float dy, float dz,
                                     float tmax, int start, float eps, int max_steps, int32_t* cells, float* t_exit,
-                                    int max_len, RayResult& res)
+                                    int max_len, RayResult& res, const LogView* lg = nullptr, int64_t r = 0)
 {
     res.C[0] = res.C[1] = res.C[2] = 0.0f;
     res.T = 1.0f;
     if (start < 0 || (int64_t)start >= s.n_sites) {
         res.status = -1;
+        if constexpr (LOG) lg->tail[r] = make_int4(0, 0, 0, 0);
         return;
     }
     float Y[sh_count(DEG)];
     sh_basis<DEG>(dx, dy, dz, Y);
     uint2 ref = s.row[start];
+    uint2 tail = ref;
     double t0 = 0.0;
     float T = 1.0f;
     int n = 0;
@@ -141,6 +176,9 @@ __device__ inline void walk_forward(const SceneView& s, float ox, float oy, floa
         if (n == max_steps) {
             res.status = -2;
             break;
+        }
+        if constexpr (LOG) {
+            if (n == lg->cap) tail = ref;
         }
         Visit<DEG> v;
         visit_cell<DEG, BF16>(s, ref, t0, tmax, ox, oy, oz, dx, dy, dz, Y, v);
@@ -155,6 +193,14 @@ __device__ inline void walk_forward(const SceneView& s, float ox, float oy, floa
                 t_exit[n] = (float)v.te;
             }
         }
+        if constexpr (LOG) {
+            if (n < lg->cap) {
+                const bool moves = !v.clipped && (v.t1 >= t0);
+                lg->code[n * lg->stride + r] =
+                    (uint32_t)ref_cell(ref) | (moves ? kLogMoves : 0u) | (v.clipped ? kLogClipped : 0u);
+                lg->te[n * lg->stride + r] = v.te;
+            }
+        }
         ++n;
         if (v.clipped) {
             res.status = n;
@@ -164,6 +210,10 @@ __device__ inline void walk_forward(const SceneView& s, float ox, float oy, floa
         t0 = v.te;
     }
     res.T = T;
+    if constexpr (LOG) {
+        if (n <= lg->cap) tail = ref;
+        lg->tail[r] = make_int4((int)tail.x, (int)tail.y, n, 0);
+    }
 }
 
 // Pinhole camera ray through the centre of pixel (px, py): direction

@@ -25,6 +25,12 @@
 //   p = o + t_n d, den = (x_j - x_i).d:  dt/dx_i = (p - x_i)/den,
 //   dt/dx_j = (x_j - p)/den   (geometry enters only through the segment
 //   widths, Sec. 3.1).
+// A training forward can log each visit (cell and flags, te in double) in a
+// step-major walk log; the backward then reads the visits instead of
+// repeating the face scans (same records, same te, so the same segments bit
+// for bit), and a second launch recomputes only the walks that outgrew the
+// log. The exit face's n.d is rebuilt from the two sites with the pack's
+// rounding, so both paths use the same value.
 // Each visit's gradients for one cell (3B SH values, density, site) form a
 // package that is emitted one iteration later, when the following visit has
 // fixed the exit gradient. Packages are summed across the wavefront per cell
@@ -45,16 +51,17 @@ __device__ inline int64_t ray_index()
     return xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
 }
 
-template <int DEG, bool BF16, bool TRACE>
+template <int DEG, bool BF16, bool TRACE, bool LOG>
 __global__ __launch_bounds__(kBlock) void k_forward(WalkArgs a)
 {
     const int64_t r = ray_index();
     if (r >= a.n_rays) return;
     RayResult res;
-    walk_forward<DEG, BF16, TRACE>(a.s, a.origin[3 * r], a.origin[3 * r + 1], a.origin[3 * r + 2], a.dir[3 * r],
-                                   a.dir[3 * r + 1], a.dir[3 * r + 2], a.t_max[r], a.start[r], a.eps, a.max_steps,
-                                   TRACE ? a.cells + r * a.max_len : nullptr,
-                                   TRACE ? a.t_exit + r * a.max_len : nullptr, a.max_len, res);
+    const LogView lg = {a.log_code, a.log_te, a.log_tail, a.log_cap, a.n_rays};
+    walk_forward<DEG, BF16, TRACE, LOG>(a.s, a.origin[3 * r], a.origin[3 * r + 1], a.origin[3 * r + 2],
+                                        a.dir[3 * r], a.dir[3 * r + 1], a.dir[3 * r + 2], a.t_max[r], a.start[r],
+                                        a.eps, a.max_steps, TRACE ? a.cells + r * a.max_len : nullptr,
+                                        TRACE ? a.t_exit + r * a.max_len : nullptr, a.max_len, res, &lg, r);
     a.rgb[3 * r + 0] = res.C[0];
     a.rgb[3 * r + 1] = res.C[1];
     a.rgb[3 * r + 2] = res.C[2];
@@ -199,7 +206,7 @@ __device__ inline void exit_offsets(double t, float ox, float oy, float oz, floa
     }
 }
 
-template <int DEG, bool BF16, bool REDUCE>
+template <int DEG, bool BF16, bool REDUCE, bool LOG>
 __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
 {
     constexpr int B = sh_count(DEG);
@@ -220,6 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
     float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 1, tmax = 0;
     float g[3] = {0, 0, 0}, gT = 0, Cout[3] = {0, 0, 0}, Tfin = 1;
     uint2 ref = make_uint2(0, 0);
+    int n_total = 0;  // visited cells of the logged forward
     if (r < a.n_rays) {
         const int start = a.start[r];
         if (start >= 0 && (int64_t)start < a.s.n_sites) {
@@ -240,6 +248,17 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
             Cout[2] = a.rgb_in[3 * r + 2];
             Tfin = a.t_final_in[r];
             ref = a.s.row[start];
+            if (a.log_tail) {
+                // a logged walk: the log kernel takes the rays whose visits
+                // are all in the log, the recompute kernel the longer ones
+                const int4 tl = a.log_tail[r];
+                const bool in_log = tl.z >= 0 && tl.z <= a.log_cap;
+                if (LOG) {
+                    ref = make_uint2((uint32_t)tl.x, (uint32_t)tl.y);  // the cell after the last visit
+                    n_total = tl.z;
+                }
+                if (in_log != LOG) state = 3;
+            }
         }
     }
     float Y[B];
@@ -251,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
     // previous visit, awaiting its exit gradient
     bool have_prev = false, p_moves = false;
     Package prev = {0, {0, 0, 0}, 0, {0, 0, 0}};
-    float p_site[3] = {0, 0, 0}, p_den = 1, p_sdt = 0;
+    float p_site[3] = {0, 0, 0}, p_sdt = 0;
     double p_t1 = 0.0;
     // entry term of the cell after the last visit
     Package entry = {0, {0, 0, 0}, 0, {0, 0, 0}};
@@ -261,10 +280,31 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
         bool has = false;
         Package out = prev;
         if (state == 0) {
-            bool stop = !(T > a.eps) || (n == a.max_steps);
+            bool stop;
+            if constexpr (LOG)
+                stop = (n == n_total);
+            else
+                stop = !(T > a.eps) || (n == a.max_steps);
             if (!stop) {
                 Visit<DEG> v;
-                visit_cell<DEG, BF16>(a.s, ref, t0, tmax, ox, oy, oz, dx, dy, dz, Y, v);
+                int cell;
+                bool moves;
+                if constexpr (LOG) {
+                    // the visit as the forward logged it: same record, same te,
+                    // so the same segment bit for bit, without the face scan
+                    const uint32_t code = a.log_code[(int64_t)n * a.n_rays + r];
+                    v.te = a.log_te[(int64_t)n * a.n_rays + r];
+                    cell = min((int)(code & kLogCell), (int)(a.s.n_sites - 1));
+                    load_record<DEG, BF16>(a.s.rec, cell, v.at);
+                    v.t1 = v.te;  // a moving exit is unclamped: te = t1
+                    v.clipped = (code & kLogClipped) != 0;
+                    moves = (code & kLogMoves) != 0;
+                    segment<DEG>(t0, Y, v);
+                } else {
+                    cell = ref_cell(ref);
+                    visit_cell<DEG, BF16>(a.s, ref, t0, tmax, ox, oy, oz, dx, dy, dz, Y, v);
+                    moves = !v.clipped && (v.t1 >= t0);
+                }
                 const Attr<DEG>& at = v.at;
                 const float w = T * v.alpha;
                 Cacc[0] = fmaf(w, v.c[0], Cacc[0]);
@@ -280,7 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
                     if (p_moves) {
                         // exit point relative to both sites, in double: p - x = (o - x) + t d
                         const float gt = p_sdt - sdt;
-                        const float s = gt / p_den;
+                        const float s = gt / face_den(p_site, at.site, dx, dy, dz);
                         float pa[3], pb[3];
                         exit_offsets(p_t1, ox, oy, oz, dx, dy, dz, p_site, at.site, pa, pb);
                         prev.dx[0] = fmaf(s, pa[0], prev.dx[0]);
@@ -293,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
                     has = true;
                     out = prev;
                 }
-                prev.cell = ref_cell(ref);
+                prev.cell = cell;
                 prev.gw[0] = g[0] * w;
                 prev.gw[1] = g[1] * w;
                 prev.gw[2] = g[2] * w;
@@ -305,26 +345,27 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
                 p_site[1] = at.site[1];
                 p_site[2] = at.site[2];
                 p_t1 = v.t1;
-                p_den = v.h.den;
                 p_sdt = sdt;
-                p_moves = !v.clipped && (v.t1 >= t0);
+                p_moves = moves;
                 have_prev = true;
                 T = Tn;
                 ++n;
                 if (v.clipped) {
                     stop = true;
                 } else {
-                    ref = v.h.next;
+                    if (!LOG) ref = v.h.next;
                     t0 = v.te;
                 }
             }
             if (stop) {
                 if (have_prev && p_moves) {
                     // the last exit moved with its face but no segment follows it
-                    const float s = p_sdt / p_den;
                     float xj[3], pa[3], pb[3];
-                    entry.cell = ref_cell(ref);
+                    // (kept in range, so that a log not written by the forward
+                    // cannot address outside the scene)
+                    entry.cell = min(ref_cell(ref), (int)(a.s.n_sites - 1));
                     load_site<DEG, BF16>(a.s.rec, entry.cell, xj);
+                    const float s = p_sdt / face_den(p_site, xj, dx, dy, dz);
                     exit_offsets(p_t1, ox, oy, oz, dx, dy, dz, p_site, xj, pa, pb);
                     prev.dx[0] = fmaf(s, pa[0], prev.dx[0]);
                     prev.dx[1] = fmaf(s, pa[1], prev.dx[1]);
@@ -364,16 +405,28 @@ static hipError_t launch_walk_t(WalkKind kind, const WalkArgs& a, hipStream_t st
     const dim3 grid((unsigned)blocks), block(kBlock);
     switch (kind) {
     case kForward:
-        hipLaunchKernelGGL((k_forward<DEG, BF16, false>), grid, block, 0, stream, a);
+        hipLaunchKernelGGL((k_forward<DEG, BF16, false, false>), grid, block, 0, stream, a);
         break;
     case kTrace:
-        hipLaunchKernelGGL((k_forward<DEG, BF16, true>), grid, block, 0, stream, a);
+        hipLaunchKernelGGL((k_forward<DEG, BF16, true, false>), grid, block, 0, stream, a);
+        break;
+    case kForwardLog:
+        hipLaunchKernelGGL((k_forward<DEG, BF16, false, true>), grid, block, 0, stream, a);
         break;
     case kBackwardReduce:
-        hipLaunchKernelGGL((k_backward<DEG, BF16, true>), grid, block, 0, stream, a);
+        hipLaunchKernelGGL((k_backward<DEG, BF16, true, false>), grid, block, 0, stream, a);
         break;
     case kBackwardAtomic:
-        hipLaunchKernelGGL((k_backward<DEG, BF16, false>), grid, block, 0, stream, a);
+        hipLaunchKernelGGL((k_backward<DEG, BF16, false, false>), grid, block, 0, stream, a);
+        break;
+    case kBackwardLogReduce:
+        // rays within the log, then the rays whose walks outgrew it (recomputed)
+        hipLaunchKernelGGL((k_backward<DEG, BF16, true, true>), grid, block, 0, stream, a);
+        hipLaunchKernelGGL((k_backward<DEG, BF16, true, false>), grid, block, 0, stream, a);
+        break;
+    case kBackwardLogAtomic:
+        hipLaunchKernelGGL((k_backward<DEG, BF16, false, true>), grid, block, 0, stream, a);
+        hipLaunchKernelGGL((k_backward<DEG, BF16, false, false>), grid, block, 0, stream, a);
         break;
     }
     return hipGetLastError();

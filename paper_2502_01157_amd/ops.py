@@ -16,6 +16,7 @@ from . import _lib as L
 
 DEFAULT_EPS = 1e-4
 DEFAULT_MAX_STEPS = 8192
+DEFAULT_LOG_CAPACITY = 256  # visits per ray saved by a differentiable forward (12 B each)
 
 
 def _stream(device: Optional[torch.device] = None) -> ctypes.c_void_p:
@@ -153,9 +154,31 @@ def raygen(pose12, fov_deg: float, width: int, height: int, bound: tuple, start:
     return o, d, t, s, px
 
 
+class WalkLog:
+    """Device buffers of a walk log (``rf_walk_log``): per ray, the first
+    ``capacity`` visits of the forward walk (cell and flags, exit distance in
+    double) and a tail record, so that the backward skips the face scans.
+    Takes ``n_rays * (12 * capacity + 16)`` bytes."""
+
+    def __init__(self, n_rays: int, capacity: int, device=None):
+        if capacity < 0:
+            raise ValueError("capacity must be >= 0")
+        self.n_rays, self.capacity = int(n_rays), int(capacity)
+        self.code = torch.empty((self.capacity, self.n_rays), dtype=torch.int32, device=device)
+        self.t_exit = torch.empty((self.capacity, self.n_rays), dtype=torch.float64, device=device)
+        self.tail = torch.empty((self.n_rays, 4), dtype=torch.int32, device=device)
+        self.desc = L.WalkLog(_ptr(self.code) if self.code.numel() else None,
+                              _ptr(self.t_exit) if self.t_exit.numel() else None,
+                              _ptr(self.tail) if self.tail.numel() else None, self.capacity)
+
+    def check(self, n_rays: int) -> None:
+        if n_rays != self.n_rays:
+            raise ValueError(f"walk log holds {self.n_rays} rays, the call has {n_rays}")
+
+
 def render_forward(scene: PackedScene, origin, direction, t_max, start, eps: float = DEFAULT_EPS,
-                   max_steps: int = DEFAULT_MAX_STEPS, out=None):
-    """rgb [R,3], t_final [R], steps [R] (int32; < 0 flags RF_RAY_*)."""
+                   max_steps: int = DEFAULT_MAX_STEPS, out=None, log: Optional[WalkLog] = None):
+    """rgb [R,3], t_final [R], steps [R] (int32; < 0 flags RF_RAY_*); also fills ``log`` if given."""
     R = int(direction.shape[0])
     dev = direction.device
     if out is None:
@@ -165,8 +188,14 @@ def render_forward(scene: PackedScene, origin, direction, t_max, start, eps: flo
     rgb, tf, steps = out
     rays = _rays(origin, direction, t_max, start)
     p = _params(eps, max_steps)
-    L.check(L.lib().rf_render_forward(ctypes.byref(scene.desc), ctypes.byref(rays), ctypes.byref(p),
-                                      rgb.data_ptr(), tf.data_ptr(), steps.data_ptr(), _stream(dev)))
+    if log is None:
+        L.check(L.lib().rf_render_forward(ctypes.byref(scene.desc), ctypes.byref(rays), ctypes.byref(p),
+                                          rgb.data_ptr(), tf.data_ptr(), steps.data_ptr(), _stream(dev)))
+    else:
+        log.check(R)
+        L.check(L.lib().rf_render_forward_logged(ctypes.byref(scene.desc), ctypes.byref(rays), ctypes.byref(p),
+                                                 rgb.data_ptr(), tf.data_ptr(), steps.data_ptr(),
+                                                 ctypes.byref(log.desc), _stream(dev)))
     return rgb, tf, steps
 
 
@@ -189,8 +218,11 @@ def render_trace(scene: PackedScene, origin, direction, t_max, start, eps: float
 
 def render_backward(scene: PackedScene, origin, direction, t_max, start, rgb, t_final, grad_rgb,
                     grad_t_final=None, eps: float = DEFAULT_EPS, max_steps: int = DEFAULT_MAX_STEPS,
-                    mode: int = 0, grads=None):
-    """Gradients (sites [N,3], density [N], sh [N,B,3]); accumulated into ``grads`` if given."""
+                    mode: int = 0, grads=None, log: Optional[WalkLog] = None):
+    """Gradients (sites [N,3], density [N], sh [N,B,3]); accumulated into ``grads`` if given.
+
+    With ``log`` (filled by ``render_forward`` on the same scene, rays and
+    parameters) the visits are read from the log instead of recomputed."""
     R = int(direction.shape[0])
     dev = direction.device
     n, B = scene.n_sites, sh_count(scene.sh_degree)
@@ -209,10 +241,17 @@ def render_backward(scene: PackedScene, origin, direction, t_max, start, rgb, t_
     _dev(gsh, torch.float32, (n, B, 3), "grad_sh")
     rays = _rays(origin, direction, t_max, start)
     p = _params(eps, max_steps)
-    L.check(L.lib().rf_render_backward(ctypes.byref(scene.desc), ctypes.byref(rays), ctypes.byref(p),
-                                       rgb.data_ptr(), t_final.data_ptr(), grad_rgb.data_ptr(),
-                                       _ptr(grad_t_final), gs.data_ptr(), gd.data_ptr(), gsh.data_ptr(),
-                                       int(mode), _stream(dev)))
+    if log is None:
+        L.check(L.lib().rf_render_backward(ctypes.byref(scene.desc), ctypes.byref(rays), ctypes.byref(p),
+                                           rgb.data_ptr(), t_final.data_ptr(), grad_rgb.data_ptr(),
+                                           _ptr(grad_t_final), gs.data_ptr(), gd.data_ptr(), gsh.data_ptr(),
+                                           int(mode), _stream(dev)))
+    else:
+        log.check(R)
+        L.check(L.lib().rf_render_backward_logged(ctypes.byref(scene.desc), ctypes.byref(rays), ctypes.byref(p),
+                                                  rgb.data_ptr(), t_final.data_ptr(), grad_rgb.data_ptr(),
+                                                  _ptr(grad_t_final), ctypes.byref(log.desc), gs.data_ptr(),
+                                                  gd.data_ptr(), gsh.data_ptr(), int(mode), _stream(dev)))
     return gs, gd, gsh
 
 
@@ -223,18 +262,22 @@ class RadFoamRender(torch.autograd.Function):
             attr_dtype, eps, max_steps) -> (rgb [R,3], t_final [R])
 
     Packs the scene (face planes from the current sites, attributes in
-    ``attr_dtype``), walks every ray, and saves what the recomputing backward
-    needs. Gradients flow to sites, density and sh; none to the rays or the
-    adjacency.
+    ``attr_dtype``), walks every ray, and saves a walk log of the first
+    ``log_capacity`` visits per ray (0: none; the backward then recomputes
+    every walk). Gradients flow to sites, density and sh; none to the rays or
+    the adjacency.
     """
 
     @staticmethod
     def forward(ctx, sites, density, sh, off, idx, origin, direction, t_max, start, sh_degree: int = 3,
-                attr_dtype: str = "f32", eps: float = DEFAULT_EPS, max_steps: int = DEFAULT_MAX_STEPS):
+                attr_dtype: str = "f32", eps: float = DEFAULT_EPS, max_steps: int = DEFAULT_MAX_STEPS,
+                log_capacity: int = DEFAULT_LOG_CAPACITY):
         sites_c, dens_c, sh_c = sites.detach().contiguous(), density.detach().contiguous(), sh.detach().contiguous()
         scene = PackedScene(sites_c, off, idx, dens_c, sh_c, sh_degree, attr_dtype, validate=False)
-        rgb, tf, steps = render_forward(scene, origin, direction, t_max, start, eps, max_steps)
+        log = WalkLog(int(direction.shape[0]), log_capacity, direction.device) if log_capacity > 0 else None
+        rgb, tf, steps = render_forward(scene, origin, direction, t_max, start, eps, max_steps, log=log)
         ctx.scene = scene
+        ctx.log = log
         ctx.hyper = (eps, max_steps)
         ctx.save_for_backward(origin, direction, t_max, start, rgb, tf)
         ctx.mark_non_differentiable(steps)
@@ -248,12 +291,15 @@ class RadFoamRender(torch.autograd.Function):
             grad_rgb = torch.zeros_like(rgb)
         gs, gd, gsh = render_backward(ctx.scene, origin, direction, t_max, start, rgb, tf,
                                       grad_rgb.contiguous().float(),
-                                      None if grad_tf is None else grad_tf.contiguous().float(), eps, max_steps)
-        return gs, gd, gsh, None, None, None, None, None, None, None, None, None, None
+                                      None if grad_tf is None else grad_tf.contiguous().float(), eps, max_steps,
+                                      log=ctx.log)
+        ctx.log = None
+        return gs, gd, gsh, None, None, None, None, None, None, None, None, None, None, None
 
 
 def render(sites, density, sh, off, idx, origin, direction, t_max, start, sh_degree: int = 3,
-           attr_dtype: str = "f32", eps: float = DEFAULT_EPS, max_steps: int = DEFAULT_MAX_STEPS):
+           attr_dtype: str = "f32", eps: float = DEFAULT_EPS, max_steps: int = DEFAULT_MAX_STEPS,
+           log_capacity: int = DEFAULT_LOG_CAPACITY):
     """Autograd entry point: returns (rgb, t_final, steps)."""
     return RadFoamRender.apply(sites, density, sh, off, idx, origin, direction, t_max, start, sh_degree,
-                               attr_dtype, eps, max_steps)
+                               attr_dtype, eps, max_steps, log_capacity)

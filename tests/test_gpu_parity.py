@@ -239,7 +239,7 @@ def test_edge_cases(rf, clustered):
 # a4/a5: backward walk and its wavefront reduction
 # ---------------------------------------------------------------------------
 
-def check_backward(rf, scene, rays, eps, mode=0, dtype="f32", with_gt=True, seed=0):
+def check_backward(rf, scene, rays, eps, mode=0, dtype="f32", with_gt=True, seed=0, log_capacity=None):
     import torch
 
     osc = oracle.OracleScene.from_scene(scene)
@@ -255,10 +255,11 @@ def check_backward(rf, scene, rays, eps, mode=0, dtype="f32", with_gt=True, seed
     ref_g = oracle.backward(osc, *rays, g, gT, eps=eps)
     p, _ = packed(rf, scene, dtype)
     o, d, t, s = to_dev(*rays)
-    rgb, tf, steps = rf.render_forward(p, o, d, t, s, eps=eps)
+    log = None if log_capacity is None else rf.WalkLog(len(rays[1]), log_capacity, o.device)
+    rgb, tf, steps = rf.render_forward(p, o, d, t, s, eps=eps, log=log)
     gg, = to_dev(g)
     gt_dev = to_dev(gT)[0] if with_gt else None
-    gs, gd, gsh = rf.render_backward(p, o, d, t, s, rgb, tf, gg, gt_dev, eps=eps, mode=mode)
+    gs, gd, gsh = rf.render_backward(p, o, d, t, s, rgb, tf, gg, gt_dev, eps=eps, mode=mode, log=log)
     torch.cuda.synchronize()
     errs = [grad_err(x.cpu().numpy(), y) for x, y in zip((gs, gd, gsh), ref_g)]
     assert max(errs) <= GRAD_RTOL, errs
@@ -298,6 +299,99 @@ def test_backward_modes_agree(rf, clustered):
     b = rf.render_backward(p, o, d, t, s, rgb, tf, g, mode=1)
     for x, y in zip(a, b):
         assert grad_err(x.cpu().numpy(), y.cpu().numpy()) < 1e-5
+
+
+@pytest.mark.parametrize("cap", [256, "half", 1, 0])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_logged_walk(rf, clustered, dtype, cap):
+    """The logged forward returns the plain forward's outputs bit for bit and
+    logs exactly the traced visits; the logged backward gives the recomputing
+    backward's gradients, for a log that holds every walk (256), about half of
+    them (the rest resume from the tail), one visit, or none."""
+    import torch
+
+    scene, cam, _ = clustered
+    rays = camera_rays(scene, cam)[:4]
+    R = len(rays[2])
+    p, _ = packed(rf, scene, dtype)
+    o, d, t, s = to_dev(*rays)
+    plain = rf.render_forward(p, o, d, t, s)
+    steps_np = plain[2].cpu().numpy()
+    if cap == "half":
+        cap = int(np.median(steps_np))
+    log = rf.WalkLog(R, cap, o.device)
+    out = rf.render_forward(p, o, d, t, s, log=log)
+    for x, y in zip(plain, out):
+        assert torch.equal(x, y)
+    if cap == int(np.median(steps_np)):
+        assert (steps_np > cap).any() and (steps_np <= cap).any()
+
+    tail = log.tail.cpu().numpy()
+    np.testing.assert_array_equal(tail[:, 2], steps_np)  # every ray here starts in a cell and ends normally
+    tr = rf.render_trace(p, o, d, t, s, max_len=1024)
+    cells, t_exit = tr["cells"].cpu().numpy(), tr["t_exit"].cpu().numpy()
+    code = log.code.cpu().numpy().view(np.uint32)
+    te = log.t_exit.cpu().numpy()
+    for r in range(R):
+        n = min(int(steps_np[r]), cap)
+        np.testing.assert_array_equal(code[:n, r] & ((1 << 30) - 1), cells[r, :n])
+        np.testing.assert_array_equal(te[:n, r].astype(np.float32), t_exit[r, :n])
+        clipped = (code[:n, r] >> 30) & 1
+        assert not clipped[: max(n - 1, 0)].any()
+        if n == steps_np[r] and n > 0:  # the last visit is in the log: clipped iff it ends at t_max
+            assert bool(clipped[n - 1]) == (te[n - 1, r] == np.float64(rays[2][r]))
+
+    g = torch.randn_like(out[0])
+    gT = torch.randn_like(out[1])
+    for mode in (0, 1):
+        a = rf.render_backward(p, o, d, t, s, out[0], out[1], g, gT, mode=mode)
+        b = rf.render_backward(p, o, d, t, s, out[0], out[1], g, gT, mode=mode, log=log)
+        for x, y in zip(b, a):
+            assert grad_err(x.cpu().numpy(), y.cpu().numpy()) < 1e-5
+
+
+@pytest.mark.parametrize("cap", [256, 20])
+def test_logged_backward_matches_oracle(rf, clustered, cap):
+    scene, cam, _ = clustered
+    check_backward(rf, scene, camera_rays(scene, cam)[:4], eps=1e-4, log_capacity=cap)
+    rays = inside_rays(scene, np.random.default_rng(7), 777, -0.95, 0.95)
+    dense = _Deg(scene, 3)
+    dense.density = scene.density * 40.0
+    check_backward(rf, dense, rays, eps=1e-2, seed=2, log_capacity=cap)
+
+
+def test_logged_walk_argument_errors(rf, clustered):
+    import ctypes
+
+    import torch
+
+    from paper_2502_01157_amd import _lib as L
+    from paper_2502_01157_amd.ops import _params, _rays, _stream
+
+    scene, cam, _ = clustered
+    p, _ = packed(rf, scene)
+    o, d, t, s = to_dev(*camera_rays(scene, cam)[:4])
+    R = int(t.shape[0])
+    with pytest.raises(ValueError):
+        rf.WalkLog(R, -1, o.device)
+    with pytest.raises(ValueError):
+        rf.render_forward(p, o, d, t, s, log=rf.WalkLog(R + 1, 8, o.device))
+    rgb, tf, steps = (torch.empty((R, 3), device=o.device), torch.empty(R, device=o.device),
+                      torch.empty(R, dtype=torch.int32, device=o.device))
+    rays, prm = _rays(o, d, t, s), _params(1e-4, 8192)
+    lib = L.lib()
+    args = (ctypes.byref(p.desc), ctypes.byref(rays), ctypes.byref(prm), rgb.data_ptr(), tf.data_ptr(),
+            steps.data_ptr())
+    assert lib.rf_render_forward_logged(*args, None, _stream(o.device)) == L.RF_ERR_INVALID_ARG
+    bad = rf.WalkLog(R, 4, o.device)
+    bad.desc.capacity = -1
+    assert lib.rf_render_forward_logged(*args, ctypes.byref(bad.desc), _stream(o.device)) == L.RF_ERR_INVALID_ARG
+    bad.desc.capacity = 4
+    bad.desc.t_exit = bad.t_exit.data_ptr() + 4  # misaligned doubles
+    assert lib.rf_render_forward_logged(*args, ctypes.byref(bad.desc), _stream(o.device)) == L.RF_ERR_INVALID_ARG
+    bad.desc.t_exit = None
+    assert lib.rf_render_forward_logged(*args, ctypes.byref(bad.desc), _stream(o.device)) == L.RF_ERR_INVALID_ARG
+    torch.cuda.synchronize()
 
 
 def test_autograd_function(rf, clustered):
