@@ -56,6 +56,7 @@ def _load():
         lib.orc_raygen.argtypes = [P, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P]
         lib.orc_face_planes.argtypes = [P, P, P, ctypes.c_int64, P]
         lib.orc_bf16_round.argtypes = [P, P, ctypes.c_int64]
+        lib.orc_nearest_site.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P]
         lib.orc_bf16_round.restype = None
         lib.orc_check_csr.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64]
         lib.orc_forward.argtypes = [ctypes.POINTER(_Scene), P, P, P, P, ctypes.c_int64, ctypes.c_double,
@@ -161,6 +162,18 @@ def face_planes(sites, off, idx) -> np.ndarray:
     out = np.empty((i.shape[0], 4))
     _check(_load().orc_face_planes(_ptr(s), _ptr(o), _ptr(i), s.shape[0], _ptr(out)), "face_planes")
     return out
+
+
+def nearest_site(sites, points, return_gap: bool = False):
+    """Index of each point's nearest site (eq. (5)) by exhaustive FP64 search,
+    lowest index on exact ties; with ``return_gap`` also the runner-up's
+    relative squared-distance gap."""
+    s = _f64(sites).reshape(-1, 3)
+    p = _f64(points).reshape(-1, 3)
+    out = np.empty(len(p), dtype=np.int32)
+    gap = np.empty(len(p), dtype=np.float64)
+    _check(_load().orc_nearest_site(_ptr(s), len(s), _ptr(p), len(p), _ptr(out), _ptr(gap)), "nearest_site")
+    return (out, gap) if return_gap else out
 
 
 def bf16_round(x) -> np.ndarray:

@@ -194,6 +194,37 @@ int orc_face_planes(const double *sites, const int32_t *off, const int32_t *idx,
     return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* The cell containing a point (eq. (5)): its nearest site, by exhaustive   */
+/* search over all sites; the lowest index wins an exact tie. gap (if not   */
+/* NULL) receives (d2_second - d2_best) / d2_second, the relative distance  */
+/* of the runner-up (0 for an exact tie, 1 when the point is a site).       */
+/* ------------------------------------------------------------------------ */
+int orc_nearest_site(const double *sites, int64_t n_sites, const double *points, int64_t n_points, int32_t *out,
+                     double *gap)
+{
+    if (!sites || n_sites < 1 || n_points < 0 || (n_points > 0 && (!points || !out))) return ORC_EINVAL;
+    for (int64_t q = 0; q < n_points; ++q) {
+        const double *p = points + 3 * q;
+        int64_t best = -1;
+        double d_best = INFINITY, d_second = INFINITY;
+        for (int64_t i = 0; i < n_sites; ++i) {
+            const double dx = p[0] - sites[3 * i], dy = p[1] - sites[3 * i + 1], dz = p[2] - sites[3 * i + 2];
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            if (d2 < d_best) {
+                d_second = d_best;
+                d_best = d2;
+                best = i;
+            } else if (d2 < d_second) {
+                d_second = d2;
+            }
+        }
+        out[q] = (int32_t)best;
+        if (gap) gap[q] = d_second > 0.0 ? (d_second - d_best) / d_second : 0.0;
+    }
+    return ORC_OK;
+}
+
 /* IEEE binary32 -> bfloat16 with round-to-nearest-even (NaN stays NaN). */
 void orc_bf16_round(const float *in, uint16_t *out, int64_t n)
 {

@@ -554,3 +554,34 @@ def test_site_gradient_sums_match_translation():
         Lm = _loss(osc, o + e, d, tmax, start, g, 0 * tmax, 0.0)
         fd = (Lp - Lm) / (2 * h)                 # = sum_i dL/dx_i (translation of all sites)
         assert abs(fd - gs[:, a].sum()) < 1e-6 * max(1.0, abs(fd))
+
+
+# ---------------------------------------------------------------------------
+# nearest site (the cell of a point, eq. (5)): start-cell location
+# ---------------------------------------------------------------------------
+
+def test_nearest_site_by_hand_on_a_line():
+    # sites at x = 0, 1, 3; the bisectors are x = 0.5 and x = 2
+    sites = np.array([[0.0, 0, 0], [1.0, 0, 0], [3.0, 0, 0]])
+    q = np.array([[0.4, 0, 0], [0.5, 0, 0], [0.6, 0, 0], [2.0, 0, 0], [2.1, 0, 0], [3.0, 0, 0], [-5.0, 2, 0]])
+    idx, gap = oracle.nearest_site(sites, q, return_gap=True)
+    np.testing.assert_array_equal(idx, [0, 0, 1, 1, 2, 2, 0])  # exact ties keep the lower index
+    # 0.6: d2 = 0.36 to site 0 and 0.16 to site 1; a point on a bisector has gap 0; a site has gap 1
+    np.testing.assert_allclose(gap[[1, 2, 3, 5]], [0.0, (0.36 - 0.16) / 0.36, 0.0, 1.0])
+
+
+def test_nearest_site_matches_kdtree():
+    from scipy.spatial import cKDTree
+
+    scene = synth.small_scene("clustered", 5000, seed=41, sh_deg=0)
+    rng = np.random.default_rng(42)
+    q = np.concatenate([rng.uniform(-1.2, 1.2, size=(3000, 3)), scene.sites[:50].astype(np.float64),
+                        rng.standard_normal((200, 3)) * 10.0])
+    idx, gap = oracle.nearest_site(scene.sites, q, return_gap=True)
+    dist, ref = cKDTree(scene.sites.astype(np.float64)).query(q, k=1)
+    clear = gap > 1e-9
+    assert clear.mean() > 0.99
+    np.testing.assert_array_equal(idx[clear], ref[clear])
+    mine = np.linalg.norm(q - scene.sites[idx].astype(np.float64), axis=1)
+    np.testing.assert_allclose(mine, dist, rtol=1e-12, atol=0)
+    np.testing.assert_array_equal(idx[3000:3050], np.arange(50))
