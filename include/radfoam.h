@@ -221,6 +221,23 @@ rf_status rf_render_backward(const rf_packed_scene *scene, const rf_rays *rays, 
                              int32_t mode, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Start-cell location: the cell containing each point, i.e. its nearest
+ * site (eq. (5)); Algorithm 1 starts the walk of a ray in the cell of its
+ * origin. A greedy walk over the Delaunay graph from seed[q] (cell 0 when
+ * seed is NULL) moves to the neighbour nearest the point while one is
+ * nearer, first in FP32 across the bisector planes, then with squared
+ * distances in double (ties go to the lower index). On a Delaunay graph a
+ * site that is not the nearest always has a nearer neighbour, so the walk
+ * ends at the nearest site; it takes O(distance / cell size) steps.
+ *   points  float[n_points][3]  device
+ *   seed    int32[n_points]     device, nullable
+ *   cells   int32[n_points]     out: nearest site; -1 seed out of range;
+ *                               -2 max_steps steps were not enough
+ * ---------------------------------------------------------------------- */
+rf_status rf_locate(const rf_packed_scene *scene, const float *points, int64_t n_points, const int32_t *seed,
+                    int32_t max_steps, int32_t *cells, void *stream);
+
+/* ------------------------------------------------------------------------
  * Walk log: what the backward needs of each visit, saved by the forward so
  * that the backward (Sec. 3.1 gradients, in the forward order of Algorithm 1)
  * does not repeat the face scans. Step-major: visit n (0-based) of ray r is
@@ -297,7 +314,10 @@ rf_status rf_packed_attributes(const rf_packed_scene *scene, float *density, flo
  * rf_server_submit admits a request immediately or returns RF_ERR_BUSY: it
  * needs a free slot (at most max_inflight <= 64 requests in flight) and W*H*16
  * contiguous bytes of the pool (pool_bytes). Callers that need FIFO order keep
- * their own queue and retry its head.
+ * their own queue and retry its head. start_cell is the cell containing the
+ * camera position; with start_cell < 0 the server locates it on the device
+ * (as rf_locate, seeded from a 16^3 grid of cells located over the bound when
+ * the server is created) before the request's first tiles run.
  * rf_server_poll lists finished requests not yet collected; rf_server_result
  * copies one into `rgba` (host memory, >= W*H*16 bytes; NULL discards it) and
  * frees its slot and pool range. rf_server_destroy finishes admitted requests,

@@ -18,6 +18,7 @@ from .ops import (  # noqa: E402,F401
     PackedScene,
     RadFoamRender,
     WalkLog,
+    locate,
     raygen,
     render,
     render_backward,

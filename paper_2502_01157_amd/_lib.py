@@ -108,11 +108,12 @@ def lib() -> ctypes.CDLL:
         L.rf_render_backward_logged.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Rays),
                                                 ctypes.POINTER(Params), P, P, P, P, ctypes.POINTER(WalkLog), P, P,
                                                 P, ctypes.c_int32, P]
+        L.rf_locate.argtypes = [ctypes.POINTER(PackedSceneDesc), P, ctypes.c_int64, P, ctypes.c_int32, P, P]
         L.rf_packed_planes.argtypes = [ctypes.POINTER(PackedSceneDesc), P, P]
         L.rf_packed_attributes.argtypes = [ctypes.POINTER(PackedSceneDesc), P, P, P]
         for name in ("rf_packed_bytes", "rf_pack_scene", "rf_packed_errors", "rf_raygen", "rf_render_forward",
                      "rf_render_trace", "rf_render_backward", "rf_render_forward_logged",
-                     "rf_render_backward_logged", "rf_packed_planes", "rf_packed_attributes"):
+                     "rf_render_backward_logged", "rf_locate", "rf_packed_planes", "rf_packed_attributes"):
             getattr(L, name).restype = st
         L.rf_server_create.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Params),
                                        ctypes.POINTER(BoundDesc), ctypes.c_size_t, ctypes.c_int32,

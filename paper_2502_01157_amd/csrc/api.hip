@@ -367,6 +367,28 @@ rf_status rf_render_backward_logged(const rf_packed_scene* scene, const rf_rays*
                       "logged backward walk");
 }
 
+rf_status rf_locate(const rf_packed_scene* scene, const float* points, int64_t n_points, const int32_t* seed,
+                    int32_t max_steps, int32_t* cells, void* stream)
+{
+    rf_status st;
+    if ((st = check_packed(scene)) != RF_OK) return st;
+    if (n_points < 0 || n_points > ((int64_t)1 << 37))
+        return fail(RF_ERR_INVALID_ARG, "n_points = %lld out of range", (long long)n_points);
+    if (n_points > 0 && (!points || !cells)) return fail(RF_ERR_INVALID_ARG, "points or cells is NULL");
+    if (max_steps < 1) return fail(RF_ERR_INVALID_ARG, "max_steps must be >= 1");
+    rf::LocateArgs a;
+    memset(&a, 0, sizeof a);
+    a.s = view(scene);
+    a.points = points;
+    a.seed = seed;
+    a.n_points = n_points;
+    a.max_steps = max_steps;
+    a.cells = cells;
+    return hip_status(rf::launch_locate(scene->sh_degree, scene->attr_dtype == RF_BF16, a,
+                                        static_cast<hipStream_t>(stream)),
+                      "locate");
+}
+
 rf_status rf_packed_planes(const rf_packed_scene* scene, float* planes, void* stream)
 {
     rf_status st = check_packed(scene);

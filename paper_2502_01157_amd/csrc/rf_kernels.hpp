@@ -77,6 +77,21 @@ struct RaygenArgs {
     int32_t* pixel;
 };
 
+struct LocateArgs {
+    SceneView s;
+    const float* points;  // [n_points][3]
+    const int32_t* seed;  // [n_points], or null: the seed grid's cell, or cell 0 without a grid
+    int64_t n_points;
+    int32_t max_steps;
+    int32_t* cells;       // [n_points] nearest site, -1 bad seed, -2 max_steps reached
+    // optional seed grid: grid_n^3 located cells of a regular grid over
+    // [grid_lo, grid_lo + grid_n / grid_inv), x fastest
+    const int32_t* grid;
+    int32_t grid_n;
+    float grid_lo[3];
+    float grid_inv[3];
+};
+
 enum WalkKind {
     kForward = 0,
     kTrace = 1,
@@ -93,6 +108,7 @@ void set_error(const char* msg);
 hipError_t launch_walk(WalkKind kind, int sh_degree, bool bf16, const WalkArgs& a, hipStream_t stream);
 hipError_t launch_pack(int sh_degree, bool bf16, const PackArgs& a, hipStream_t stream);
 hipError_t launch_raygen(const RaygenArgs& a, hipStream_t stream);
+hipError_t launch_locate(int sh_degree, bool bf16, const LocateArgs& a, hipStream_t stream);
 hipError_t launch_unpack(int sh_degree, bool bf16, const SceneView& s, float* planes_out, float* density_out,
                          float* sh_out, hipStream_t stream);
 

@@ -44,6 +44,7 @@ constexpr int kMaxSlots = 64;           // in-flight requests
 constexpr int kMaxBatchTiles = 8192;    // tiles per launch (524,288 rays)
 constexpr int kLaunchesInFlight = 2;
 constexpr int kLocalTileBits = 25;      // descriptor = slot << 25 | tile within the request
+constexpr int kSeedGrid = 16;           // seed grid for locating camera cells on the device
 
 struct ReqRecord {
     float rot[9];
@@ -128,6 +129,8 @@ struct rf_server {
     size_t pool_floats = 0;
     rf::ReqRecord* dev_reqs = nullptr;    // device table
     rf::ReqRecord* host_reqs = nullptr;   // pinned staging of the table
+    int32_t* dev_grid = nullptr;          // located seed cells of a kSeedGrid^3 grid over the bound
+    float grid_lo[3] = {0, 0, 0}, grid_inv[3] = {0, 0, 0};
     uint32_t* dev_desc[rf::kLaunchesInFlight] = {nullptr, nullptr};
     uint32_t* host_desc[rf::kLaunchesInFlight] = {nullptr, nullptr};
     hipEvent_t done_ev[rf::kLaunchesInFlight] = {nullptr, nullptr};
@@ -234,6 +237,33 @@ void retire(rf_server* s)
     }
 }
 
+rf::SceneView scene_view(const rf_server* s)
+{
+    rf::SceneView v;
+    const unsigned char* base = static_cast<const unsigned char*>(s->scene.base);
+    v.planes = reinterpret_cast<const float4*>(base + s->scene.off_planes);
+    v.adj = reinterpret_cast<const uint2*>(base + s->scene.off_adj);
+    v.row = reinterpret_cast<const uint2*>(base + s->scene.off_row);
+    v.rec = base + s->scene.off_rec;
+    v.n_sites = s->scene.n_sites;
+    v.n_edges = s->scene.n_edges;
+    return v;
+}
+
+rf::LocateArgs locate_args(const rf_server* s)
+{
+    rf::LocateArgs a;
+    memset(&a, 0, sizeof a);
+    a.s = scene_view(s);
+    a.max_steps = 1 << 20;
+    a.grid_n = rf::kSeedGrid;
+    for (int k = 0; k < 3; ++k) {
+        a.grid_lo[k] = s->grid_lo[k];
+        a.grid_inv[k] = s->grid_inv[k];
+    }
+    return a;
+}
+
 // Builds and enqueues one launch from the pending tiles, oldest request first.
 // Called with the lock held; returns false if there was nothing to launch.
 bool launch_next(rf_server* s)
@@ -248,6 +278,15 @@ bool launch_next(rf_server* s)
         if (!sl.uploaded && e == hipSuccess) {
             e = hipMemcpyAsync(&s->dev_reqs[slot], &s->host_reqs[slot], sizeof(rf::ReqRecord),
                                hipMemcpyHostToDevice, s->stream);
+            if (e == hipSuccess && s->host_reqs[slot].start < 0) {
+                // the camera's cell, located on the device into the record
+                rf::LocateArgs la = locate_args(s);
+                la.points = s->dev_reqs[slot].pos;
+                la.n_points = 1;
+                la.cells = &s->dev_reqs[slot].start;
+                la.grid = s->dev_grid;
+                e = rf::launch_locate(s->scene.sh_degree, s->scene.attr_dtype == RF_BF16, la, s->stream);
+            }
             sl.uploaded = true;
         }
     }
@@ -267,13 +306,7 @@ bool launch_next(rf_server* s)
         e = hipMemcpyAsync(s->dev_desc[b], s->host_desc[b], sizeof(uint32_t) * n, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) {
         rf::BatchArgs a;
-        const unsigned char* base = static_cast<const unsigned char*>(s->scene.base);
-        a.s.planes = reinterpret_cast<const float4*>(base + s->scene.off_planes);
-        a.s.adj = reinterpret_cast<const uint2*>(base + s->scene.off_adj);
-        a.s.row = reinterpret_cast<const uint2*>(base + s->scene.off_row);
-        a.s.rec = base + s->scene.off_rec;
-        a.s.n_sites = s->scene.n_sites;
-        a.s.n_edges = s->scene.n_edges;
+        a.s = scene_view(s);
         a.eps = s->params.eps;
         a.max_steps = s->params.max_steps;
         a.bound_kind = s->bound.kind;
@@ -313,6 +346,45 @@ void scheduler(rf_server* s)
     }
 }
 
+// The seed grid: cell centres of a kSeedGrid^3 grid over the bound's box,
+// each located once from cell 0; a request's camera cell is then located from
+// the grid cell that contains the camera, a few steps away.
+hipError_t build_seed_grid(rf_server* s)
+{
+    constexpr int G = rf::kSeedGrid;
+    float lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = s->bound.kind == 0 ? s->bound.p[k] : -s->bound.p[0];
+        hi[k] = s->bound.kind == 0 ? s->bound.p[3 + k] : s->bound.p[0];
+        s->grid_lo[k] = lo[k];
+        s->grid_inv[k] = hi[k] > lo[k] ? (float)G / (hi[k] - lo[k]) : 0.0f;
+    }
+    std::vector<float> pts((size_t)G * G * G * 3);
+    for (int z = 0; z < G; ++z)
+        for (int y = 0; y < G; ++y)
+            for (int x = 0; x < G; ++x) {
+                const int c[3] = {x, y, z};
+                float* p = &pts[(((size_t)z * G + y) * G + x) * 3];
+                for (int k = 0; k < 3; ++k) p[k] = lo[k] + (c[k] + 0.5f) * (hi[k] - lo[k]) / G;
+            }
+    float* dev_pts = nullptr;
+    hipError_t e = hipMalloc((void**)&s->dev_grid, sizeof(int32_t) * G * G * G);
+    if (e == hipSuccess) e = hipMalloc((void**)&dev_pts, sizeof(float) * pts.size());
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dev_pts, pts.data(), sizeof(float) * pts.size(), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) {
+        rf::LocateArgs a = locate_args(s);
+        a.points = dev_pts;
+        a.n_points = (int64_t)G * G * G;
+        a.cells = s->dev_grid;
+        a.grid = nullptr;  // from cell 0
+        e = rf::launch_locate(s->scene.sh_degree, s->scene.attr_dtype == RF_BF16, a, s->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (dev_pts) (void)hipFree(dev_pts);
+    return e;
+}
+
 void release(rf_server* s)
 {
     for (int b = 0; b < rf::kLaunchesInFlight; ++b) {
@@ -321,6 +393,7 @@ void release(rf_server* s)
         if (s->host_desc[b]) (void)hipHostFree(s->host_desc[b]);
     }
     if (s->dev_reqs) (void)hipFree(s->dev_reqs);
+    if (s->dev_grid) (void)hipFree(s->dev_grid);
     if (s->host_reqs) (void)hipHostFree(s->host_reqs);
     if (s->pool) (void)hipHostFree(s->pool);
     if (s->stream) (void)hipStreamDestroy(s->stream);
@@ -365,6 +438,7 @@ rf_status rf_server_create(const rf_packed_scene* scene, const rf_params* params
             e = hipHostMalloc((void**)&s->host_desc[b], sizeof(uint32_t) * rf::kMaxBatchTiles, hipHostMallocDefault);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&s->done_ev[b], hipEventDisableTiming);
     }
+    if (e == hipSuccess) e = build_seed_grid(s);
     if (e != hipSuccess) {
         release(s);
         delete s;

@@ -154,6 +154,21 @@ def raygen(pose12, fov_deg: float, width: int, height: int, bound: tuple, start:
     return o, d, t, s, px
 
 
+def locate(scene: PackedScene, points, seed=None, max_steps: int = 1 << 20):
+    """Nearest site of each point [M,3] (the cell containing it): int32 [M];
+    -1 for a seed out of range, -2 if ``max_steps`` greedy steps did not
+    suffice. ``seed`` (int32 [M], optional) is where each walk starts."""
+    M = int(points.shape[0])
+    dev = points.device
+    _dev(points, torch.float32, (M, 3), "points")
+    if seed is not None:
+        _dev(seed, torch.int32, (M,), "seed")
+    cells = torch.empty(M, dtype=torch.int32, device=dev)
+    L.check(L.lib().rf_locate(ctypes.byref(scene.desc), _ptr(points) if M else None, M, _ptr(seed),
+                              int(max_steps), _ptr(cells) if M else None, _stream(dev)))
+    return cells
+
+
 class WalkLog:
     """Device buffers of a walk log (``rf_walk_log``): per ray, the first
     ``capacity`` visits of the forward walk (cell and flags, exit distance in

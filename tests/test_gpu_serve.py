@@ -129,3 +129,21 @@ def test_server_argument_errors(setup):
         with pytest.raises(rf.RfError, match="INVALID_ARG"):
             srv.submit(reqs[0]["pose12"], 0.0, 8, 8, 0)
         assert srv.poll() == []
+
+
+def test_device_located_start_cells(setup):
+    """Requests submitted without a start cell (start_cell < 0) are located on
+    the device; where the camera's nearest site is not an FP64 near-tie the
+    cell is the host's, so the image is the same bit for bit."""
+    rf, scene, packed, reqs, alone = setup
+    from paper_2502_01157_amd.serve import Server, replay
+
+    pos = np.stack([r["camera"].position for r in reqs]).astype(np.float32)
+    ref, gap = oracle.nearest_site(scene.sites, pos, return_gap=True)
+    assert (gap > 1e-12).all()
+    np.testing.assert_array_equal(ref, [r["start_cell"] for r in reqs])
+    located = [dict(r, start_cell=-1) for r in reqs]
+    with Server(packed, scene.bound, pool_bytes=8 << 20, max_inflight=16) as srv:
+        out = replay(srv, located, keep=range(len(reqs)), timeout_s=20)
+    for i in range(len(reqs)):
+        np.testing.assert_array_equal(out["images"][i], alone[i], err_msg=f"request {i}")
