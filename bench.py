@@ -18,7 +18,6 @@ Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--config clustered_
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -40,11 +39,15 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+WALK_SOURCES = ("walk.hip", "rf_walk.hpp", "rf_device.hpp", "rf_kernels.hpp")
+
+
 def kernel_source_digest() -> str:
-    """Digest of the HIP sources; HBM traffic figures are only valid for the digest they were taken on."""
+    """Digest of the sources the walk kernels are built from; HBM traffic figures
+    are only valid for the digest they were taken on."""
     h = hashlib.sha1()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2502_01157_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
+    for name in WALK_SOURCES:
+        with open(os.path.join(ROOT, "paper_2502_01157_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:12]
 
