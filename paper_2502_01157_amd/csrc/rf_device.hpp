@@ -77,15 +77,46 @@ struct Attr {
     float site[3];
 };
 
-template <int DEG, bool BF16>
-__device__ inline void load_record(const unsigned char* __restrict__ rec_base, int cell, Attr<DEG>& a)
+// LDS pointers (address space 3) for data staged by a wavefront; 16-byte LDS
+// elements are read as native vectors (HIP's vector classes do not copy from
+// address-space-qualified references).
+typedef __attribute__((address_space(3))) unsigned char lds_u8;
+typedef __attribute__((address_space(3))) void lds_void;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) const f32x4 lds_f32x4;
+typedef __attribute__((address_space(3))) const u32x4 lds_u32x4;
+
+// Direct global-to-LDS load of 16 bytes per active lane: lane i writes
+// dst + 16 i (dst must be the same for every lane of the wavefront).
+__device__ inline void copy16_to_lds(const void* src, lds_u8* dst)
+{
+    __builtin_amdgcn_global_load_lds(src, (lds_void*)dst, 16, 0, 0);
+}
+
+__device__ inline float4 ld16(const float4* p) { return *p; }
+__device__ inline uint4 ld16(const uint4* p) { return *p; }
+__device__ inline float4 ld16(lds_f32x4* p)
+{
+    const f32x4 v = *p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ inline uint4 ld16(lds_u32x4* p)
+{
+    const u32x4 v = *p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// Unpacks a record from its 16-byte chunks, read through P (a global or an
+// LDS pointer).
+template <int DEG, bool BF16, typename P>
+__device__ inline void unpack_record(P p, Attr<DEG>& a)
 {
     using R = Rec<DEG, BF16>;
-    const uint4* p = reinterpret_cast<const uint4*>(rec_base + (size_t)cell * R::BYTES);
     uint32_t w[4 * R::CHUNKS];
 #pragma unroll
     for (int c = 0; c < R::CHUNKS; ++c) {
-        const uint4 v = p[c];
+        const uint4 v = ld16(p + c);
         w[4 * c + 0] = v.x;
         w[4 * c + 1] = v.y;
         w[4 * c + 2] = v.z;
@@ -102,6 +133,13 @@ __device__ inline void load_record(const unsigned char* __restrict__ rec_base, i
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) a.site[k] = __uint_as_float(w[R::SITE_OFF / 4 + k]);
+}
+
+template <int DEG, bool BF16>
+__device__ inline void load_record(const unsigned char* __restrict__ rec_base, int cell, Attr<DEG>& a)
+{
+    using R = Rec<DEG, BF16>;
+    unpack_record<DEG, BF16>(reinterpret_cast<const uint4*>(rec_base + (size_t)cell * R::BYTES), a);
 }
 
 template <int DEG, bool BF16>

@@ -14,19 +14,20 @@ struct FaceHit {
 
 // Nearest front face of a cell: den = n.d > 0 and the smallest
 // t = (c - n.o) / den, compared without division (ties keep the first face).
-// Faces are read four at a time from the row's base with immediate offsets;
-// a batch may run up to three faces past the row's end (the plane array is
-// padded), and those faces are masked by k < deg.
-__device__ inline FaceHit nearest_front_face(const float4* __restrict__ planes, int beg, int deg, float ox, float oy,
-                                             float oz, float dx, float dy, float dz)
+// Faces are read four at a time from the row's base (in the plane array or a
+// wavefront's LDS copy of the row) with immediate offsets; a batch may run up
+// to three faces past the row's end (the plane array is padded, an LDS row is
+// followed by more of the wavefront's LDS), and those faces are masked by
+// k < deg.
+template <typename P>
+__device__ inline FaceHit scan_row(P row, int deg, float ox, float oy, float oz, float dx, float dy, float dz)
 {
-    const float4* __restrict__ row = planes + beg;
     float bn = 1.0f, bd = 0.0f;
     int bk = -1;
     for (int k = 0; k < deg; k += 4) {
         float4 p[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) p[u] = row[k + u];
+        for (int u = 0; u < 4; ++u) p[u] = ld16(row + k + u);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const float den = fmaf(p[u].z, dz, fmaf(p[u].y, dy, p[u].x * dx));
@@ -38,6 +39,12 @@ __device__ inline FaceHit nearest_front_face(const float4* __restrict__ planes, 
         }
     }
     return {bn, bd, bk, make_uint2(0u, 0u)};
+}
+
+__device__ inline FaceHit nearest_front_face(const float4* __restrict__ planes, int beg, int deg, float ox, float oy,
+                                             float oz, float dx, float dy, float dz)
+{
+    return scan_row(planes + beg, deg, ox, oy, oz, dx, dy, dz);
 }
 
 template <int DEG>
@@ -130,6 +137,96 @@ __device__ inline float face_den(const float* xi, const float* xj, float dx, flo
     return fmaf(nz, dz, fmaf(ny, dy, nx * dx));
 }
 
+// ---------------------------------------------------------------------------
+// Wavefront staging of the visited cells' data in LDS.
+//
+// The lanes of a wavefront (one 8x8 tile) are mostly in the same few cells at
+// each step (about 9 distinct cells and 155 distinct faces for 64 lanes at
+// 1M sites). Loading a row of planes per lane costs the vector memory path
+// per active lane; instead, each distinct cell's row and record are copied
+// once into the wavefront's LDS region by direct global-to-LDS loads (one
+// 16-byte chunk per lane), and every lane then reads its own cell's copy.
+// Cells that do not fit the region are read from global memory as before.
+// ---------------------------------------------------------------------------
+template <int DEG, bool BF16>
+struct StageLayout {
+    using R = Rec<DEG, BF16>;
+    static constexpr int kFaces = 352;                 // face slots (16 B each)
+    static constexpr int kRecs = 16;                   // record slots
+    static constexpr int kRecOff = kFaces * 16;
+    static constexpr int kBytes = kRecOff + kRecs * R::BYTES;
+};
+
+// Called with every lane of the wavefront active. Lanes with `want` stage the
+// row and record of their cell `ref`; on return face_slot / rec_slot give the
+// position of the copy in `region` (-1: not staged, read from global memory).
+template <int DEG, bool BF16>
+__device__ inline void stage_cells(const SceneView& s, bool want, uint2 ref, lds_u8* region, int& face_slot,
+                                   int& rec_slot)
+{
+    using SL = StageLayout<DEG, BF16>;
+    using R = Rec<DEG, BF16>;
+    const int lane = __lane_id();
+    const int cell = ref_cell(ref);
+    uint64_t pend = __ballot(want);
+    int off = 0, nrec = 0;
+    face_slot = -1;
+    rec_slot = -1;
+    while (pend) {
+        const int leader = __builtin_ctzll(pend);
+        const int key = __builtin_amdgcn_readlane(cell, leader);
+        const int gbeg = __builtin_amdgcn_readlane(ref_beg(ref), leader);
+        const int gdeg = __builtin_amdgcn_readlane(ref_deg(ref), leader);
+        const uint64_t members = __ballot(want && cell == key);
+        pend &= ~members;
+        if (off + gdeg > SL::kFaces || nrec == SL::kRecs) continue;
+        for (int k0 = 0; k0 < gdeg; k0 += kWave)
+            if (k0 + lane < gdeg)
+                copy16_to_lds(s.planes + gbeg + k0 + lane, region + (off + k0) * 16);
+        if (lane < R::CHUNKS)
+            copy16_to_lds(s.rec + (size_t)key * R::BYTES + lane * 16, region + SL::kRecOff + nrec * R::BYTES);
+        if ((members >> lane) & 1) {
+            face_slot = off;
+            rec_slot = nrec;
+        }
+        off += gdeg;
+        ++nrec;
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // the copies have landed in LDS
+    __builtin_amdgcn_wave_barrier();
+}
+
+// visit_cell reading the staged copies where there are any.
+template <int DEG, bool BF16>
+__device__ inline void visit_cell_staged(const SceneView& s, uint2 ref, int face_slot, int rec_slot,
+                                         lds_u8* region, double t0, float tmax, float ox, float oy, float oz,
+                                         float dx, float dy, float dz, const float* Y, Visit<DEG>& v)
+{
+    using SL = StageLayout<DEG, BF16>;
+    using R = Rec<DEG, BF16>;
+    const int cell = ref_cell(ref), beg = ref_beg(ref), deg = ref_deg(ref);
+    lds_f32x4* lrow = reinterpret_cast<lds_f32x4*>(region) + face_slot;
+    if (face_slot >= 0)
+        v.h = scan_row(lrow, deg, ox, oy, oz, dx, dy, dz);
+    else
+        v.h = nearest_front_face(s.planes, beg, deg, ox, oy, oz, dx, dy, dz);
+    float4 wp = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (v.h.k >= 0) {
+        wp = face_slot >= 0 ? ld16(lrow + v.h.k) : s.planes[beg + v.h.k];
+        v.h.next = s.adj[beg + v.h.k];
+    }
+    if (rec_slot >= 0)
+        unpack_record<DEG, BF16>(reinterpret_cast<lds_u32x4*>(region + SL::kRecOff + rec_slot * R::BYTES), v.at);
+    else
+        load_record<DEG, BF16>(s.rec, cell, v.at);
+    v.t1 = INFINITY;
+    if (v.h.k >= 0) v.t1 = exit_distance(wp, v.at.site, ox, oy, oz, dx, dy, dz);
+    const double tm = (double)tmax;
+    v.clipped = (v.h.k < 0) || (v.t1 >= tm);
+    v.te = fmax(t0, fmin(v.t1, tm));
+    segment<DEG>(t0, Y, v);
+}
+
 // Where a logged walk records its visits: visit n of ray r at [n * stride + r]
 // (step-major, so the lanes of a wavefront, which advance in lock step, write
 // contiguous words), the first `cap` visits only; tail[r] holds the row of the
@@ -213,6 +310,91 @@ __device__ inline void walk_forward(const SceneView& s, float ox, float oy, floa
     if constexpr (LOG) {
         if (n <= lg->cap) tail = ref;
         lg->tail[r] = make_int4((int)tail.x, (int)tail.y, n, 0);
+    }
+}
+
+// walk_forward with wavefront staging: the loop runs until every lane of the
+// wavefront is done, so that all 64 lanes take part in each staging round;
+// `live` is false for lanes without a ray. Same arithmetic as walk_forward,
+// so the same outputs bit for bit.
+template <int DEG, bool BF16, bool TRACE, bool LOG>
+__device__ inline void walk_forward_staged(const SceneView& s, bool live, float ox, float oy, float oz, float dx,
+                                           float dy, float dz, float tmax, int start, float eps, int max_steps,
+                                           int32_t* cells, float* t_exit, int max_len, RayResult& res,
+                                           const LogView* lg, int64_t r, lds_u8* region)
+{
+    res.C[0] = res.C[1] = res.C[2] = 0.0f;
+    res.T = 1.0f;
+    res.status = 0;
+    if (live && (start < 0 || (int64_t)start >= s.n_sites)) {
+        res.status = -1;
+        if constexpr (LOG) lg->tail[r] = make_int4(0, 0, 0, 0);
+        live = false;
+    }
+    const bool logged = live;
+    float Y[sh_count(DEG)];
+    sh_basis<DEG>(dx, dy, dz, Y);
+    uint2 ref = live ? s.row[start] : make_uint2(0u, 0u);
+    uint2 tail = ref;
+    double t0 = 0.0;
+    float T = 1.0f;
+    int n = 0;
+    while (__ballot(live)) {
+        if (live) {
+            if (!(T > eps)) {
+                res.status = n;
+                live = false;
+            } else if (n == max_steps) {
+                res.status = -2;
+                live = false;
+            }
+        }
+        int face_slot, rec_slot;
+        stage_cells<DEG, BF16>(s, live, ref, region, face_slot, rec_slot);
+        if (live) {
+            if constexpr (LOG) {
+                if (n == lg->cap) tail = ref;
+            }
+            Visit<DEG> v;
+            visit_cell_staged<DEG, BF16>(s, ref, face_slot, rec_slot, region, t0, tmax, ox, oy, oz, dx, dy, dz, Y,
+                                         v);
+            const float w = T * v.alpha;
+            res.C[0] = fmaf(w, v.c[0], res.C[0]);
+            res.C[1] = fmaf(w, v.c[1], res.C[1]);
+            res.C[2] = fmaf(w, v.c[2], res.C[2]);
+            T *= expf(-v.tau);
+            if constexpr (TRACE) {
+                if (n < max_len) {
+                    cells[n] = ref_cell(ref);
+                    t_exit[n] = (float)v.te;
+                }
+            }
+            if constexpr (LOG) {
+                if (n < lg->cap) {
+                    const bool moves = !v.clipped && (v.t1 >= t0);
+                    lg->code[n * lg->stride + r] =
+                        (uint32_t)ref_cell(ref) | (moves ? kLogMoves : 0u) | (v.clipped ? kLogClipped : 0u);
+                    lg->te[n * lg->stride + r] = v.te;
+                }
+            }
+            ++n;
+            if (v.clipped) {
+                res.status = n;
+                live = false;
+            } else {
+                ref = v.h.next;
+                t0 = v.te;
+            }
+        }
+        // the next round's copies overwrite this round's: every lane has read its own
+        __builtin_amdgcn_wave_barrier();
+    }
+    res.T = T;
+    if constexpr (LOG) {
+        if (logged) {
+            if (n <= lg->cap) tail = ref;
+            lg->tail[r] = make_int4((int)tail.x, (int)tail.y, n, 0);
+        }
     }
 }
 

@@ -1,7 +1,10 @@
 // The forward and backward Voronoi ray walk (Algorithm 1 and its gradient) for gfx950.
 //
 // One ray per lane; rays arrive in 8x8 screen-tile order, so a wavefront is
-// one tile and its lanes walk mostly the same cells at the same time.
+// one tile and its lanes walk mostly the same cells at the same time. The
+// forward kernels exploit that: at each step the wavefront copies the face
+// rows and records of its lanes' distinct cells into its LDS region once
+// (direct global-to-LDS loads) and every lane scans its cell from there.
 //
 // Per visited cell i the walk
 //   1. scans the cell's face planes (one float4 per Delaunay neighbour),
@@ -54,14 +57,19 @@ __device__ inline int64_t ray_index()
 template <int DEG, bool BF16, bool TRACE, bool LOG>
 __global__ __launch_bounds__(kBlock) void k_forward(WalkArgs a)
 {
+    using SL = StageLayout<DEG, BF16>;
+    __shared__ __align__(16) unsigned char stage_mem[(kBlock / kWave) * SL::kBytes];
+    lds_u8* region = (lds_u8*)(stage_mem + (threadIdx.x / kWave) * SL::kBytes);
     const int64_t r = ray_index();
-    if (r >= a.n_rays) return;
+    const bool valid = r < a.n_rays;  // lanes past the end still take part in the staging
+    const int64_t q = valid ? r : 0;
     RayResult res;
     const LogView lg = {a.log_code, a.log_te, a.log_tail, a.log_cap, a.n_rays};
-    walk_forward<DEG, BF16, TRACE, LOG>(a.s, a.origin[3 * r], a.origin[3 * r + 1], a.origin[3 * r + 2],
-                                        a.dir[3 * r], a.dir[3 * r + 1], a.dir[3 * r + 2], a.t_max[r], a.start[r],
-                                        a.eps, a.max_steps, TRACE ? a.cells + r * a.max_len : nullptr,
-                                        TRACE ? a.t_exit + r * a.max_len : nullptr, a.max_len, res, &lg, r);
+    walk_forward_staged<DEG, BF16, TRACE, LOG>(
+        a.s, valid, a.origin[3 * q], a.origin[3 * q + 1], a.origin[3 * q + 2], a.dir[3 * q], a.dir[3 * q + 1],
+        a.dir[3 * q + 2], a.t_max[q], a.start[q], a.eps, a.max_steps, TRACE ? a.cells + q * a.max_len : nullptr,
+        TRACE ? a.t_exit + q * a.max_len : nullptr, a.max_len, res, &lg, q, region);
+    if (!valid) return;
     a.rgb[3 * r + 0] = res.C[0];
     a.rgb[3 * r + 1] = res.C[1];
     a.rgb[3 * r + 2] = res.C[2];
@@ -267,6 +275,13 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
     float T = 1.0f, Cacc[3] = {0.0f, 0.0f, 0.0f};
     double t0 = 0.0;
     int n = 0;
+    // the log entry of visit n, loaded one visit ahead
+    uint32_t pf_code = 0;
+    double pf_te = 0.0;
+    if (LOG && state == 0 && n_total > 0) {
+        pf_code = a.log_code[r];
+        pf_te = a.log_te[r];
+    }
     // previous visit, awaiting its exit gradient
     bool have_prev = false, p_moves = false;
     Package prev = {0, {0, 0, 0}, 0, {0, 0, 0}};
@@ -292,10 +307,19 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
                 if constexpr (LOG) {
                     // the visit as the forward logged it: same record, same te,
                     // so the same segment bit for bit, without the face scan
-                    const uint32_t code = a.log_code[(int64_t)n * a.n_rays + r];
-                    v.te = a.log_te[(int64_t)n * a.n_rays + r];
+                    const uint32_t code = pf_code;
+                    v.te = pf_te;
                     cell = min((int)(code & kLogCell), (int)(a.s.n_sites - 1));
                     load_record<DEG, BF16>(a.s.rec, cell, v.at);
+                    // the next visit's entry, issued after the record loads so
+                    // that waiting for the record does not wait for it (loads
+                    // complete in issue order)
+                    // (unconditional, so that the wait counts stay exact: the
+                    // last visit reloads its own entry)
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int64_t nxt = (int64_t)(n + 1 < n_total ? n + 1 : n) * a.n_rays + r;
+                    pf_code = a.log_code[nxt];
+                    pf_te = a.log_te[nxt];
                     v.t1 = v.te;  // a moving exit is unclamped: te = t1
                     v.clipped = (code & kLogClipped) != 0;
                     moves = (code & kLogMoves) != 0;
