@@ -94,6 +94,15 @@ __device__ inline void copy16_to_lds(const void* src, lds_u8* dst)
     __builtin_amdgcn_global_load_lds(src, (lds_void*)dst, 16, 0, 0);
 }
 
+// The same through a buffer descriptor of `bytes` bytes at the wavefront-
+// uniform address `base` (built with scalar instructions): each active lane
+// loads the 16 bytes at base + lane_offset and writes dst + 16 i.
+__device__ inline void copy16_to_lds(const void* base, uint32_t bytes, uint32_t lane_offset, lds_u8* dst)
+{
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, bytes, 0x00020000);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void*)dst, 16, lane_offset, 0, 0, 0);
+}
+
 __device__ inline float4 ld16(const float4* p) { return *p; }
 __device__ inline uint4 ld16(const uint4* p) { return *p; }
 __device__ inline float4 ld16(lds_f32x4* p)

@@ -167,24 +167,25 @@ __device__ inline void stage_cells(const SceneView& s, bool want, uint2 ref, lds
     using SL = StageLayout<DEG, BF16>;
     using R = Rec<DEG, BF16>;
     const int lane = __lane_id();
-    const int cell = ref_cell(ref);
+    const uint32_t lane16 = 16u * (uint32_t)lane;
     uint64_t pend = __ballot(want);
     int off = 0, nrec = 0;
     face_slot = -1;
     rec_slot = -1;
     while (pend) {
         const int leader = __builtin_ctzll(pend);
-        const int key = __builtin_amdgcn_readlane(cell, leader);
-        const int gbeg = __builtin_amdgcn_readlane(ref_beg(ref), leader);
-        const int gdeg = __builtin_amdgcn_readlane(ref_deg(ref), leader);
-        const uint64_t members = __ballot(want && cell == key);
+        // ref.x = cell | deg << 24 identifies the cell
+        const uint32_t kx = __builtin_amdgcn_readlane(ref.x, leader);
+        const int gbeg = __builtin_amdgcn_readlane(ref.y, leader);
+        const int key = (int)(kx & 0xffffffu), gdeg = (int)(kx >> 24);
+        const uint64_t members = __ballot(want && ref.x == kx);
         pend &= ~members;
         if (off + gdeg > SL::kFaces || nrec == SL::kRecs) continue;
         for (int k0 = 0; k0 < gdeg; k0 += kWave)
             if (k0 + lane < gdeg)
-                copy16_to_lds(s.planes + gbeg + k0 + lane, region + (off + k0) * 16);
+                copy16_to_lds(s.planes + gbeg + k0, 16u * kWave, lane16, region + (off + k0) * 16);
         if (lane < R::CHUNKS)
-            copy16_to_lds(s.rec + (size_t)key * R::BYTES + lane * 16, region + SL::kRecOff + nrec * R::BYTES);
+            copy16_to_lds(s.rec + (size_t)key * R::BYTES, R::BYTES, lane16, region + SL::kRecOff + nrec * R::BYTES);
         if ((members >> lane) & 1) {
             face_slot = off;
             rec_slot = nrec;

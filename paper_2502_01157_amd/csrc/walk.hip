@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(WalkArgs a)
 {
     using SL = StageLayout<DEG, BF16>;
     __shared__ __align__(16) unsigned char stage_mem[(kBlock / kWave) * SL::kBytes];
-    lds_u8* region = (lds_u8*)(stage_mem + (threadIdx.x / kWave) * SL::kBytes);
+    lds_u8* region = (lds_u8*)(stage_mem + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave) * SL::kBytes);
     const int64_t r = ray_index();
     const bool valid = r < a.n_rays;  // lanes past the end still take part in the staging
     const int64_t q = valid ? r : 0;
@@ -109,97 +109,173 @@ __device__ inline void emit_atomic(bool has, const Package& p, const float* Y, c
     unsafeAtomicAdd(a.g_sites + 3 * (size_t)p.cell + 2, p.dx[2]);
 }
 
-// Called with every lane of the wavefront active. Lanes holding a package for
-// the same cell are grouped (leader by ballot); for each group, lane q < 3B+4
-// sums column q over the group's members from the wave's LDS rows and issues
-// one atomic, so a group costs one coalesced atomic instruction. Members are
-// read eight at a time (padded with an all-zero row) so that sixteen LDS reads
-// are in flight per wait.
-// LDS rows (stride S, 64 lanes + 1 zero row): Y[0..B-1], gw[0..2], dsig, dx[0..2], 1.
+// Gradient emission of one wavefront, called with every lane active.
+//
+// Lanes holding a package for the same cell are grouped (leader by ballot);
+// for each group, lane q < 3B+4 sums column q over the group's members from
+// the wave's LDS rows (one row per lane: Y[0..B-1], gw[0..2], dsig, dx[0..2],
+// 1; members read four or eight at a time, padded with an all-zero row).
+// The group's sums then go into a per-wavefront cache of gradient rows in LDS
+// (kSlots rows keyed by cell, first-in first-out): the 64 rays of a tile
+// visit only a few hundred distinct cells over their whole walks, each many
+// times, so summing in LDS and flushing a row with one coalesced atomic
+// instruction when it is evicted (or at the end) replaces most atomics.
+// The slot keys live in one register across lanes 0..kSlots-1, so a lookup is
+// one ballot.
 template <int DEG>
 struct EmitLayout {
     static constexpr int B = sh_count(DEG);
     static constexpr int S = (B + 8) | 1;
     static constexpr int ROWS = kWave + 1;
     static constexpr int NOUT = 3 * B + 4;
+    static constexpr int kSlots = 32;
+    static constexpr int FLOATS = ROWS * S + kSlots * NOUT;  // per wavefront
 };
 
 template <int DEG>
-__device__ inline void emit_reduce(bool has, const Package& p, const float* Y, float* __restrict__ my, int lane,
-                                   const WalkArgs& a)
-{
+struct Emitter {
     using E = EmitLayout<DEG>;
-    constexpr int B = E::B, S = E::S, NOUT = E::NOUT;
-    uint64_t pend = __ballot(has);
-    if (pend == 0) return;
-    if (has) {
-        float* row = my + lane * S;
-#pragma unroll
-        for (int b = 0; b < B; ++b) row[b] = Y[b];
-        row[B + 0] = p.gw[0];
-        row[B + 1] = p.gw[1];
-        row[B + 2] = p.gw[2];
-        row[B + 3] = p.dsig;
-        row[B + 4] = p.dx[0];
-        row[B + 5] = p.dx[1];
-        row[B + 6] = p.dx[2];
-        row[B + 7] = 1.0f;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-    // the column this lane owns: value = row[colA] * row[colB], destination
-    // base + cell * stride
-    int colA, colB;
-    float* base;
+    float* rows;   // LDS, ROWS x S
+    float* cache;  // LDS, kSlots x NOUT
+    int lane;
+    int colA, colB;  // this lane's column: row[colA] * row[colB]
+    float* base;     // its destination: base + cell * stride
     int stride;
-    if (lane < 3 * B) {
-        colA = lane / 3;
-        colB = B + lane % 3;
-        base = a.g_sh + lane;
-        stride = 3 * B;
-    } else if (lane == 3 * B) {
-        colA = B + 3;
-        colB = B + 7;
-        base = a.g_density;
-        stride = 1;
-    } else {
-        const int q = min(lane - 3 * B - 1, 2);
-        colA = B + 4 + q;
-        colB = B + 7;
-        base = a.g_sites + q;
-        stride = 3;
+    int slot_key;    // key of slot `lane` (lanes < kSlots), -1 empty
+    int next_slot;   // wavefront-uniform FIFO position
+
+    // lds: the wavefront's E::FLOATS floats of LDS
+    __device__ void init(float* lds, int lane_, const WalkArgs& a)
+    {
+        constexpr int B = E::B;
+        rows = lds;
+        cache = lds + E::ROWS * E::S;
+        lane = lane_;
+        if (lane < 3 * B) {
+            colA = lane / 3;
+            colB = B + lane % 3;
+            base = a.g_sh + lane;
+            stride = 3 * B;
+        } else if (lane == 3 * B) {
+            colA = B + 3;
+            colB = B + 7;
+            base = a.g_density;
+            stride = 1;
+        } else {
+            const int q = min(lane - 3 * B - 1, 2);
+            colA = B + 4 + q;
+            colB = B + 7;
+            base = a.g_sites + q;
+            stride = 3;
+        }
+        slot_key = -1;
+        next_slot = 0;
+        // the padding row read by member batches that are not full
+        if (lane < E::S) rows[kWave * E::S + lane] = 0.0f;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
-    const int key_cell = has ? p.cell : -1;
-    while (pend) {
-        const int leader = __builtin_ctzll(pend);
-        const int key = __builtin_amdgcn_readlane(key_cell, leader);
-        const uint64_t members = __ballot(key_cell == key) & pend;
-        pend &= ~members;
+
+    // Sum over the members `mm` of this lane's column, W members per LDS batch.
+    template <int W>
+    __device__ float column_sum(uint64_t mm) const
+    {
         float acc = 0.0f;
-        uint64_t mm = members;
         while (mm) {
-            int idx[8];
+            int idx[W];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < W; ++q) {
                 idx[q] = mm ? __builtin_ctzll(mm) : kWave;  // row kWave is all zeros
                 mm &= mm - 1;
             }
-            float va[8], vb[8];
+            float va[W], vb[W];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                va[q] = my[idx[q] * S + colA];
-                vb[q] = my[idx[q] * S + colB];
+            for (int q = 0; q < W; ++q) {
+                va[q] = rows[idx[q] * E::S + colA];
+                vb[q] = rows[idx[q] * E::S + colB];
             }
 #pragma unroll
-            for (int q = 0; q < 8; ++q) acc = fmaf(va[q], vb[q], acc);
+            for (int q = 0; q < W; ++q) acc = fmaf(va[q], vb[q], acc);
         }
-        if (lane < NOUT && acc != 0.0f) unsafeAtomicAdd(base + (size_t)key * stride, acc);
+        return acc;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
+
+    // Adds the wavefront's column sums for `key` to its cache row, evicting
+    // (flushing) the oldest row when the cell has none.
+    __device__ void accumulate(int key, float acc)
+    {
+        const uint64_t hit = __ballot(lane < E::kSlots && slot_key == key);
+        if (hit) {
+            // each lane owns its column, so the add needs no result and no wait
+            const int slot = __builtin_ctzll(hit);
+            if (lane < E::NOUT) cache[slot * E::NOUT + lane] += acc;
+            return;
+        }
+        const int slot = next_slot;
+        next_slot = next_slot + 1 == E::kSlots ? 0 : next_slot + 1;
+        const int old = __builtin_amdgcn_readlane(slot_key, slot);
+        if (lane < E::NOUT) {
+            if (old >= 0) {
+                const float v = cache[slot * E::NOUT + lane];
+                if (v != 0.0f) unsafeAtomicAdd(base + (size_t)old * stride, v);
+            }
+            cache[slot * E::NOUT + lane] = acc;
+        }
+        if (lane == slot) slot_key = key;
+    }
+
+    // The ray's SH basis, constant over its walk: written into the lane's row once.
+    __device__ void set_basis(const float* Y)
+    {
+        float* row = rows + lane * E::S;
+#pragma unroll
+        for (int b = 0; b < E::B; ++b) row[b] = Y[b];
+    }
+
+    __device__ void emit(bool has, const Package& p)
+    {
+        constexpr int B = E::B;
+        uint64_t pend = __ballot(has);
+        if (pend == 0) return;
+        if (has) {
+            float* row = rows + lane * E::S;  // row[0..B-1] = Y, written once by set_basis
+            row[B + 0] = p.gw[0];
+            row[B + 1] = p.gw[1];
+            row[B + 2] = p.gw[2];
+            row[B + 3] = p.dsig;
+            row[B + 4] = p.dx[0];
+            row[B + 5] = p.dx[1];
+            row[B + 6] = p.dx[2];
+            row[B + 7] = 1.0f;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int key_cell = has ? p.cell : -1;
+        while (pend) {
+            const int key_a = __builtin_amdgcn_readlane(key_cell, __builtin_ctzll(pend));
+            const uint64_t ma = __ballot(key_cell == key_a) & pend;
+            pend &= ~ma;
+            const float acc_a = __popcll(ma) <= 4 ? column_sum<4>(ma) : column_sum<8>(ma);
+            accumulate(key_a, acc_a);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    // Flushes every cached row (at the end of the wavefront's walks).
+    __device__ void flush()
+    {
+        for (int slot = 0; slot < E::kSlots; ++slot) {
+            const int key = __builtin_amdgcn_readlane(slot_key, slot);
+            if (key < 0) continue;
+            if (lane < E::NOUT) {
+                const float v = cache[slot * E::NOUT + lane];
+                if (v != 0.0f) unsafeAtomicAdd(base + (size_t)key * stride, v);
+            }
+        }
+    }
+};
 
 // Offsets of the exit point p = o + t d from the two sites of the face, formed
 // in double so that p - x does not lose the digits of |o| + t.
@@ -219,15 +295,10 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
 {
     constexpr int B = sh_count(DEG);
     using E = EmitLayout<DEG>;
-    __shared__ float lds[REDUCE ? (kBlock / kWave) * E::ROWS * E::S : 1];
+    __shared__ float lds[REDUCE ? (kBlock / kWave) * E::FLOATS : 1];
     const int lane = threadIdx.x & (kWave - 1);
-    float* my = lds + (REDUCE ? (threadIdx.x / kWave) * E::ROWS * E::S : 0);
-    if (REDUCE) {
-        // the padding row read by member batches with fewer than eight members
-        if (lane < E::S) my[kWave * E::S + lane] = 0.0f;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-    }
+    Emitter<DEG> em;
+    if constexpr (REDUCE) em.init(lds + (threadIdx.x / kWave) * E::FLOATS, lane, a);
 
     const int64_t r = ray_index();
     // lane state: 0 walking, 1 emit the last visit, 2 emit the next cell's entry term, 3 done
@@ -271,6 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
     }
     float Y[B];
     sh_basis<DEG>(dx, dy, dz, Y);
+    if constexpr (REDUCE) em.set_basis(Y);
 
     float T = 1.0f, Cacc[3] = {0.0f, 0.0f, 0.0f};
     double t0 = 0.0;
@@ -411,10 +483,11 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
             state = 3;
         }
         if constexpr (REDUCE)
-            emit_reduce<DEG>(has, out, Y, my, lane, a);
+            em.emit(has, out);
         else
             emit_atomic<DEG>(has, out, Y, a);
     }
+    if constexpr (REDUCE) em.flush();
 }
 
 // ---------------------------------------------------------------------------
