@@ -62,7 +62,10 @@ def measured_traffic(kernel: str, workload: str, dtype: str):
     m = re.search(r"kernel source digest: ([0-9a-f]+)", text)
     if not m or m.group(1) != kernel_source_digest():
         return None
-    m = re.search(rf"^\| k_{kernel}\S* \| \d+ \| \d+ \| \d+ \| ([0-9.]+) \| ([0-9.]+) \|", text, re.M)
+    # the launch the training step times: the logged forward, the log kernel of the backward
+    label = {"forward": "logged (training step)", "backward": "log kernel"}[kernel]
+    m = re.search(rf"^\| k_{kernel} \| {re.escape(label)} \| \d+ \| \d+ \| \d+ \| ([0-9.]+) \| ([0-9.]+) \|",
+                  text, re.M)
     if not m:
         return None
     return int(round((float(m.group(1)) + float(m.group(2))) * 1e6))
@@ -99,6 +102,7 @@ def main() -> int:
     ap.add_argument("--log-capacity", type=int, default=256, help="visits per ray kept in the walk log")
     ap.add_argument("--only", choices=["f32", "bf16"], default=None, help="time one attribute precision only")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving replay (512 Poisson requests)")
+    ap.add_argument("--no-locate", action="store_true", help="skip the start-cell location timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -278,10 +282,51 @@ def main() -> int:
 
     if not args.no_serving and args.config == "clustered_1m":
         out["serving"] = serving(rf, scenes, scene, bound, dts)
+    if not args.no_locate:
+        out["locate"] = locate(rf, scenes["f32"], bound, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, cam, bound, start, g_np, visits / R, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def locate(rf, packed, bound, dev, n_points: int = 1 << 20, grid: int = 32):
+    """Start-cell location (nearest site) of random points in the bound's box:
+    walks seeded from a grid^3 lattice of located cells, and walks from cell 0."""
+    import torch
+
+    lo = torch.tensor([bound[1]] * 3 if bound[0] == "box" else [-bound[1]] * 3, device=dev)
+    hi = torch.tensor([bound[2]] * 3 if bound[0] == "box" else [bound[1]] * 3, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    pts = lo + (hi - lo) * torch.rand((n_points, 3), device=dev, generator=g)
+    ax = (torch.arange(grid, device=dev, dtype=torch.float32) + 0.5) / grid
+    cz, cy, cx = torch.meshgrid(ax, ax, ax, indexing="ij")
+    centres = (lo + (hi - lo) * torch.stack([cx, cy, cz], -1).reshape(-1, 3)).contiguous()
+    lattice = rf.locate(packed, centres)
+    ijk = ((pts - lo) / (hi - lo) * grid).long().clamp_(0, grid - 1)
+    seeds = lattice[(ijk[:, 2] * grid + ijk[:, 1]) * grid + ijk[:, 0]].contiguous()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_seeded = timed(lambda: rf.locate(packed, pts, seeds), 10)
+    cold = pts[: n_points // 16].contiguous()
+    ms_cold = timed(lambda: rf.locate(packed, cold), 3)
+    cells = rf.locate(packed, pts, seeds)
+    log(f"locate: {n_points} points seeded from a {grid}^3 lattice {ms_seeded:.3f} ms, "
+        f"{len(cold)} from cell 0 {ms_cold:.3f} ms, flagged {(cells < 0).sum().item()}")
+    return {"points": n_points, "seed": f"{grid}^3 lattice of located cells", "ms": round(ms_seeded, 4),
+            "mpoints_s": round(n_points / ms_seeded / 1e3, 2), "cold_points": len(cold),
+            "cold_ms": round(ms_cold, 4), "cold_mpoints_s": round(len(cold) / ms_cold / 1e3, 3)}
 
 
 def serving(rf, packed, scene, bound, dts):
