@@ -57,6 +57,8 @@ def _load():
         lib.orc_face_planes.argtypes = [P, P, P, ctypes.c_int64, P]
         lib.orc_bf16_round.argtypes = [P, P, ctypes.c_int64]
         lib.orc_nearest_site.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P]
+        lib.orc_quantile.argtypes = [ctypes.POINTER(_Scene), P, P, P, P, ctypes.c_int64, ctypes.c_double,
+                                     ctypes.c_int32, P, P, ctypes.c_int, P, P, P, P]
         lib.orc_bf16_round.restype = None
         lib.orc_check_csr.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64]
         lib.orc_forward.argtypes = [ctypes.POINTER(_Scene), P, P, P, P, ctypes.c_int64, ctypes.c_double,
@@ -247,3 +249,22 @@ def backward(scene: OracleScene, o, d, tmax, start, grad_rgb, grad_t=None, eps: 
                                 int(max_steps), _ptr(g), _ptr(gt), threads or default_threads(),
                                 _ptr(gs), _ptr(gd), _ptr(gsh)), "backward")
     return gs, gd, gsh
+
+
+def quantile(scene: OracleScene, o, d, tmax, start, u, grad_loss=None, eps: float = DEFAULT_EPS,
+             max_steps: int = DEFAULT_MAX_STEPS, threads: Optional[int] = None):
+    """Quantile regulariser (Sec. 3.4): per ray, the quantiles W^-1(u1), W^-1(u2) [R,2] of the
+    normalised weight distribution along the walk and the loss |W^-1(u1) - W^-1(u2)| [R]; with
+    ``grad_loss`` [R] also the gradients (sites [N,3], density [N]) of sum(grad_loss * loss)."""
+    o, d, t, s, R = _rays(o, d, tmax, start)
+    uu = np.ascontiguousarray(_f64(u).reshape(R, 2))
+    gl = None if grad_loss is None else np.ascontiguousarray(_f64(grad_loss).reshape(R))
+    tq = np.empty((R, 2))
+    loss = np.empty(R)
+    n = scene.n_sites
+    gs = np.zeros((n, 3)) if gl is not None else None
+    gd = np.zeros(n) if gl is not None else None
+    _check(_load().orc_quantile(ctypes.byref(scene._c), _ptr(o), _ptr(d), _ptr(t), _ptr(s), R, float(eps),
+                                int(max_steps), _ptr(uu), _ptr(gl), threads or default_threads(), _ptr(tq),
+                                _ptr(loss), _ptr(gs), _ptr(gd)), "quantile")
+    return (tq, loss) if gl is None else (tq, loss, gs, gd)

@@ -485,6 +485,9 @@ typedef struct {
     /* backward */
     const double *grad_rgb, *grad_t;
     double *gsites, *gdens, *gsh;
+    /* quantile regulariser */
+    const double *u, *grad_loss;
+    double *tq, *loss;
     int status;
 } job_t;
 
@@ -540,6 +543,107 @@ static void *backward_worker(void *arg)
         const double gT = j->grad_t ? j->grad_t[r] : 0.0;
         ray_gradient(j->s, j->o + 3 * r, j->d + 3 * r, buf.v, buf.len, tf, j->grad_rgb + 3 * r, gT, j->gsites,
                      j->gdens, j->gsh);
+    }
+    free(buf.v);
+    return NULL;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Quantile regulariser (Sec. 3.4, training objectives): for a ray with     */
+/* composited segments n (weights w_n = T_n alpha_n), W(t) is the weight    */
+/* accumulated up to distance t; inside a segment the density is constant,  */
+/* so W(t) = W(t0_n) + T_n (1 - exp(-sigma_n (t - t0_n))). The quantile      */
+/* W^-1(u) of the normalised distribution is the t at which W(t) reaches     */
+/* u A, A = sum of the w_n (the ray's opacity, 1 - T_final). The loss of a   */
+/* ray is |W^-1(u1) - W^-1(u2)| for its two draws u1, u2.                   */
+/* ------------------------------------------------------------------------ */
+
+/* W^-1(u) for the visits v[0..nv): returns the segment index (-1 if A = 0). */
+static int64_t quantile_point(const orc_scene *s, const visit_t *v, int64_t nv, double u, double *tstar)
+{
+    double A = 0.0;
+    for (int64_t n = 0; n < nv; ++n) A += v[n].T * (-expm1(-v[n].tau));
+    *tstar = 0.0;
+    if (!(A > 0.0)) return -1;
+    const double m = u * A;
+    double cum = 0.0;
+    int64_t last = -1;
+    for (int64_t n = 0; n < nv; ++n) {
+        const double w = v[n].T * (-expm1(-v[n].tau));
+        if (!(w > 0.0)) continue;
+        last = n;
+        if (cum + w >= m) {
+            const double sigma = s->density[v[n].cell];
+            double t = v[n].t0 - log1p(-(m - cum) / v[n].T) / sigma;
+            if (t > v[n].te) t = v[n].te;
+            if (t < v[n].t0) t = v[n].t0;
+            *tstar = t;
+            return n;
+        }
+        cum += w;
+    }
+    *tstar = v[last].te; /* u A beyond the rounded total: the end of the last weighted segment */
+    return last;
+}
+
+/* Adds c (d t_star / d theta) to the density and site gradients, by implicit
+ * differentiation of W(t_star) = u A: d t_star = (u dA - dW(t_star)) / (T(t_star) sigma_k),
+ * where T(t_star) = 1 - W(t_star) and theta ranges over the densities and the exit
+ * distances of moving faces (whose site gradients follow as in ray_gradient). */
+static void quantile_gradient(const orc_scene *s, const double o[3], const double d[3], const visit_t *v, int64_t nv,
+                              double u, double tstar, int64_t k, double c, double *gsites, double *gdens)
+{
+    double A = 0.0;
+    for (int64_t n = 0; n < nv; ++n) A += v[n].T * (-expm1(-v[n].tau));
+    const double Tf = 1.0 - A;
+    const double sk = s->density[v[k].cell];
+    const double Tstar = v[k].T * exp(-sk * (tstar - v[k].t0));
+    const double den = Tstar * sk;
+    for (int64_t n = 0; n < nv; ++n) {
+        const double delta = v[n].te - v[n].t0;
+        const double dA = Tf * delta;
+        const double dW = n < k ? Tstar * delta : (n == k ? Tstar * (tstar - v[k].t0) : 0.0);
+        gdens[v[n].cell] += c * (u * dA - dW) / den;
+    }
+    for (int64_t m = 0; m < nv; ++m) {
+        if (!v[m].moves) continue;
+        const double sm = s->density[v[m].cell];
+        const double sm1 = m + 1 < nv ? s->density[v[m + 1].cell] : 0.0;
+        const double dA = Tf * (sm - sm1);
+        const double dW = m + 1 < k ? Tstar * (sm - sm1) : (m + 1 == k ? Tstar * (sm - sk) : 0.0);
+        const double gt = c * (u * dA - dW) / den;
+        const int32_t i = v[m].cell, j = v[m].next;
+        const double *xi = s->sites + 3 * (int64_t)i;
+        const double *xj = s->sites + 3 * (int64_t)j;
+        for (int a = 0; a < 3; ++a) {
+            const double p = o[a] + v[m].t1 * d[a];
+            gsites[3 * (int64_t)i + a] += gt * (p - xi[a]) / v[m].den;
+            gsites[3 * (int64_t)j + a] += gt * (xj[a] - p) / v[m].den;
+        }
+    }
+}
+
+static void *quantile_worker(void *arg)
+{
+    job_t *j = (job_t *)arg;
+    visit_buf buf = {0, 0, 0};
+    for (int64_t r = j->r0; r < j->r1; ++r) {
+        double rgb[3], tf, t[2];
+        int64_t k[2];
+        buf.len = 0;
+        const int32_t st = walk_ray(j->s, j->o + 3 * r, j->d + 3 * r, j->tmax[r], j->start[r], j->eps, j->max_steps,
+                                    rgb, &tf, &buf, NULL);
+        for (int q = 0; q < 2; ++q) {
+            k[q] = st == ORC_BAD_START ? -1 : quantile_point(j->s, buf.v, buf.len, j->u[2 * r + q], &t[q]);
+            if (k[q] < 0) t[q] = 0.0;
+            j->tq[2 * r + q] = t[q];
+        }
+        j->loss[r] = (k[0] < 0 || k[1] < 0) ? 0.0 : fabs(t[0] - t[1]);
+        if (!j->grad_loss || k[0] < 0 || k[1] < 0 || t[0] == t[1]) continue;
+        const double sg = t[0] > t[1] ? 1.0 : -1.0;
+        for (int q = 0; q < 2; ++q)
+            quantile_gradient(j->s, j->o + 3 * r, j->d + 3 * r, buf.v, buf.len, j->u[2 * r + q], t[q], k[q],
+                              (q == 0 ? sg : -sg) * j->grad_loss[r], j->gsites, j->gdens);
     }
     free(buf.v);
     return NULL;
@@ -657,4 +761,45 @@ int orc_backward(const orc_scene *s, const double *o, const double *d, const dou
     j.gdens = grad_density;
     j.gsh = grad_sh;
     return run_jobs(&j, n_rays, nthreads, backward_worker, 1);
+}
+
+int orc_quantile(const orc_scene *s, const double *o, const double *d, const double *tmax, const int32_t *start,
+                 int64_t n_rays, double eps, int32_t max_steps, const double *u, const double *grad_loss, int nthreads,
+                 double *tq, double *loss, double *grad_sites, double *grad_density)
+{
+    if (check_inputs(s, d, n_rays) != ORC_OK || max_steps < 1 || !u || !tq || !loss) return ORC_EINVAL;
+    for (int64_t r = 0; r < 2 * n_rays; ++r)
+        if (!(u[r] >= 0.0 && u[r] <= 1.0)) return ORC_EINVAL;
+    if (grad_loss && (!grad_sites || !grad_density)) return ORC_EINVAL;
+    job_t j;
+    memset(&j, 0, sizeof j);
+    j.s = s;
+    j.o = o;
+    j.d = d;
+    j.tmax = tmax;
+    j.start = start;
+    j.eps = eps;
+    j.max_steps = max_steps;
+    j.u = u;
+    j.grad_loss = grad_loss;
+    j.tq = tq;
+    j.loss = loss;
+    double *dummy_sh = NULL, *dummy_s = NULL, *dummy_d = NULL;
+    if (grad_loss) {
+        j.gsites = grad_sites;
+        j.gdens = grad_density;
+    } else {
+        dummy_s = (double *)calloc((size_t)3 * s->n_sites, sizeof(double));
+        dummy_d = (double *)calloc((size_t)s->n_sites, sizeof(double));
+        j.gsites = dummy_s;
+        j.gdens = dummy_d;
+    }
+    dummy_sh = (double *)calloc((size_t)3 * sh_count(s->sh_deg) * s->n_sites, sizeof(double));
+    j.gsh = dummy_sh;
+    int rc = (!dummy_sh || !j.gsites || !j.gdens) ? ORC_ENOMEM
+                                                    : run_jobs(&j, n_rays, nthreads, quantile_worker, 1);
+    free(dummy_sh);
+    free(dummy_s);
+    free(dummy_d);
+    return rc;
 }

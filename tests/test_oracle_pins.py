@@ -585,3 +585,118 @@ def test_nearest_site_matches_kdtree():
     mine = np.linalg.norm(q - scene.sites[idx].astype(np.float64), axis=1)
     np.testing.assert_allclose(mine, dist, rtol=1e-12, atol=0)
     np.testing.assert_array_equal(idx[3000:3050], np.arange(50))
+
+
+# ---------------------------------------------------------------------------
+# quantile regulariser (Sec. 3.4, training objectives)
+# ---------------------------------------------------------------------------
+
+def test_quantile_homogeneous_medium_closed_form(uniform_scene):
+    # constant sigma along the whole ray: tau(t) = sigma t, so the normalised
+    # CDF is (1 - e^{-sigma t}) / (1 - e^{-sigma t_max}) and its inverse is
+    # -ln(1 - u (1 - e^{-sigma t_max})) / sigma
+    sc = uniform_scene
+    rng = np.random.default_rng(31)
+    o, d, tmax, start = random_inside_rays(rng, 150, 0.0, 1.0, sc.sites)
+    sig = 2.3
+    osc = hand_scene(sc.sites, 0, density=sig, colour=[0.5, 0.5, 0.5])
+    u = rng.uniform(size=(150, 2))
+    u[:5] = [[0.0, 1.0], [1.0, 0.0], [0.5, 0.5], [0.25, 0.75], [1e-9, 1 - 1e-9]]
+    tq, loss = oracle.quantile(osc, o, d, tmax, start, u, eps=0.0)
+    ref = -np.log1p(-u * (1.0 - np.exp(-sig * tmax))[:, None]) / sig
+    np.testing.assert_allclose(tq, ref, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(loss, np.abs(ref[:, 0] - ref[:, 1]), rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(tq[0], [0.0, tmax[0]], atol=1e-12)  # u = 0 and u = 1: the ends of the support
+    assert loss[2] == 0.0
+
+
+def test_quantile_inverts_the_weight_cdf_by_bisection(clustered_scene):
+    # W(t) = 1 - exp(-tau(t)), tau(t) summed over the traced segments with the
+    # scene's densities; bisection on W(t) = u W(end) must land on the oracle's quantile
+    sc = clustered_scene
+    rng = np.random.default_rng(32)
+    o, d, tmax, start = random_inside_rays(rng, 40, -0.9, 0.9, sc.sites)
+    osc = oracle.OracleScene.from_scene(sc)
+    u = rng.uniform(size=(40, 2))
+    tq, loss = oracle.quantile(osc, o, d, tmax, start, u, eps=1e-3)
+    tr = oracle.trace(osc, o, d, tmax, start, eps=1e-3, max_len=512)
+    dens = sc.density.astype(np.float64)
+    for r in range(40):
+        L = tr["len"][r]
+        cells, te = tr["cells"][r, :L], tr["t_exit"][r, :L]
+        t0 = np.concatenate([[0.0], te[:-1]])
+
+        def W(t):
+            return 1.0 - np.exp(-(dens[cells] * np.clip(np.minimum(te, t) - t0, 0, None)).sum())
+
+        total = W(te[-1])
+        for q in range(2):
+            lo, hi = 0.0, te[-1]
+            for _ in range(200):
+                mid = 0.5 * (lo + hi)
+                lo, hi = (mid, hi) if W(mid) < u[r, q] * total else (lo, mid)
+            assert abs(tq[r, q] - hi) <= 1e-9 * max(1.0, te[-1]), (r, q, tq[r, q], hi)
+
+
+def test_quantile_scale_invariance(clustered_scene):
+    sc = clustered_scene
+    rng = np.random.default_rng(33)
+    o, d, tmax, start = random_inside_rays(rng, 60, -0.9, 0.9, sc.sites)
+    u = rng.uniform(size=(60, 2))
+    osc = oracle.OracleScene.from_scene(sc)
+    tq, loss = oracle.quantile(osc, o, d, tmax, start, u, eps=1e-3)
+    s = 4.0
+    osc2 = oracle.OracleScene(sc.sites.astype(np.float64) * s, sc.off, sc.idx, sc.density.astype(np.float64) / s,
+                              sc.sh, sc.sh_deg)
+    tq2, loss2 = oracle.quantile(osc2, o * s, d, tmax * s, start, u, eps=1e-3)
+    np.testing.assert_allclose(tq2, s * tq, rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-2])
+def test_quantile_gradients_match_finite_differences(eps):
+    sc = synth.small_scene("uniform11", 120, seed=34, sh_deg=0)
+    rng = np.random.default_rng(35)
+    o, d, tmax, start = random_inside_rays(rng, 60, -0.9, 0.9, sc.sites)
+    dens = sc.density.astype(np.float64) * (4.0 if eps else 1.0)
+    osc = oracle.OracleScene(sc.sites, sc.off, sc.idx, dens, sc.sh, 0)
+    tr = oracle.trace(osc, o, d, tmax, start, eps=eps)
+    keep = (tr["margin"] > 1e-4) & (tr["graze"] > 1e-4) & ((tr["term"] > 1e-2) | (eps == 0))
+    o, d, tmax, start = o[keep], d[keep], tmax[keep], start[keep]
+    u = rng.uniform(0.05, 0.95, size=(len(d), 2))
+    g = rng.standard_normal(len(d))
+    tq, loss, gs, gd = oracle.quantile(osc, o, d, tmax, start, u, g, eps=eps, threads=1)
+    assert len(d) >= 30 and np.all(tq[:, 0] != tq[:, 1])
+    sites = sc.sites.astype(np.float64)
+
+    def L(sites_=sites, dens_=dens):
+        s = oracle.OracleScene(sites_, sc.off, sc.idx, dens_, sc.sh, 0)
+        return (oracle.quantile(s, o, d, tmax, start, u, eps=eps, threads=1)[1] * g).sum()
+
+    h = 1e-6
+    touched = np.unique(np.concatenate([tr["cells"][keep][r, :tr["len"][keep][r]] for r in range(len(d))]))
+    rng2 = np.random.default_rng(36)
+    for i in rng2.choice(touched, size=min(25, len(touched)), replace=False):
+        for a in range(3):
+            sp, sm = sites.copy(), sites.copy()
+            sp[i, a] += h
+            sm[i, a] -= h
+            fd = (L(sites_=sp) - L(sites_=sm)) / (2 * h)
+            assert abs(fd - gs[i, a]) <= 1e-5 * max(1.0, abs(fd)), (i, a, fd, gs[i, a])
+        dp, dm = dens.copy(), dens.copy()
+        dp[i] += h
+        dm[i] -= h
+        fd = (L(dens_=dp) - L(dens_=dm)) / (2 * h)
+        assert abs(fd - gd[i]) <= 1e-5 * max(1.0, abs(fd)), (i, fd, gd[i])
+    untouched = np.setdiff1d(np.arange(sc.n_sites), touched)
+    assert np.all(gd[untouched] == 0)
+    # a walk that ends on the transmittance test still has a moving last exit,
+    # so the site of the cell behind it (never visited) gets a gradient too
+    beyond = untouched[np.abs(gs[untouched]).max(axis=1) > 0]
+    assert eps > 0 or len(beyond) == 0
+    for i in beyond[:10]:
+        for a in range(3):
+            sp, sm = sites.copy(), sites.copy()
+            sp[i, a] += h
+            sm[i, a] -= h
+            fd = (L(sites_=sp) - L(sites_=sm)) / (2 * h)
+            assert abs(fd - gs[i, a]) <= 1e-5 * max(1.0, abs(fd)), (i, a, fd, gs[i, a])
