@@ -278,6 +278,43 @@ rf_status rf_render_backward_logged(const rf_packed_scene *scene, const rf_rays 
                                     float *grad_density, float *grad_sh, int32_t mode, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Quantile regulariser (Sec. 3.4, training objectives): per ray, the loss
+ * |W^-1(u1) - W^-1(u2)|, where W^-1 is the quantile function of the
+ * normalised distribution of the volume-rendering weights along the ray
+ * (W(t) = 1 - exp(-tau(t)) divided by the ray's opacity 1 - T_final; inside
+ * a cell the density is constant, so W is exponential there) and u1, u2 are
+ * the ray's two uniform draws. A ray with zero opacity has loss 0.
+ *   draws    float[n_rays][2]  u1, u2 in [0, 1] (the caller's random numbers)
+ *   t        float[n_rays][2]  out: W^-1(u1), W^-1(u2) (0 with zero opacity)
+ *   segment  int32[n_rays][2]  out: the visit index holding each quantile (-1: none)
+ *   sigma    float[n_rays][2]  out: that visit's density
+ * The t, segment and sigma arrays are what the backward needs.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    const float *draws;
+    float *t;
+    int32_t *segment;
+    float *sigma;
+} rf_quantiles;
+
+/* Quantiles and per-ray loss (float[n_rays]) of the walks in `log` (written
+ * by rf_render_forward_logged with the same scene, rays and params, whose
+ * t_final is passed; walks longer than the log are walked again). */
+rf_status rf_quantile_forward(const rf_packed_scene *scene, const rf_rays *rays, const rf_params *params,
+                              const float *t_final, const rf_walk_log *log, const rf_quantiles *q, float *loss,
+                              void *stream);
+
+/* rf_render_backward_logged for L = sum grad_rgb.rgb + sum grad_t_final T
+ * + sum grad_loss loss: the quantile term's gradients flow to the densities
+ * and, through the exit distances, to the sites. `q` holds the outputs of
+ * rf_quantile_forward for the same log; grad_loss is float[n_rays]. */
+rf_status rf_render_backward_quantile(const rf_packed_scene *scene, const rf_rays *rays, const rf_params *params,
+                                      const float *rgb, const float *t_final, const float *grad_rgb,
+                                      const float *grad_t_final, const rf_walk_log *log, const rf_quantiles *q,
+                                      const float *grad_loss, float *grad_sites, float *grad_density,
+                                      float *grad_sh, int32_t mode, void *stream);
+
+/* ------------------------------------------------------------------------
  * Traced forward walk, for tests: the forward outputs plus, per ray, the
  * visited cells and each segment's clamped exit distance.
  *   cells   int32[n_rays][max_len]  (entries past the visit count untouched)

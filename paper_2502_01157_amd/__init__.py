@@ -16,9 +16,11 @@ from .ops import (  # noqa: E402,F401
     DEFAULT_LOG_CAPACITY,
     DEFAULT_MAX_STEPS,
     PackedScene,
+    Quantiles,
     RadFoamRender,
     WalkLog,
     locate,
+    quantile_forward,
     raygen,
     render,
     render_backward,

@@ -69,6 +69,11 @@ class WalkLog(ctypes.Structure):
                 ("capacity", ctypes.c_int32)]
 
 
+class Quantiles(ctypes.Structure):
+    _fields_ = [("draws", ctypes.c_void_p), ("t", ctypes.c_void_p), ("segment", ctypes.c_void_p),
+                ("sigma", ctypes.c_void_p)]
+
+
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected_busy", ctypes.c_int64),
                 ("rays_done", ctypes.c_int64), ("pool_used_bytes", ctypes.c_int64), ("pool_bytes", ctypes.c_int64),
@@ -85,6 +90,10 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                               f"or python paper_2502_01157_amd/build.py")
+        # torch first: librf.so and torch both need libamdhip64.so.7, and the
+        # first one loaded serves both, so torch must get its own build of it
+        import torch  # noqa: F401
+
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.c_void_p
         st = ctypes.c_int
@@ -108,12 +117,19 @@ def lib() -> ctypes.CDLL:
         L.rf_render_backward_logged.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Rays),
                                                 ctypes.POINTER(Params), P, P, P, P, ctypes.POINTER(WalkLog), P, P,
                                                 P, ctypes.c_int32, P]
+        L.rf_quantile_forward.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Rays),
+                                          ctypes.POINTER(Params), P, ctypes.POINTER(WalkLog),
+                                          ctypes.POINTER(Quantiles), P, P]
+        L.rf_render_backward_quantile.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Rays),
+                                                  ctypes.POINTER(Params), P, P, P, P, ctypes.POINTER(WalkLog),
+                                                  ctypes.POINTER(Quantiles), P, P, P, P, ctypes.c_int32, P]
         L.rf_locate.argtypes = [ctypes.POINTER(PackedSceneDesc), P, ctypes.c_int64, P, ctypes.c_int32, P, P]
         L.rf_packed_planes.argtypes = [ctypes.POINTER(PackedSceneDesc), P, P]
         L.rf_packed_attributes.argtypes = [ctypes.POINTER(PackedSceneDesc), P, P, P]
         for name in ("rf_packed_bytes", "rf_pack_scene", "rf_packed_errors", "rf_raygen", "rf_render_forward",
                      "rf_render_trace", "rf_render_backward", "rf_render_forward_logged",
-                     "rf_render_backward_logged", "rf_locate", "rf_packed_planes", "rf_packed_attributes"):
+                     "rf_render_backward_logged", "rf_quantile_forward", "rf_render_backward_quantile",
+                     "rf_locate", "rf_packed_planes", "rf_packed_attributes"):
             getattr(L, name).restype = st
         L.rf_server_create.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Params),
                                        ctypes.POINTER(BoundDesc), ctypes.c_size_t, ctypes.c_int32,

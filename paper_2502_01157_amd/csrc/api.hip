@@ -367,6 +367,71 @@ rf_status rf_render_backward_logged(const rf_packed_scene* scene, const rf_rays*
                       "logged backward walk");
 }
 
+static rf_status check_quantiles(const rf_quantiles* q, int64_t n_rays)
+{
+    if (!q) return fail(RF_ERR_INVALID_ARG, "quantiles is NULL");
+    if (n_rays > 0 && (!q->draws || !q->t || !q->segment || !q->sigma))
+        return fail(RF_ERR_INVALID_ARG, "a quantile array is NULL");
+    return RF_OK;
+}
+
+static void set_quantiles(rf::WalkArgs& a, const rf_quantiles* q)
+{
+    a.q_u = q->draws;
+    a.q_t = q->t;
+    a.q_seg = q->segment;
+    a.q_sig = q->sigma;
+}
+
+rf_status rf_quantile_forward(const rf_packed_scene* scene, const rf_rays* rays, const rf_params* params,
+                              const float* t_final, const rf_walk_log* log, const rf_quantiles* q, float* loss,
+                              void* stream)
+{
+    rf_status st;
+    if ((st = check_packed(scene)) != RF_OK || (st = check_rays(rays)) != RF_OK || (st = check_params(params)) != RF_OK)
+        return st;
+    if ((st = check_log(log, rays->n_rays)) != RF_OK || (st = check_quantiles(q, rays->n_rays)) != RF_OK) return st;
+    if (rays->n_rays > 0 && (!t_final || !loss)) return fail(RF_ERR_INVALID_ARG, "t_final or loss is NULL");
+    rf::WalkArgs a = walk_args(scene, rays, params);
+    a.t_final_in = t_final;
+    set_log(a, log);
+    set_quantiles(a, q);
+    a.q_loss = loss;
+    return hip_status(rf::launch_walk(rf::kQuantile, scene->sh_degree, scene->attr_dtype == RF_BF16, a,
+                                      static_cast<hipStream_t>(stream)),
+                      "quantile forward");
+}
+
+rf_status rf_render_backward_quantile(const rf_packed_scene* scene, const rf_rays* rays, const rf_params* params,
+                                      const float* rgb, const float* t_final, const float* grad_rgb,
+                                      const float* grad_t_final, const rf_walk_log* log, const rf_quantiles* q,
+                                      const float* grad_loss, float* grad_sites, float* grad_density, float* grad_sh,
+                                      int32_t mode, void* stream)
+{
+    rf_status st;
+    if ((st = check_packed(scene)) != RF_OK || (st = check_rays(rays)) != RF_OK || (st = check_params(params)) != RF_OK)
+        return st;
+    if (mode != 0 && mode != 1) return fail(RF_ERR_INVALID_ARG, "mode must be 0 or 1");
+    if (rays->n_rays > 0 && (!rgb || !t_final || !grad_rgb || !grad_loss))
+        return fail(RF_ERR_INVALID_ARG, "rgb, t_final, grad_rgb and grad_loss are required");
+    if (!grad_sites || !grad_density || !grad_sh) return fail(RF_ERR_INVALID_ARG, "a gradient array is NULL");
+    if ((st = check_log(log, rays->n_rays)) != RF_OK || (st = check_quantiles(q, rays->n_rays)) != RF_OK) return st;
+    rf::WalkArgs a = walk_args(scene, rays, params);
+    a.rgb_in = rgb;
+    a.t_final_in = t_final;
+    a.grad_rgb = grad_rgb;
+    a.grad_t = grad_t_final;
+    a.g_sites = grad_sites;
+    a.g_density = grad_density;
+    a.g_sh = grad_sh;
+    set_log(a, log);
+    set_quantiles(a, q);
+    a.grad_q = grad_loss;
+    return hip_status(rf::launch_walk(mode == 0 ? rf::kBackwardLogReduce : rf::kBackwardLogAtomic, scene->sh_degree,
+                                      scene->attr_dtype == RF_BF16, a, static_cast<hipStream_t>(stream)),
+                      "backward walk with the quantile term");
+}
+
 rf_status rf_locate(const rf_packed_scene* scene, const float* points, int64_t n_points, const int32_t* seed,
                     int32_t max_steps, int32_t* cells, void* stream)
 {

@@ -161,6 +161,20 @@ __device__ inline void load_site(const unsigned char* __restrict__ rec_base, int
     s[2] = p[2];
 }
 
+// The density of a cell (exactly as unpack_record widens it).
+template <int DEG, bool BF16>
+__device__ inline float load_sigma(const unsigned char* __restrict__ rec_base, int cell)
+{
+    using R = Rec<DEG, BF16>;
+    const unsigned char* p = rec_base + (size_t)cell * R::BYTES;
+    if constexpr (BF16) {
+        const uint32_t w = *reinterpret_cast<const uint32_t*>(p + 4 * (R::NSH >> 1));
+        return (R::NSH & 1) ? bf16_hi(w) : bf16_lo(w);
+    } else {
+        return *reinterpret_cast<const float*>(p + 4 * R::NSH);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Real spherical harmonics, degree <= 3, l-major with m = -l..l, textbook
 // normalisation (orthonormal on the sphere), as polynomials of the unit

@@ -45,6 +45,13 @@ struct WalkArgs {
     double* log_te;      // [log_cap][n_rays] clamped exit distance of the visit
     int4* log_tail;      // [n_rays] (row of the cell after the logged visits, visited cells, 0)
     int32_t log_cap;
+    // quantile regulariser: two draws per ray in, quantiles and their visit out
+    const float* q_u;    // [n_rays][2]
+    float* q_t;          // [n_rays][2] W^-1(u)
+    int32_t* q_seg;      // [n_rays][2] visit index holding it, -1 none
+    float* q_sig;        // [n_rays][2] that visit's density
+    float* q_loss;       // [n_rays]
+    const float* grad_q; // [n_rays] upstream gradient of the loss (backward)
 };
 
 struct PackArgs {
@@ -99,7 +106,8 @@ enum WalkKind {
     kBackwardAtomic = 3,
     kForwardLog = 4,
     kBackwardLogReduce = 5,
-    kBackwardLogAtomic = 6
+    kBackwardLogAtomic = 6,
+    kQuantile = 7
 };
 
 // Records an error message for rf_last_error() on this host thread.

@@ -344,6 +344,30 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
     sh_basis<DEG>(dx, dy, dz, Y);
     if constexpr (REDUCE) em.set_basis(Y);
 
+    // quantile regulariser, if requested: with D = u T_f / (1 - u + u T_f)
+    // (dL/dtau_total of L = -ln(1 - u A)) and the quantile's visit k, density
+    // sigma_k, t = t0_k + (L - tau_<k) / sigma_k gives, for a loss gradient c,
+    // dtau_n += c (D - [n < k]) / sigma_k, plus the two terms outside tau:
+    // dsigma_k -= c (t - t0_k) / sigma_k and the exit before k moves t by c.
+    float qc[2] = {0.0f, 0.0f}, qD[2] = {0.0f, 0.0f}, qs[2] = {1.0f, 1.0f}, qt[2] = {0.0f, 0.0f};
+    int qk[2] = {-1, -1};
+    if (state == 0 && a.grad_q) {
+        const float t_a = a.q_t[2 * r], t_b = a.q_t[2 * r + 1];
+        const int k_a = a.q_seg[2 * r], k_b = a.q_seg[2 * r + 1];
+        if (k_a >= 0 && k_b >= 0 && t_a != t_b) {
+            const float sg = t_a > t_b ? a.grad_q[r] : -a.grad_q[r];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const float u = a.q_u[2 * r + j];
+                qc[j] = j == 0 ? sg : -sg;
+                qD[j] = u * Tfin / (1.0f - u + u * Tfin);
+                qs[j] = a.q_sig[2 * r + j];
+                qt[j] = a.q_t[2 * r + j];
+                qk[j] = a.q_seg[2 * r + j];
+            }
+        }
+    }
+
     float T = 1.0f, Cacc[3] = {0.0f, 0.0f, 0.0f};
     double t0 = 0.0;
     int n = 0;
@@ -410,12 +434,23 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
                 float dtau = -gT * Tfin;
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) dtau = fmaf(g[ch], Tn * v.c[ch] - (Cout[ch] - Cacc[ch]), dtau);
+                float dsig_q = 0.0f, gt_q = 0.0f;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    if (qc[j] != 0.0f) {
+                        dtau += qc[j] * (qD[j] - (n < qk[j] ? 1.0f : 0.0f)) / qs[j];
+                        if (n == qk[j]) {
+                            dsig_q -= qc[j] * (float)((double)qt[j] - t0) / qs[j];
+                            gt_q += qc[j];
+                        }
+                    }
+                }
                 const float sdt = at.sigma * dtau;
                 float edx[3] = {0.0f, 0.0f, 0.0f};
                 if (have_prev) {
                     if (p_moves) {
                         // exit point relative to both sites, in double: p - x = (o - x) + t d
-                        const float gt = p_sdt - sdt;
+                        const float gt = p_sdt - sdt + gt_q;
                         const float s = gt / face_den(p_site, at.site, dx, dy, dz);
                         float pa[3], pb[3];
                         exit_offsets(p_t1, ox, oy, oz, dx, dy, dz, p_site, at.site, pa, pb);
@@ -433,7 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
                 prev.gw[0] = g[0] * w;
                 prev.gw[1] = g[1] * w;
                 prev.gw[2] = g[2] * w;
-                prev.dsig = v.delta * dtau;
+                prev.dsig = fmaf(v.delta, dtau, dsig_q);
                 prev.dx[0] = edx[0];
                 prev.dx[1] = edx[1];
                 prev.dx[2] = edx[2];
@@ -491,6 +526,110 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Quantile regulariser (Sec. 3.4): W^-1(u) of the normalised weight
+// distribution along a ray. With W(t) = 1 - exp(-tau(t)) (constant density in
+// a cell) and A = 1 - T_final, W(t) = u A exactly where the accumulated
+// optical depth reaches L = -ln(1 - u A), so the quantile lies in the first
+// weighted segment k whose depth crosses L, at t0_k + (L - tau_<k) / sigma_k.
+// The visits come from the walk log (one density gather per visit); a walk
+// longer than the log is walked again.
+// ---------------------------------------------------------------------------
+struct QuantileScan {
+    float L[2];
+    bool found[2] = {false, false};
+    int seg[2] = {-1, -1};
+    float sig[2] = {0.0f, 0.0f};
+    double t[2] = {0.0, 0.0};
+    float tau_cum = 0.0f;
+    int last = -1;  // last weighted visit
+    float last_sig = 0.0f;
+    double last_te = 0.0;
+
+    __device__ void visit(int n, float sigma, double t0, double te, float tau)
+    {
+        if (tau > 0.0f) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (!found[j] && tau_cum + tau >= L[j]) {
+                    found[j] = true;
+                    seg[j] = n;
+                    sig[j] = sigma;
+                    t[j] = fmin(fmax(t0 + (double)((L[j] - tau_cum) / sigma), t0), te);
+                }
+            }
+            last = n;
+            last_sig = sigma;
+            last_te = te;
+        }
+        tau_cum += tau;
+    }
+
+    __device__ void finish()
+    {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if (!found[j] && last >= 0) {  // u A beyond the rounded total depth
+                seg[j] = last;
+                sig[j] = last_sig;
+                t[j] = last_te;
+            }
+        }
+    }
+};
+
+template <int DEG, bool BF16>
+__global__ __launch_bounds__(kBlock) void k_quantile(WalkArgs a)
+{
+    const int64_t r = ray_index();
+    if (r >= a.n_rays) return;
+    QuantileScan q;
+    const int start = a.start[r];
+    const float A = 1.0f - a.t_final_in[r];
+    if (start >= 0 && (int64_t)start < a.s.n_sites && A > 0.0f) {
+        q.L[0] = -log1pf(-a.q_u[2 * r] * A);
+        q.L[1] = -log1pf(-a.q_u[2 * r + 1] * A);
+        const int4 tl = a.log_tail[r];
+        if (tl.z >= 0 && tl.z <= a.log_cap) {
+            double t0 = 0.0;
+            for (int n = 0; n < tl.z; ++n) {
+                const uint32_t code = a.log_code[(int64_t)n * a.n_rays + r];
+                const double te = a.log_te[(int64_t)n * a.n_rays + r];
+                const float sigma = load_sigma<DEG, BF16>(a.s.rec, min((int)(code & kLogCell), (int)(a.s.n_sites - 1)));
+                const float delta = (float)(te - t0);
+                q.visit(n, sigma, t0, te, sigma > 0.0f ? sigma * delta : 0.0f);
+                t0 = te;
+            }
+        } else {
+            // the walk outgrew the log: walk it again (same visits as the forward)
+            const float ox = a.origin[3 * r], oy = a.origin[3 * r + 1], oz = a.origin[3 * r + 2];
+            const float dx = a.dir[3 * r], dy = a.dir[3 * r + 1], dz = a.dir[3 * r + 2];
+            float Y[sh_count(DEG)];
+            sh_basis<DEG>(dx, dy, dz, Y);
+            uint2 ref = a.s.row[start];
+            double t0 = 0.0;
+            float T = 1.0f;
+            for (int n = 0; T > a.eps && n < a.max_steps; ++n) {
+                Visit<DEG> v;
+                visit_cell<DEG, BF16>(a.s, ref, t0, a.t_max[r], ox, oy, oz, dx, dy, dz, Y, v);
+                q.visit(n, v.at.sigma, t0, v.te, v.tau);
+                T *= expf(-v.tau);
+                if (v.clipped) break;
+                ref = v.h.next;
+                t0 = v.te;
+            }
+        }
+        q.finish();
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        a.q_t[2 * r + j] = (float)q.t[j];
+        a.q_seg[2 * r + j] = q.seg[j];
+        a.q_sig[2 * r + j] = q.sig[j];
+    }
+    a.q_loss[r] = (q.seg[0] >= 0 && q.seg[1] >= 0) ? fabsf((float)q.t[0] - (float)q.t[1]) : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
 // Dispatch.
 // ---------------------------------------------------------------------------
 template <int DEG, bool BF16>
@@ -524,6 +663,9 @@ static hipError_t launch_walk_t(WalkKind kind, const WalkArgs& a, hipStream_t st
     case kBackwardLogAtomic:
         hipLaunchKernelGGL((k_backward<DEG, BF16, false, true>), grid, block, 0, stream, a);
         hipLaunchKernelGGL((k_backward<DEG, BF16, false, false>), grid, block, 0, stream, a);
+        break;
+    case kQuantile:
+        hipLaunchKernelGGL((k_quantile<DEG, BF16>), grid, block, 0, stream, a);
         break;
     }
     return hipGetLastError();

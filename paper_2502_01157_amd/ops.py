@@ -154,6 +154,40 @@ def raygen(pose12, fov_deg: float, width: int, height: int, bound: tuple, start:
     return o, d, t, s, px
 
 
+class Quantiles:
+    """The quantile regulariser's per-ray state (``rf_quantiles``): the two
+    draws [R,2] and, after ``quantile_forward``, the quantiles, the visit
+    holding each and its density (what the backward needs)."""
+
+    def __init__(self, draws: torch.Tensor):
+        R = int(draws.shape[0])
+        _dev(draws, torch.float32, (R, 2), "draws")
+        self.draws = draws
+        self.t = torch.zeros((R, 2), dtype=torch.float32, device=draws.device)
+        self.segment = torch.full((R, 2), -1, dtype=torch.int32, device=draws.device)
+        self.sigma = torch.zeros((R, 2), dtype=torch.float32, device=draws.device)
+        self.desc = L.Quantiles(_ptr(draws) if R else None, _ptr(self.t) if R else None,
+                                _ptr(self.segment) if R else None, _ptr(self.sigma) if R else None)
+
+
+def quantile_forward(scene: PackedScene, origin, direction, t_max, start, t_final, log: WalkLog, draws,
+                     eps: float = DEFAULT_EPS, max_steps: int = DEFAULT_MAX_STEPS):
+    """Quantile regulariser of the walks in ``log``: (Quantiles, loss [R]) with
+    loss = |W^-1(u1) - W^-1(u2)| per ray (Sec. 3.4)."""
+    R = int(direction.shape[0])
+    dev = direction.device
+    log.check(R)
+    _dev(t_final, torch.float32, (R,), "t_final")
+    q = Quantiles(draws)
+    loss = torch.empty(R, dtype=torch.float32, device=dev)
+    rays = _rays(origin, direction, t_max, start)
+    p = _params(eps, max_steps)
+    L.check(L.lib().rf_quantile_forward(ctypes.byref(scene.desc), ctypes.byref(rays), ctypes.byref(p),
+                                        _ptr(t_final) if R else None, ctypes.byref(log.desc), ctypes.byref(q.desc),
+                                        _ptr(loss) if R else None, _stream(dev)))
+    return q, loss
+
+
 def locate(scene: PackedScene, points, seed=None, max_steps: int = 1 << 20):
     """Nearest site of each point [M,3] (the cell containing it): int32 [M];
     -1 for a seed out of range, -2 if ``max_steps`` greedy steps did not
@@ -233,11 +267,14 @@ def render_trace(scene: PackedScene, origin, direction, t_max, start, eps: float
 
 def render_backward(scene: PackedScene, origin, direction, t_max, start, rgb, t_final, grad_rgb,
                     grad_t_final=None, eps: float = DEFAULT_EPS, max_steps: int = DEFAULT_MAX_STEPS,
-                    mode: int = 0, grads=None, log: Optional[WalkLog] = None):
+                    mode: int = 0, grads=None, log: Optional[WalkLog] = None,
+                    quantiles: Optional["Quantiles"] = None, grad_loss=None):
     """Gradients (sites [N,3], density [N], sh [N,B,3]); accumulated into ``grads`` if given.
 
     With ``log`` (filled by ``render_forward`` on the same scene, rays and
-    parameters) the visits are read from the log instead of recomputed."""
+    parameters) the visits are read from the log instead of recomputed; with
+    ``quantiles`` (from ``quantile_forward`` on that log) and ``grad_loss`` [R]
+    the quantile regulariser's gradient is included."""
     R = int(direction.shape[0])
     dev = direction.device
     n, B = scene.n_sites, sh_count(scene.sh_degree)
@@ -256,7 +293,18 @@ def render_backward(scene: PackedScene, origin, direction, t_max, start, rgb, t_
     _dev(gsh, torch.float32, (n, B, 3), "grad_sh")
     rays = _rays(origin, direction, t_max, start)
     p = _params(eps, max_steps)
-    if log is None:
+    if quantiles is not None:
+        if log is None or grad_loss is None:
+            raise ValueError("the quantile term needs the walk log and grad_loss")
+        log.check(R)
+        _dev(grad_loss, torch.float32, (R,), "grad_loss")
+        L.check(L.lib().rf_render_backward_quantile(ctypes.byref(scene.desc), ctypes.byref(rays), ctypes.byref(p),
+                                                    rgb.data_ptr(), t_final.data_ptr(), grad_rgb.data_ptr(),
+                                                    _ptr(grad_t_final), ctypes.byref(log.desc),
+                                                    ctypes.byref(quantiles.desc), grad_loss.data_ptr(),
+                                                    gs.data_ptr(), gd.data_ptr(), gsh.data_ptr(), int(mode),
+                                                    _stream(dev)))
+    elif log is None:
         L.check(L.lib().rf_render_backward(ctypes.byref(scene.desc), ctypes.byref(rays), ctypes.byref(p),
                                            rgb.data_ptr(), t_final.data_ptr(), grad_rgb.data_ptr(),
                                            _ptr(grad_t_final), gs.data_ptr(), gd.data_ptr(), gsh.data_ptr(),
@@ -274,47 +322,67 @@ class RadFoamRender(torch.autograd.Function):
     """Differentiable render of rays through a Voronoi scene.
 
     forward(sites, density, sh, off, idx, origin, dir, t_max, start, sh_degree,
-            attr_dtype, eps, max_steps) -> (rgb [R,3], t_final [R])
+            attr_dtype, eps, max_steps, log_capacity, quantile_draws)
+        -> (rgb [R,3], t_final [R], steps [R], quantile_loss [R])
 
     Packs the scene (face planes from the current sites, attributes in
     ``attr_dtype``), walks every ray, and saves a walk log of the first
     ``log_capacity`` visits per ray (0: none; the backward then recomputes
-    every walk). Gradients flow to sites, density and sh; none to the rays or
-    the adjacency.
+    every walk). With ``quantile_draws`` [R,2] it also returns the quantile
+    regulariser |W^-1(u1) - W^-1(u2)| per ray (Sec. 3.4; zeros otherwise).
+    Gradients flow to sites, density and sh; none to the rays or the adjacency.
     """
 
     @staticmethod
     def forward(ctx, sites, density, sh, off, idx, origin, direction, t_max, start, sh_degree: int = 3,
                 attr_dtype: str = "f32", eps: float = DEFAULT_EPS, max_steps: int = DEFAULT_MAX_STEPS,
-                log_capacity: int = DEFAULT_LOG_CAPACITY):
+                log_capacity: int = DEFAULT_LOG_CAPACITY, quantile_draws=None):
         sites_c, dens_c, sh_c = sites.detach().contiguous(), density.detach().contiguous(), sh.detach().contiguous()
         scene = PackedScene(sites_c, off, idx, dens_c, sh_c, sh_degree, attr_dtype, validate=False)
-        log = WalkLog(int(direction.shape[0]), log_capacity, direction.device) if log_capacity > 0 else None
+        R = int(direction.shape[0])
+        want_log = log_capacity > 0 or quantile_draws is not None
+        log = WalkLog(R, max(log_capacity, 0), direction.device) if want_log else None
         rgb, tf, steps = render_forward(scene, origin, direction, t_max, start, eps, max_steps, log=log)
+        q = None
+        if quantile_draws is not None:
+            q, qloss = quantile_forward(scene, origin, direction, t_max, start, tf, log,
+                                        quantile_draws.detach().contiguous().float(), eps, max_steps)
+        else:
+            qloss = torch.zeros(R, dtype=torch.float32, device=direction.device)
         ctx.scene = scene
         ctx.log = log
+        ctx.q = q
         ctx.hyper = (eps, max_steps)
         ctx.save_for_backward(origin, direction, t_max, start, rgb, tf)
         ctx.mark_non_differentiable(steps)
-        return rgb, tf, steps
+        if q is None:
+            ctx.mark_non_differentiable(qloss)
+        return rgb, tf, steps, qloss
 
     @staticmethod
-    def backward(ctx, grad_rgb, grad_tf, _grad_steps):
+    def backward(ctx, grad_rgb, grad_tf, _grad_steps, grad_q):
         origin, direction, t_max, start, rgb, tf = ctx.saved_tensors
         eps, max_steps = ctx.hyper
         if grad_rgb is None:
             grad_rgb = torch.zeros_like(rgb)
+        q = ctx.q
+        if q is not None and grad_q is None:
+            q = None
         gs, gd, gsh = render_backward(ctx.scene, origin, direction, t_max, start, rgb, tf,
                                       grad_rgb.contiguous().float(),
                                       None if grad_tf is None else grad_tf.contiguous().float(), eps, max_steps,
-                                      log=ctx.log)
+                                      log=ctx.log, quantiles=q,
+                                      grad_loss=None if q is None else grad_q.contiguous().float())
         ctx.log = None
-        return gs, gd, gsh, None, None, None, None, None, None, None, None, None, None, None
+        ctx.q = None
+        return gs, gd, gsh, None, None, None, None, None, None, None, None, None, None, None, None
 
 
 def render(sites, density, sh, off, idx, origin, direction, t_max, start, sh_degree: int = 3,
            attr_dtype: str = "f32", eps: float = DEFAULT_EPS, max_steps: int = DEFAULT_MAX_STEPS,
-           log_capacity: int = DEFAULT_LOG_CAPACITY):
-    """Autograd entry point: returns (rgb, t_final, steps)."""
-    return RadFoamRender.apply(sites, density, sh, off, idx, origin, direction, t_max, start, sh_degree,
-                               attr_dtype, eps, max_steps, log_capacity)
+           log_capacity: int = DEFAULT_LOG_CAPACITY, quantile_draws=None):
+    """Autograd entry point: (rgb, t_final, steps), plus the per-ray quantile
+    loss when ``quantile_draws`` [R,2] is given."""
+    out = RadFoamRender.apply(sites, density, sh, off, idx, origin, direction, t_max, start, sh_degree,
+                              attr_dtype, eps, max_steps, log_capacity, quantile_draws)
+    return out if quantile_draws is not None else out[:3]

@@ -1,0 +1,196 @@
+"""Quantile regulariser (Sec. 3.4) on the GPU against the FP64 oracle.
+
+The GPU finds each quantile where the FP32 accumulated optical depth reaches
+L = -ln(1 - u (1 - T_final)) and places it at t0_k + (L - tau_<k) / sigma_k.
+L and tau_<k carry relative errors of about n eps32 (a product of n
+transmittance factors, a running sum of n depths, n ~ 100), so
+|t - t_ref| <= 5e-5 (1 + L + tau_<k) / sigma_k is the bound checked. The loss
+is discontinuous where a quantile's depth meets a segment boundary (the
+segment k changes), so gradients are compared on rays whose L_j is not within
+1e-4 (1 + L_j) of any boundary depth, whose quantiles differ, and which are
+decidable for the walk itself.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from parity import GRAD_RTOL, camera_rays, decidable, grad_err, inside_rays
+
+pytestmark = pytest.mark.gpu
+
+
+def _dv(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def setup():
+    scene, rng = synth.small_scene("clustered", 20000, seed=61, sh_deg=3, return_rng=True)
+    cam = synth.make_cameras("clustered_200k", rng, n=1, res=(64, 48))[0]
+    cam_rays = camera_rays(scene, cam)[:4]
+    in_rays = inside_rays(scene, np.random.default_rng(62), 1000, -0.95, 0.95)
+    rays = tuple(np.concatenate([a, b]) for a, b in zip(cam_rays, in_rays))
+    return scene, rays
+
+
+def _boundary_depths(scene, tr, r):
+    L = tr["len"][r]
+    cells, te = tr["cells"][r, :L], tr["t_exit"][r, :L]
+    t0 = np.concatenate([[0.0], te[:-1]])
+    return np.cumsum(scene.density.astype(np.float64)[cells] * (te - t0))
+
+
+def _run(rf, scene, rays, u, eps, cap, dtype="f32", grad=None):
+    import torch
+
+    p = rf.PackedScene(*map(_dv, (scene.sites, scene.off, scene.idx, scene.density, scene.sh)), scene.sh_deg, dtype)
+    o, d, t, s = map(_dv, rays)
+    log = rf.WalkLog(len(rays[2]), cap, o.device)
+    rgb, tf, steps = rf.render_forward(p, o, d, t, s, eps=eps, log=log)
+    q, loss = rf.quantile_forward(p, o, d, t, s, tf, log, _dv(u), eps=eps)
+    out = dict(t=q.t.cpu().numpy(), seg=q.segment.cpu().numpy(), sig=q.sigma.cpu().numpy(), loss=loss.cpu().numpy(),
+               tf=tf.cpu().numpy())
+    if grad is not None:
+        g_rgb, g_q = grad
+        gs, gd, gsh = rf.render_backward(p, o, d, t, s, rgb, tf, _dv(g_rgb), eps=eps, log=log, quantiles=q,
+                                         grad_loss=_dv(g_q))
+        out["grads"] = (gs.cpu().numpy(), gd.cpu().numpy(), gsh.cpu().numpy())
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("cap", [256, 16])
+def test_quantiles_and_loss_match_oracle(setup, dtype, cap):
+    import paper_2502_01157_amd as rf
+
+    scene, rays = setup
+    R = len(rays[2])
+    u = np.random.default_rng(63).uniform(size=(R, 2)).astype(np.float32)
+    u[:4] = [[0.0, 1.0], [0.5, 0.5], [1.0, 0.25], [0.0, 0.0]]
+    dens, sh = scene.density, scene.sh
+    if dtype == "bf16":
+        dens = oracle.bf16_to_f32(oracle.bf16_round(dens))
+        sh = oracle.bf16_to_f32(oracle.bf16_round(sh))
+    osc = oracle.OracleScene.from_scene(scene, density=dens, sh=sh)
+    tq_ref, loss_ref = oracle.quantile(osc, *rays, u.astype(np.float64), eps=1e-4)
+    tr = oracle.trace(osc, *rays, eps=1e-4, max_len=1024)
+    dec = decidable(tr, 1e-4)
+    g = _run(rf, scene, rays, u, 1e-4, cap, dtype)
+    checked = 0
+    for r in np.nonzero(dec)[0]:
+        tau = _boundary_depths(osc, tr, r)
+        A = 1.0 - tr["t_final"][r]
+        for j in range(2):
+            if g["seg"][r, j] < 0:
+                assert A == 0.0 or tr["len"][r] == 0
+                continue
+            Lj = -np.log1p(-u[r, j] * A)
+            k = g["seg"][r, j]
+            tau_lt = tau[k - 1] if k > 0 else 0.0
+            tol = 5e-5 * (1.0 + Lj + tau_lt) / g["sig"][r, j] + 1e-6 * abs(tq_ref[r, j])
+            assert abs(g["t"][r, j] - tq_ref[r, j]) <= tol, (r, j, g["t"][r, j], tq_ref[r, j], tol)
+            checked += 1
+    assert checked > 0.9 * 2 * dec.sum()
+    np.testing.assert_array_equal(g["loss"][1], 0.0)  # u1 = u2
+    assert g["t"][0, 0] <= g["t"][0, 1]
+
+
+@pytest.mark.parametrize("cap", [256, 16])
+def test_gradients_with_quantile_term_match_oracle(setup, cap):
+    import paper_2502_01157_amd as rf
+
+    scene, rays = setup
+    R = len(rays[2])
+    rng = np.random.default_rng(64)
+    u = rng.uniform(0.02, 0.98, size=(R, 2)).astype(np.float32)
+    osc = oracle.OracleScene.from_scene(scene)
+    tr = oracle.trace(osc, *rays, eps=1e-4, max_len=1024)
+    tq_ref, _ = oracle.quantile(osc, *rays, u.astype(np.float64), eps=1e-4)
+    keep = decidable(tr, 1e-4) & (np.abs(tq_ref[:, 0] - tq_ref[:, 1]) > 1e-3)
+    for r in np.nonzero(keep)[0]:
+        tau = _boundary_depths(osc, tr, r)
+        A = 1.0 - tr["t_final"][r]
+        for j in range(2):
+            Lj = -np.log1p(-u[r, j] * A)
+            if len(tau) == 0 or np.min(np.abs(tau - Lj)) < 1e-4 * (1.0 + Lj):
+                keep[r] = False
+    assert keep.mean() > 0.8
+    rays = tuple(a[keep] for a in rays)
+    u = u[keep]
+    n = len(rays[2])
+    g_rgb = rng.standard_normal((n, 3)).astype(np.float32)
+    g_q = rng.standard_normal(n).astype(np.float32)
+    ref_c = oracle.backward(osc, *rays, g_rgb, eps=1e-4)
+    _, _, ref_qs, ref_qd = oracle.quantile(osc, *rays, u.astype(np.float64), g_q, eps=1e-4)
+    ref = (ref_c[0] + ref_qs, ref_c[1] + ref_qd, ref_c[2])
+    got = _run(rf, scene, rays, u, 1e-4, cap, grad=(g_rgb, g_q))["grads"]
+    errs = [grad_err(x, y) for x, y in zip(got, ref)]
+    assert max(errs) <= GRAD_RTOL, errs
+    # the quantile term alone
+    got0 = _run(rf, scene, rays, u, 1e-4, cap, grad=(np.zeros_like(g_rgb), g_q))["grads"]
+    assert grad_err(got0[0], ref_qs) <= GRAD_RTOL and grad_err(got0[1], ref_qd) <= GRAD_RTOL
+    assert np.all(got0[2] == 0)
+
+
+def test_autograd_quantile_loss(setup):
+    import torch
+
+    import paper_2502_01157_amd as rf
+
+    scene, rays = setup
+    R = len(rays[2])
+    u = _dv(np.random.default_rng(65).uniform(size=(R, 2)).astype(np.float32))
+    sites, off, idx, dens, sh = map(_dv, (scene.sites, scene.off, scene.idx, scene.density, scene.sh))
+    for x in (sites, dens, sh):
+        x.requires_grad_(True)
+    o, d, t, s = map(_dv, rays)
+    rgb, tf, steps, qloss = rf.render(sites, dens, sh, off, idx, o, d, t, s, 3, quantile_draws=u)
+    g = torch.randn_like(rgb)
+    ((rgb * g).sum() + 0.1 * qloss.sum()).backward()
+    p = rf.PackedScene(*map(_dv, (scene.sites, scene.off, scene.idx, scene.density, scene.sh)), 3)
+    log = rf.WalkLog(R, 256, o.device)
+    rgb2, tf2, _ = rf.render_forward(p, o, d, t, s, log=log)
+    q, loss2 = rf.quantile_forward(p, o, d, t, s, tf2, log, u)
+    assert torch.equal(qloss.detach(), loss2)
+    ref = rf.render_backward(p, o, d, t, s, rgb2, tf2, g, log=log, quantiles=q,
+                             grad_loss=torch.full_like(loss2, 0.1))
+    for x, y in zip((sites.grad, dens.grad, sh.grad), ref):
+        assert grad_err(x.cpu().numpy(), y.cpu().numpy()) < 1e-5
+    # without draws: three outputs, as before
+    assert len(rf.render(sites, dens, sh, off, idx, o, d, t, s, 3)) == 3
+
+
+def test_quantile_edge_cases(setup):
+    import torch
+
+    import paper_2502_01157_amd as rf
+
+    scene, rays = setup
+    o, d, t, s = map(_dv, (a[:64] for a in rays))
+    R = 64
+    # no density: no opacity, loss 0, no gradient
+    p0 = rf.PackedScene(*map(_dv, (scene.sites, scene.off, scene.idx, np.zeros_like(scene.density), scene.sh)), 3)
+    log = rf.WalkLog(R, 256, o.device)
+    rgb, tf, _ = rf.render_forward(p0, o, d, t, s, log=log)
+    q, loss = rf.quantile_forward(p0, o, d, t, s, tf, log, torch.rand((R, 2), device=o.device))
+    assert torch.all(loss == 0) and torch.all(q.segment == -1)
+    gs, gd, gsh = rf.render_backward(p0, o, d, t, s, rgb, tf, torch.zeros_like(rgb), log=log, quantiles=q,
+                                     grad_loss=torch.ones_like(loss))
+    assert torch.all(gs == 0) and torch.all(gd == 0)
+    # bad start cells
+    p = rf.PackedScene(*map(_dv, (scene.sites, scene.off, scene.idx, scene.density, scene.sh)), 3)
+    bad = torch.full_like(s, -1)
+    rgb, tf, _ = rf.render_forward(p, o, d, t, bad, log=log)
+    q, loss = rf.quantile_forward(p, o, d, t, bad, tf, log, torch.rand((R, 2), device=o.device))
+    assert torch.all(loss == 0)
+    # argument errors
+    with pytest.raises(ValueError):
+        rf.render_backward(p, o, d, t, s, rgb, tf, torch.zeros_like(rgb), quantiles=q, grad_loss=loss)
+    with pytest.raises(ValueError):
+        rf.quantile_forward(p, o, d, t, s, tf, rf.WalkLog(R + 1, 8, o.device), torch.rand((R, 2), device=o.device))
