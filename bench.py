@@ -103,6 +103,7 @@ def main() -> int:
     ap.add_argument("--only", choices=["f32", "bf16"], default=None, help="time one attribute precision only")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving replay (512 Poisson requests)")
     ap.add_argument("--no-locate", action="store_true", help="skip the start-cell location timing")
+    ap.add_argument("--no-quantile", action="store_true", help="skip the quantile regulariser timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -284,10 +285,54 @@ def main() -> int:
         out["serving"] = serving(rf, scenes, scene, bound, dts)
     if not args.no_locate:
         out["locate"] = locate(rf, scenes["f32"], bound, dev)
+    if not args.no_quantile and walk_log is not None:
+        out["quantile"] = quantile_cost(rf, scenes["f32"], rays, grad_rgb, walk_log, dev, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, cam, bound, start, g_np, visits / R, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def quantile_cost(rf, packed, rays, grad_rgb, walk_log, dev, reps: int):
+    """Cost of the quantile regulariser (Sec. 3.4) on top of a logged training
+    step: the quantile kernel over the walk log, and the logged backward with
+    and without the quantile term (FP32 attributes, uniform draws)."""
+    import torch
+
+    o, d, t, s = rays
+    R = int(d.shape[0])
+    g = torch.Generator(device=dev)
+    g.manual_seed(11)
+    draws = torch.rand((R, 2), device=dev, generator=g)
+    grad_loss = torch.full((R,), 1.0 / R, device=dev)
+    n, B = packed.n_sites, (packed.sh_degree + 1) ** 2
+    grads = (torch.zeros((n, 3), device=dev), torch.zeros(n, device=dev), torch.zeros((n, B, 3), device=dev))
+    rgb, tf, _ = rf.render_forward(packed, o, d, t, s, log=walk_log)
+    q, loss = rf.quantile_forward(packed, o, d, t, s, tf, walk_log, draws)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            ev[0].record()
+            fn()
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms.append(ev[0].elapsed_time(ev[1]))
+        return float(np.mean(ms))
+
+    ms_q = timed(lambda: rf.quantile_forward(packed, o, d, t, s, tf, walk_log, draws))
+    ms_b = timed(lambda: rf.render_backward(packed, o, d, t, s, rgb, tf, grad_rgb, grads=grads, log=walk_log))
+    ms_bq = timed(lambda: rf.render_backward(packed, o, d, t, s, rgb, tf, grad_rgb, grads=grads, log=walk_log,
+                                             quantiles=q, grad_loss=grad_loss))
+    mean_loss = float(loss.mean())
+    log(f"quantile: kernel {ms_q:.3f} ms, backward {ms_b:.3f} ms without / {ms_bq:.3f} ms with the quantile "
+        f"term, mean loss {mean_loss:.5f}")
+    return {"quantile_kernel_ms": round(ms_q, 4), "backward_ms": round(ms_b, 4),
+            "backward_with_quantile_ms": round(ms_bq, 4), "mean_loss": round(mean_loss, 6)}
 
 
 def locate(rf, packed, bound, dev, n_points: int = 1 << 20, grid: int = 32):
