@@ -36,10 +36,32 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
+class _Surface(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("max_bounces", ctypes.c_int32), ("centre", ctypes.c_double * 3),
+                ("radius", ctypes.c_double), ("ior", ctypes.c_double), ("bound_kind", ctypes.c_int32),
+                ("bound", ctypes.c_double * 6)]
+
+
 class _Scene(ctypes.Structure):
     _fields_ = [("sites", ctypes.c_void_p), ("off", ctypes.c_void_p), ("idx", ctypes.c_void_p),
                 ("density", ctypes.c_void_p), ("sh", ctypes.c_void_p),
-                ("n_sites", ctypes.c_int64), ("sh_deg", ctypes.c_int32)]
+                ("n_sites", ctypes.c_int64), ("sh_deg", ctypes.c_int32), ("surf", ctypes.POINTER(_Surface))]
+
+
+SURFACE_KINDS = {"none": 0, "mirror": 1, "glass": 2}
+
+
+class Surface:
+    """An analytic sphere in the scene that bends rays (mirror, or glass of
+    refractive index ``ior`` inside); legs after a crossing end at ``bound``
+    (the raygen bound); crossings after the first ``max_bounces`` are ignored."""
+
+    def __init__(self, kind: str, centre, radius: float, bound: tuple, ior: float = 1.5, max_bounces: int = 8):
+        self.kind, self.centre, self.radius, self.ior = kind, tuple(float(c) for c in centre), float(radius), float(ior)
+        self.bound, self.max_bounces = bound, int(max_bounces)
+        bk, bp = encode_bound(bound)
+        self._c = _Surface(SURFACE_KINDS[kind], self.max_bounces, (ctypes.c_double * 3)(*self.centre), self.radius,
+                           self.ior, bk, (ctypes.c_double * 6)(*bp))
 
 
 _lib = None
@@ -53,7 +75,8 @@ def _load():
         lib = ctypes.CDLL(_LIB_PATH)
         P = ctypes.c_void_p
         lib.orc_sh_basis.argtypes = [ctypes.c_int, P, ctypes.c_int64, P]
-        lib.orc_raygen.argtypes = [P, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P]
+        lib.orc_raygen.argtypes = [P, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P,
+                                   P, P, P]
         lib.orc_face_planes.argtypes = [P, P, P, ctypes.c_int64, P]
         lib.orc_bf16_round.argtypes = [P, P, ctypes.c_int64]
         lib.orc_nearest_site.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P]
@@ -64,7 +87,7 @@ def _load():
         lib.orc_forward.argtypes = [ctypes.POINTER(_Scene), P, P, P, P, ctypes.c_int64, ctypes.c_double,
                                     ctypes.c_int32, ctypes.c_int, P, P, P]
         lib.orc_trace.argtypes = [ctypes.POINTER(_Scene), P, P, P, P, ctypes.c_int64, ctypes.c_double,
-                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int, P, P, P, P, P, P, P, P, P]
+                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int, P, P, P, P, P, P, P, P, P, P, P, P]
         lib.orc_backward.argtypes = [ctypes.POINTER(_Scene), P, P, P, P, ctypes.c_int64, ctypes.c_double,
                                      ctypes.c_int32, P, P, ctypes.c_int, P, P, P]
         _lib = lib
@@ -95,7 +118,7 @@ def default_threads() -> int:
 class OracleScene:
     """Scene arrays widened to float64 and held alive for the C calls."""
 
-    def __init__(self, sites, off, idx, density, sh, sh_deg: int):
+    def __init__(self, sites, off, idx, density, sh, sh_deg: int, surface: Optional[Surface] = None):
         self.sites = _f64(sites).reshape(-1, 3)
         self.off = _i32(off)
         self.idx = _i32(idx)
@@ -106,13 +129,14 @@ class OracleScene:
         n = self.sites.shape[0]
         if self.off.shape[0] != n + 1 or self.density.shape[0] != n or self.sh.shape[0] != n:
             raise ValueError("scene arrays disagree on the number of sites")
+        self.surface = surface
         self._c = _Scene(_ptr(self.sites), _ptr(self.off), _ptr(self.idx), _ptr(self.density), _ptr(self.sh),
-                         n, self.sh_deg)
+                         n, self.sh_deg, ctypes.pointer(surface._c) if surface is not None else None)
 
     @classmethod
-    def from_scene(cls, scene, density=None, sh=None) -> "OracleScene":
+    def from_scene(cls, scene, density=None, sh=None, surface: Optional[Surface] = None) -> "OracleScene":
         return cls(scene.sites, scene.off, scene.idx, scene.density if density is None else density,
-                   scene.sh if sh is None else sh, scene.sh_deg)
+                   scene.sh if sh is None else sh, scene.sh_deg, surface)
 
     @property
     def n_sites(self) -> int:
@@ -131,8 +155,11 @@ def sh_basis(deg: int, dirs) -> np.ndarray:
     return out
 
 
-def raygen(pose12, fov_deg: float, width: int, height: int, bound: tuple):
-    """Pinhole rays in 8x8 tile order. Returns (origin, dir, tmax, pixel)."""
+CAMERA_MODELS = {"pinhole": 0, "fisheye": 1}
+
+
+def raygen(pose12, fov_deg: float, width: int, height: int, bound: tuple, model: str = "pinhole"):
+    """Camera rays (pinhole, or equidistant fisheye) in 8x8 tile order. Returns (origin, dir, tmax, pixel)."""
     pose = _f64(pose12).reshape(12)
     kind, params = encode_bound(bound)
     R = width * height
@@ -140,7 +167,8 @@ def raygen(pose12, fov_deg: float, width: int, height: int, bound: tuple):
     d = np.empty((R, 3))
     t = np.empty(R)
     px = np.empty(R, dtype=np.int32)
-    _check(_load().orc_raygen(_ptr(pose), float(fov_deg), int(width), int(height), kind, _ptr(params),
+    _check(_load().orc_raygen(_ptr(pose), float(fov_deg), int(width), int(height), CAMERA_MODELS[model], kind,
+                              _ptr(params),
                               _ptr(o), _ptr(d), _ptr(t), _ptr(px)), "raygen")
     return o, d, t, px
 
@@ -222,16 +250,23 @@ def forward(scene: OracleScene, o, d, tmax, start, eps: float = DEFAULT_EPS,
 
 
 def trace(scene: OracleScene, o, d, tmax, start, eps: float = DEFAULT_EPS,
-          max_steps: int = DEFAULT_MAX_STEPS, max_len: int = 1024, threads: Optional[int] = None) -> dict:
-    """Forward plus per-visit cells, exit distances and decision margins."""
+          max_steps: int = DEFAULT_MAX_STEPS, max_len: int = 1024, threads: Optional[int] = None,
+          legs: bool = False) -> dict:
+    """Forward plus per-visit cells, exit distances (along each visit's leg), decision margins,
+    per-visit surface crossings (``bounce``) and the surface decisions' margin (``surf_margin``);
+    with ``legs`` also each visit's leg origin and direction [R, max_len, 6]."""
     o, d, t, s, R = _rays(o, d, tmax, start)
     out = dict(rgb=np.empty((R, 3)), t_final=np.empty(R), steps=np.empty(R, dtype=np.int32),
                cells=np.full((R, max_len), -1, dtype=np.int32), t_exit=np.full((R, max_len), np.nan),
-               len=np.empty(R, dtype=np.int32), margin=np.empty(R), graze=np.empty(R), term=np.empty(R))
+               len=np.empty(R, dtype=np.int32), margin=np.empty(R), graze=np.empty(R), term=np.empty(R),
+               bounce=np.zeros((R, max_len), dtype=np.int8), surf_margin=np.empty(R))
+    if legs:
+        out["legs"] = np.full((R, max_len, 6), np.nan)
     _check(_load().orc_trace(ctypes.byref(scene._c), _ptr(o), _ptr(d), _ptr(t), _ptr(s), R, float(eps),
                              int(max_steps), int(max_len), threads or default_threads(),
-                             *[_ptr(out[k]) for k in ("rgb", "t_final", "steps", "cells", "t_exit", "len",
-                                                      "margin", "graze", "term")]), "trace")
+                             *[_ptr(out.get(k)) for k in ("rgb", "t_final", "steps", "cells", "t_exit", "len",
+                                                          "margin", "graze", "term", "bounce", "legs",
+                                                          "surf_margin")]), "trace")
     return out
 
 

@@ -31,6 +31,16 @@
  *   - the face shared with the previous cell is skipped.
  *   - T > eps is tested before each cell; at most max_steps cells are visited.
  *   - tau = sigma * delta, with tau = 0 when sigma == 0.
+ *   - secondary rays (the ray-based effects of Fig. 3): a scene may hold one
+ *     analytic sphere, a mirror or a glass interface (refractive index eta
+ *     inside, 1 outside). Where a ray crosses it inside cell i, the segment
+ *     ends there, and the walk continues in cell i along the reflected or
+ *     refracted ray (Snell's law; total internal reflection reflects), which
+ *     starts a new leg with t = 0 at the crossing and its own t_max at the
+ *     scene bound. The crossing splits the cell's visit in two; the
+ *     transmittance test before each cell is not repeated for the second
+ *     part. The foam fills the sphere too; one ray continues (no Fresnel
+ *     split); crossings after the first max_bounces are ignored.
  *
  * Per-ray status (steps[]): >= 0 the number of visited cells; -1 the start
  * cell is out of range; -2 the walk stopped because max_steps cells were
@@ -52,6 +62,19 @@
 #define ORC_BAD_START (-1)
 #define ORC_MAX_STEPS (-2)
 
+#define ORC_SURF_NONE 0
+#define ORC_SURF_MIRROR 1
+#define ORC_SURF_GLASS 2
+
+typedef struct {
+    int32_t kind;        /* ORC_SURF_* */
+    int32_t max_bounces; /* crossings handled per ray */
+    double centre[3], radius;
+    double ior;          /* glass: refractive index inside the sphere (outside: 1) */
+    int32_t bound_kind;  /* where the legs after a crossing end (see exit_distance) */
+    double bound[6];
+} orc_surface;
+
 typedef struct {
     const double *sites;   /* [N,3] */
     const int32_t *off;    /* [N+1] */
@@ -60,6 +83,7 @@ typedef struct {
     const double *sh;      /* [N,B,3] */
     int64_t n_sites;
     int32_t sh_deg;
+    const orc_surface *surf; /* NULL: no surface */
 } orc_scene;
 
 /* ------------------------------------------------------------------------ */
@@ -143,18 +167,36 @@ static double exit_distance(int bound_kind, const double *bp, const double o[3],
     return disc > 0.0 ? fmax(-b + sqrt(disc), 0.0) : 0.0;
 }
 
-int orc_raygen(const double *pose, double fov_deg, int W, int H, int bound_kind, const double *bound_params,
-               double *origin, double *dir, double *tmax, int32_t *pixel)
+/* model 0, pinhole: the pixel centre's offset (u, v) from the image centre,
+ * in pixels, maps to the camera-frame direction (u / f, v / f, 1) normalised,
+ * f = (W/2) / tan(fov/2).
+ * model 1, equidistant fisheye (a non-linear camera, Fig. 3): the angle from
+ * the optical axis grows linearly with the distance rho = |(u, v)| from the
+ * image centre, theta = rho (fov/2) / (W/2), so the left and right image
+ * edges are at fov/2; the direction is (sin theta u/rho, sin theta v/rho,
+ * cos theta) (the axis itself at rho = 0). */
+int orc_raygen(const double *pose, double fov_deg, int W, int H, int model, int bound_kind,
+               const double *bound_params, double *origin, double *dir, double *tmax, int32_t *pixel)
 {
-    if (W <= 0 || H <= 0 || !(fov_deg > 0.0 && fov_deg < 180.0) || bound_kind < 0 || bound_kind > 1)
-        return ORC_EINVAL;
-    const double f = 0.5 * W / tan(0.5 * fov_deg * M_PI / 180.0);
+    if (W <= 0 || H <= 0 || bound_kind < 0 || bound_kind > 1 || model < 0 || model > 1) return ORC_EINVAL;
+    if (model == 0 && !(fov_deg > 0.0 && fov_deg < 180.0)) return ORC_EINVAL;
+    if (model == 1 && !(fov_deg > 0.0 && fov_deg <= 360.0)) return ORC_EINVAL;
+    const double half = 0.5 * fov_deg * M_PI / 180.0;
+    const double f = 0.5 * W / tan(half);
     const double p[3] = {pose[3], pose[7], pose[11]};
     const int64_t R = (int64_t)W * H;
     for (int64_t r = 0; r < R; ++r) {
         int px, py;
         tile_pixel(r, W, H, &px, &py);
-        const double cam[3] = {(px + 0.5 - 0.5 * W) / f, (py + 0.5 - 0.5 * H) / f, 1.0};
+        const double u = px + 0.5 - 0.5 * W, v = py + 0.5 - 0.5 * H;
+        double cam[3] = {u / f, v / f, 1.0};
+        if (model == 1) {
+            const double rho = sqrt(u * u + v * v);
+            const double theta = rho * half / (0.5 * W);
+            cam[0] = rho > 0.0 ? sin(theta) * u / rho : 0.0;
+            cam[1] = rho > 0.0 ? sin(theta) * v / rho : 0.0;
+            cam[2] = cos(theta);
+        }
         double d[3];
         for (int a = 0; a < 3; ++a) d[a] = pose[4 * a + 0] * cam[0] + pose[4 * a + 1] * cam[1] + pose[4 * a + 2] * cam[2];
         const double len = sqrt(dot3(d, d));
@@ -263,7 +305,9 @@ typedef struct {
     double tau;        /* sigma * delta */
     double T;          /* transmittance before the segment */
     double c[3];       /* cell colour along d */
-    int moves;         /* the exit is t1 itself (not clamped, not clipped) */
+    int moves;         /* the exit is t1 itself (not clamped, not clipped, not at the surface) */
+    int bounce;        /* the segment ends where the leg crosses the surface */
+    double o[3], d[3]; /* the leg: t is measured from o along d */
 } visit_t;
 
 typedef struct {
@@ -275,6 +319,8 @@ typedef struct {
     double margin;   /* min over decisions of the scaled gap to the runner-up face / t_max */
     double graze;    /* min |cos| over non-front faces other than the entry face */
     double term;     /* min |ln T - ln eps| over the transmittance tests */
+    double surf;     /* min over surface decisions: |cos| at a crossing, |1 - eta^2 sin^2| at a
+                        refraction, the scaled gap between the crossing and the nearest face / t_max */
 } margins_t;
 
 static void push_visit(visit_buf *b, const visit_t *v)
@@ -289,6 +335,60 @@ static void push_visit(visit_buf *b, const visit_t *v)
     b->v[b->len++] = *v;
 }
 
+/* Distance along the leg (o, d) to its next crossing of the surface, +inf
+ * if none: the far root of |o + t d - c| = radius when the leg starts inside
+ * the sphere, the near positive root when it starts outside (a leg leaving
+ * the surface outwards has no positive near root). */
+static double surface_hit(const orc_surface *sf, const double o[3], const double d[3], int inside)
+{
+    double oc[3];
+    for (int a = 0; a < 3; ++a) oc[a] = o[a] - sf->centre[a];
+    const double b = dot3(oc, d);
+    const double c = dot3(oc, oc) - sf->radius * sf->radius;
+    const double disc = b * b - c;
+    if (!(disc > 0.0)) return INFINITY;
+    const double t = inside ? -b + sqrt(disc) : -b - sqrt(disc);
+    return t > 0.0 ? t : INFINITY;
+}
+
+/* The leg after a crossing at p with incoming direction d: the outward unit
+ * normal N = (p - c)/|p - c|; a mirror reflects, d' = d - 2 (d.N) N; glass
+ * refracts by Snell's law with n1/n2 = 1/eta entering and eta leaving,
+ * d' = (n1/n2) d + ((n1/n2) cos_i - cos_t) N_i with N_i the normal against
+ * d, cos_i = -d.N_i and cos_t = sqrt(1 - (n1/n2)^2 (1 - cos_i^2)); when the
+ * root's argument is negative the ray is totally reflected. Returns the new
+ * inside flag; *cos_i and *root report the decision's margins. */
+static int surface_turn(const orc_surface *sf, const double p[3], const double d[3], int inside, double dn[3],
+                        double *cos_i, double *root)
+{
+    double N[3];
+    for (int a = 0; a < 3; ++a) N[a] = p[a] - sf->centre[a];
+    const double len = sqrt(dot3(N, N));
+    for (int a = 0; a < 3; ++a) N[a] /= len;
+    const double dN = dot3(d, N);
+    *cos_i = fabs(dN);
+    *root = INFINITY;
+    int reflect = sf->kind == ORC_SURF_MIRROR;
+    if (!reflect) {
+        const double sgn = dN < 0.0 ? 1.0 : -1.0;          /* N_i = sgn N points against d */
+        const double eta = dN < 0.0 ? 1.0 / sf->ior : sf->ior; /* n1/n2 */
+        const double ci = -sgn * dN;
+        const double k = 1.0 - eta * eta * (1.0 - ci * ci);
+        *root = fabs(k);
+        if (k < 0.0) {
+            reflect = 1;
+        } else {
+            for (int a = 0; a < 3; ++a) dn[a] = eta * d[a] + (eta * ci - sqrt(k)) * sgn * N[a];
+            inside = !inside;
+        }
+    }
+    if (reflect)
+        for (int a = 0; a < 3; ++a) dn[a] = d[a] - 2.0 * dN * N[a];
+    const double l = sqrt(dot3(dn, dn));
+    for (int a = 0; a < 3; ++a) dn[a] /= l;
+    return inside;
+}
+
 /* Walks one ray. Returns the status code written to steps[]. */
 static int32_t walk_ray(const orc_scene *s, const double o[3], const double d[3], double tmax, int32_t start,
                         double eps, int32_t max_steps, double rgb[3], double *t_final,
@@ -296,22 +396,39 @@ static int32_t walk_ray(const orc_scene *s, const double o[3], const double d[3]
 {
     const int B = sh_count(s->sh_deg);
     double Y[16];
-    sh_basis(s->sh_deg, d, Y);
     rgb[0] = rgb[1] = rgb[2] = 0.0;
     *t_final = 1.0;
     if (mg) {
         mg->margin = INFINITY;
         mg->graze = INFINITY;
         mg->term = INFINITY;
+        mg->surf = INFINITY;
     }
     if (start < 0 || start >= s->n_sites) return ORC_BAD_START;
 
+    /* the current leg */
+    const orc_surface *sf = (s->surf && s->surf->kind != ORC_SURF_NONE) ? s->surf : NULL;
+    double lo[3] = {o[0], o[1], o[2]}, ld[3] = {d[0], d[1], d[2]};
+    sh_basis(s->sh_deg, ld, Y);
+    int inside = 0, bounces = 0;
+    double ts = INFINITY;
+    if (sf) {
+        double oc[3];
+        for (int a = 0; a < 3; ++a) oc[a] = o[a] - sf->centre[a];
+        inside = dot3(oc, oc) < sf->radius * sf->radius;
+        if (sf->max_bounces > 0) ts = surface_hit(sf, lo, ld, inside);
+    }
+
     double t0 = 0.0, T = 1.0;
     int32_t i = start, prev = -1, n = 0, status = 0;
-    const double scale0 = 1.0 + sqrt(dot3(o, o));
+    double scale0 = 1.0 + sqrt(dot3(o, o));
+    int cont = 0; /* the visit continues a cell after a crossing: no new transmittance test */
     for (;;) {
-        if (mg && eps > 0.0) mg->term = fmin(mg->term, fabs(log(T) - log(eps)));
-        if (!(T > eps)) break;
+        if (!cont) {
+            if (mg && eps > 0.0) mg->term = fmin(mg->term, fabs(log(T) - log(eps)));
+            if (!(T > eps)) break;
+        }
+        cont = 0;
         if (n == max_steps) {
             status = ORC_MAX_STEPS;
             break;
@@ -330,9 +447,9 @@ static int32_t walk_ray(const orc_scene *s, const double o[3], const double d[3]
             double nv[3], mo[3];
             for (int a = 0; a < 3; ++a) {
                 nv[a] = xj[a] - x[a];
-                mo[a] = 0.5 * (x[a] + xj[a]) - o[a];
+                mo[a] = 0.5 * (x[a] + xj[a]) - lo[a];
             }
-            const double den = dot3(nv, d);
+            const double den = dot3(nv, ld);
             const double nlen = sqrt(dot3(nv, nv));
             if (!(den > 0.0)) {
                 if (mg) mg->graze = fmin(mg->graze, fabs(den) / nlen);
@@ -353,7 +470,14 @@ static int32_t walk_ray(const orc_scene *s, const double o[3], const double d[3]
             }
         }
 
-        const double te = fmax(t0, fmin(t1, tmax));
+        double te = fmax(t0, fmin(t1, tmax));
+        /* the leg crosses the surface inside this cell */
+        const int bounce = ts < te;
+        if (mg && sf && isfinite(ts)) {
+            const double scale = scale0 + ts;
+            mg->surf = fmin(mg->surf, fabs(ts - fmin(t1, tmax)) / scale);
+        }
+        if (bounce) te = ts;
         const double delta = te - t0;
         const double sigma = s->density[i];
         const double tau = (sigma == 0.0) ? 0.0 : sigma * delta;
@@ -363,8 +487,8 @@ static int32_t walk_ray(const orc_scene *s, const double o[3], const double d[3]
             for (int ch = 0; ch < 3; ++ch) c[ch] += s->sh[(3 * (int64_t)B) * i + 3 * b + ch] * Y[b];
         for (int ch = 0; ch < 3; ++ch) rgb[ch] += T * alpha * c[ch];
 
-        const int clipped = (inext < 0) || (t1 >= tmax);
-        if (mg && inext >= 0) {
+        const int clipped = !bounce && ((inext < 0) || (t1 >= tmax));
+        if (mg && inext >= 0 && !bounce) {
             const double scale = scale0 + fabs(t1);
             const double cos1 = den1 / nlen1;
             for (int q = 0; q < ncand; ++q) {
@@ -387,12 +511,38 @@ static int32_t walk_ray(const orc_scene *s, const double o[3], const double d[3]
             v.c[0] = c[0];
             v.c[1] = c[1];
             v.c[2] = c[2];
-            v.moves = (!clipped) && (t1 >= t0);
+            v.moves = (!clipped) && (!bounce) && (t1 >= t0);
+            v.bounce = bounce;
+            for (int a = 0; a < 3; ++a) {
+                v.o[a] = lo[a];
+                v.d[a] = ld[a];
+            }
             push_visit(rec, &v);
         }
         T *= exp(-tau);
         ++n;
         if (clipped) break;
+        if (bounce) {
+            /* a new leg from the crossing, in the same cell; every face of
+               the cell is a candidate again */
+            double p[3], dn[3], ci, root;
+            for (int a = 0; a < 3; ++a) p[a] = lo[a] + ts * ld[a];
+            inside = surface_turn(sf, p, ld, inside, dn, &ci, &root);
+            if (mg) mg->surf = fmin(mg->surf, fmin(ci, root));
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = p[a];
+                ld[a] = dn[a];
+            }
+            sh_basis(s->sh_deg, ld, Y);
+            tmax = exit_distance(sf->bound_kind, sf->bound, lo, ld);
+            ++bounces;
+            ts = bounces < sf->max_bounces ? surface_hit(sf, lo, ld, inside) : INFINITY;
+            scale0 = 1.0 + sqrt(dot3(lo, lo));
+            prev = -1;
+            t0 = 0.0;
+            cont = 1;
+            continue;
+        }
         prev = i;
         i = inext;
         t0 = te;
@@ -410,15 +560,15 @@ static int32_t walk_ray(const orc_scene *s, const double o[3], const double d[3]
 /*   for an exit that moves with t1:                                        */
 /*     dL/dt_n = sigma_n dL/dtau_n - sigma_{n+1} dL/dtau_{n+1}              */
 /*     dt/dx_{i_n} = (p - x_{i_n})/den, dt/dx_{i_{n+1}} = (x_{i_{n+1}} - p)/den */
-/*     with p = o + t_n d and den = (x_{i_{n+1}} - x_{i_n}).d               */
+/*     with p = o + t_n d and den = (x_{i_{n+1}} - x_{i_n}).d, o and d the   */
+/*     visit's leg (its SH basis Y is the leg's too)                        */
 /* ------------------------------------------------------------------------ */
 
-static void ray_gradient(const orc_scene *s, const double o[3], const double d[3], const visit_t *v, int64_t nv,
-                         double T_final, const double g[3], double gT, double *gsites, double *gdens, double *gsh)
+static void ray_gradient(const orc_scene *s, const visit_t *v, int64_t nv, double T_final, const double g[3],
+                         double gT, double *gsites, double *gdens, double *gsh)
 {
     const int B = sh_count(s->sh_deg);
     double Y[16];
-    sh_basis(s->sh_deg, d, Y);
     double *R = (double *)malloc((size_t)(nv > 0 ? nv : 1) * 3 * sizeof(double));
     double *dtau = (double *)malloc((size_t)(nv > 0 ? nv : 1) * sizeof(double));
     if (!R || !dtau) {
@@ -442,6 +592,7 @@ static void ray_gradient(const orc_scene *s, const double o[3], const double d[3
         const int32_t i = v[n].cell;
         const double w = v[n].T * (-expm1(-v[n].tau));
         gdens[i] += (v[n].te - v[n].t0) * dtau[n];
+        sh_basis(s->sh_deg, v[n].d, Y); /* the basis of the visit's leg */
         for (int b = 0; b < B; ++b)
             for (int ch = 0; ch < 3; ++ch) gsh[(3 * (int64_t)B) * i + 3 * b + ch] += g[ch] * w * Y[b];
     }
@@ -453,7 +604,7 @@ static void ray_gradient(const orc_scene *s, const double o[3], const double d[3
         const double *xi = s->sites + 3 * (int64_t)i;
         const double *xj = s->sites + 3 * (int64_t)j;
         for (int a = 0; a < 3; ++a) {
-            const double p = o[a] + v[n].t1 * d[a];
+            const double p = v[n].o[a] + v[n].t1 * v[n].d[a];
             gsites[3 * (int64_t)i + a] += gt * (p - xi[a]) / v[n].den;
             gsites[3 * (int64_t)j + a] += gt * (xj[a] - p) / v[n].den;
         }
@@ -482,6 +633,9 @@ typedef struct {
     double *t_exit;
     int32_t *len;
     double *margin, *graze, *term;
+    int8_t *bounce;   /* [R][max_len], nullable */
+    double *legs;     /* [R][max_len][6]: each visit's leg origin and direction, nullable */
+    double *surf_margin;
     /* backward */
     const double *grad_rgb, *grad_t;
     double *gsites, *gdens, *gsh;
@@ -494,6 +648,12 @@ typedef struct {
 static int check_inputs(const orc_scene *s, const double *d, int64_t n_rays)
 {
     if (!s || s->n_sites < 1 || s->sh_deg < 0 || s->sh_deg > 3 || n_rays < 0) return ORC_EINVAL;
+    if (s->surf) {
+        const orc_surface *sf = s->surf;
+        if (sf->kind < ORC_SURF_NONE || sf->kind > ORC_SURF_GLASS || sf->max_bounces < 0 || !(sf->radius > 0.0) ||
+            (sf->kind == ORC_SURF_GLASS && !(sf->ior > 0.0)) || sf->bound_kind < 0 || sf->bound_kind > 1)
+            return ORC_EINVAL;
+    }
     if (orc_check_csr(s->off, s->idx, s->n_sites, s->off[s->n_sites]) != ORC_OK) return ORC_EINVAL;
     for (int64_t i = 0; i < s->n_sites; ++i)
         if (s->off[i + 1] - s->off[i] > 512) return ORC_EINVAL; /* decision-margin buffer */
@@ -519,11 +679,18 @@ static void *forward_worker(void *arg)
             for (int64_t n = 0; n < L; ++n) {
                 j->cells[r * j->max_len + n] = buf.v[n].cell;
                 j->t_exit[r * j->max_len + n] = buf.v[n].te;
+                if (j->bounce) j->bounce[r * j->max_len + n] = (int8_t)buf.v[n].bounce;
+                if (j->legs)
+                    for (int a = 0; a < 3; ++a) {
+                        j->legs[(r * j->max_len + n) * 6 + a] = buf.v[n].o[a];
+                        j->legs[(r * j->max_len + n) * 6 + 3 + a] = buf.v[n].d[a];
+                    }
             }
             j->len[r] = (int32_t)buf.len;
             j->margin[r] = mg.margin;
             j->graze[r] = mg.graze;
             j->term[r] = mg.term;
+            if (j->surf_margin) j->surf_margin[r] = mg.surf;
         }
     }
     free(buf.v);
@@ -541,8 +708,7 @@ static void *backward_worker(void *arg)
                                     rgb, &tf, &buf, NULL);
         if (st == ORC_BAD_START) continue;
         const double gT = j->grad_t ? j->grad_t[r] : 0.0;
-        ray_gradient(j->s, j->o + 3 * r, j->d + 3 * r, buf.v, buf.len, tf, j->grad_rgb + 3 * r, gT, j->gsites,
-                     j->gdens, j->gsh);
+        ray_gradient(j->s, buf.v, buf.len, tf, j->grad_rgb + 3 * r, gT, j->gsites, j->gdens, j->gsh);
     }
     free(buf.v);
     return NULL;
@@ -712,10 +878,11 @@ int orc_forward(const orc_scene *s, const double *o, const double *d, const doub
     return run_jobs(&j, n_rays, nthreads, forward_worker, 0);
 }
 
+/* bounce, legs and surf_margin are optional (NULL) outputs. */
 int orc_trace(const orc_scene *s, const double *o, const double *d, const double *tmax, const int32_t *start,
               int64_t n_rays, double eps, int32_t max_steps, int32_t max_len, int nthreads, double *rgb,
               double *t_final, int32_t *steps, int32_t *cells, double *t_exit, int32_t *len, double *margin,
-              double *graze, double *term)
+              double *graze, double *term, int8_t *bounce, double *legs, double *surf_margin)
 {
     if (check_inputs(s, d, n_rays) != ORC_OK || max_steps < 1 || max_len < 1) return ORC_EINVAL;
     job_t j;
@@ -737,6 +904,9 @@ int orc_trace(const orc_scene *s, const double *o, const double *d, const double
     j.margin = margin;
     j.graze = graze;
     j.term = term;
+    j.bounce = bounce;
+    j.legs = legs;
+    j.surf_margin = surf_margin;
     return run_jobs(&j, n_rays, nthreads, forward_worker, 0);
 }
 
@@ -768,6 +938,7 @@ int orc_quantile(const orc_scene *s, const double *o, const double *d, const dou
                  double *tq, double *loss, double *grad_sites, double *grad_density)
 {
     if (check_inputs(s, d, n_rays) != ORC_OK || max_steps < 1 || !u || !tq || !loss) return ORC_EINVAL;
+    if (s->surf && s->surf->kind != ORC_SURF_NONE) return ORC_EINVAL; /* quantiles along one leg only */
     for (int64_t r = 0; r < 2 * n_rays; ++r)
         if (!(u[r] >= 0.0 && u[r] <= 1.0)) return ORC_EINVAL;
     if (grad_loss && (!grad_sites || !grad_density)) return ORC_EINVAL;
