@@ -166,19 +166,28 @@ typedef struct {
 } rf_params;
 
 /* ------------------------------------------------------------------------
- * Camera rays (pinhole), in 8x8 screen-tile order: tiles row-major over the
- * image, pixels row-major inside a tile, partial edge tiles holding only the
- * pixels inside the image. Ray r covers pixel pixel[r] = y*width + x; its
- * direction is R (x + 0.5 - width/2, y + 0.5 - height/2, f) normalised, with
- * f = (width/2)/tan(fov/2) and R the rotation in pose (columns right, down,
- * forward). t_max is the distance at which the ray leaves the bound (the
- * origin must be inside it). start_cell is filled with `start` (the caller's
- * nn(origin) for the camera position).
+ * Camera rays, in 8x8 screen-tile order: tiles row-major over the image,
+ * pixels row-major inside a tile, partial edge tiles holding only the pixels
+ * inside the image. Ray r covers pixel pixel[r] = y*width + x. With
+ * (u, v) = (x + 0.5 - width/2, y + 0.5 - height/2) and R the rotation in pose
+ * (columns right, down, forward), its direction is
+ *   RF_CAMERA_PINHOLE: R (u, v, f) normalised, f = (width/2)/tan(fov/2);
+ *   RF_CAMERA_FISHEYE (equidistant; the non-linear camera of the ray-based
+ *     effects, Fig. 3): R (sin(a) u/rho, sin(a) v/rho, cos(a)) with
+ *     rho = |(u, v)| and a = rho (fov/2)/(width/2), so the angle from the
+ *     axis grows linearly with rho and the left and right edges are at fov/2.
+ * t_max is the distance at which the ray leaves the bound (the origin must
+ * be inside it). start_cell is filled with `start` (the caller's nn(origin)
+ * for the camera position).
  * ---------------------------------------------------------------------- */
+#define RF_CAMERA_PINHOLE 0
+#define RF_CAMERA_FISHEYE 1
+
 typedef struct {
     float pose[12];   /* row-major 3x4 [R | position] */
-    float fov_deg;    /* horizontal field of view, (0, 180) */
+    float fov_deg;    /* horizontal field of view: pinhole (0, 180), fisheye (0, 360] */
     int32_t width, height;
+    int32_t model;    /* RF_CAMERA_* (0, the pinhole, when zero-initialised) */
 } rf_camera;
 
 typedef struct {
@@ -242,15 +251,19 @@ rf_status rf_locate(const rf_packed_scene *scene, const float *points, int64_t n
  * that the backward (Sec. 3.1 gradients, in the forward order of Algorithm 1)
  * does not repeat the face scans. Step-major: visit n (0-based) of ray r is
  * entry n * n_rays + r, for n < capacity.
- *   code    uint32[capacity][n_rays]  visited cell | exit-moves << 31 |
- *                                     walk-ended-here << 30 (the exit moves
- *                                     with its face when t0 <= t1 < t_max)
+ *   code    uint32[capacity][n_rays]  visited cell (bits 0..28) |
+ *                                     exit-moves << 31 | walk-ended-here << 30
+ *                                     | surface-crossing << 29 (the exit moves
+ *                                     with its face when t0 <= t1 < t_max and
+ *                                     no surface crossing ends the segment)
  *   t_exit  double[capacity][n_rays]  the visit's clamped exit distance te
+ *                                     (along the visit's leg)
  *   tail    int32[n_rays][4]          the packed row reference (2 words) of
  *                                     the cell after the logged visits, the
- *                                     number of visited cells, 0
+ *                                     number of visited cells, the number of
+ *                                     surface crossings (0 without a surface)
  * A ray with more than `capacity` visits logs the first `capacity`; the
- * backward recomputes the rest of its walk from the tail. Memory:
+ * backward walks that ray again from its start cell. Memory:
  * n_rays * (12 * capacity + 16) bytes, device, owned by the caller; t_exit
  * 8-byte, code 4-byte and tail 16-byte aligned. A log is valid only with the
  * scene, rays and params of the forward that wrote it, until the scene is
@@ -313,6 +326,59 @@ rf_status rf_render_backward_quantile(const rf_packed_scene *scene, const rf_ray
                                       const float *grad_t_final, const rf_walk_log *log, const rf_quantiles *q,
                                       const float *grad_loss, float *grad_sites, float *grad_density,
                                       float *grad_sh, int32_t mode, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Secondary rays (the reflections and refractions of the ray-based effects,
+ * Fig. 3): one analytic sphere in the scene, a mirror or a glass interface
+ * (refractive index `ior` inside, 1 outside). The foam fills space on both
+ * sides. Where a ray's current leg crosses the sphere inside cell i, the
+ * segment ends at the crossing (an exit that does not move with the sites),
+ * and the walk continues in cell i along the reflected direction
+ * d - 2 (d.N) N, or the refracted one by Snell's law (total internal
+ * reflection reflects); the new leg measures t from the crossing and ends
+ * where it leaves `bound` (the first leg keeps the ray's own t_max). The
+ * crossing splits the cell's visit, and the T > eps test is not repeated for
+ * its second part. Crossings after the first max_bounces are ignored, so
+ * max_bounces = 0 renders as rf_render_forward, bit for bit. Leg geometry
+ * (crossing, normal, new direction, new t_max) is computed in double; the
+ * new leg's origin and direction are then rounded to float.
+ *
+ * rf_render_forward_surface: the forward outputs; with a `log` (nullable)
+ * it also writes the walk log, whose code words flag each crossing (bit 29;
+ * the cell id takes bits 0..28) and whose tail's fourth value counts the
+ * crossings. rf_render_backward_surface: the gradients of
+ * sum grad_rgb.rgb + sum grad_t_final T (accumulated, caller-zeroed, as
+ * rf_render_backward; the sphere itself is fixed), reading `log` if given
+ * (written by rf_render_forward_surface with the same arguments) and
+ * recomputing the walks otherwise or where they outgrew it; the wavefront
+ * reduction is always used. The quantile regulariser gives rays with
+ * crossings no loss and no gradient (its quantiles are defined along one
+ * leg). Errors: RF_ERR_INVALID_ARG for a NULL or invalid surface (kind not
+ * mirror or glass, radius <= 0, glass ior <= 0, max_bounces outside
+ * [0, RF_MAX_BOUNCES], bound kind not 0 or 1) and as rf_render_forward /
+ * rf_render_backward otherwise.
+ * ---------------------------------------------------------------------- */
+#define RF_SURFACE_MIRROR 1
+#define RF_SURFACE_GLASS 2
+#define RF_MAX_BOUNCES 1024
+
+typedef struct {
+    int32_t kind;         /* RF_SURFACE_* */
+    int32_t max_bounces;  /* crossings handled per ray */
+    float centre[3];
+    float radius;         /* > 0 */
+    float ior;            /* glass: refractive index inside the sphere, > 0 */
+    rf_bound bound;       /* where the legs after a crossing end */
+} rf_surface;
+
+rf_status rf_render_forward_surface(const rf_packed_scene *scene, const rf_rays *rays, const rf_params *params,
+                                    const rf_surface *surface, float *rgb, float *t_final, int32_t *steps,
+                                    const rf_walk_log *log /* nullable */, void *stream);
+rf_status rf_render_backward_surface(const rf_packed_scene *scene, const rf_rays *rays, const rf_params *params,
+                                     const rf_surface *surface, const float *rgb, const float *t_final,
+                                     const float *grad_rgb, const float *grad_t_final /* nullable */,
+                                     const rf_walk_log *log /* nullable */, float *grad_sites,
+                                     float *grad_density, float *grad_sh, void *stream);
 
 /* ------------------------------------------------------------------------
  * Traced forward walk, for tests: the forward outputs plus, per ray, the

@@ -18,6 +18,7 @@ from .ops import (  # noqa: E402,F401
     PackedScene,
     Quantiles,
     RadFoamRender,
+    Surface,
     WalkLog,
     locate,
     quantile_forward,

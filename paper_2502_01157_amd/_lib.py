@@ -57,11 +57,16 @@ class Params(ctypes.Structure):
 
 class CameraDesc(ctypes.Structure):
     _fields_ = [("pose", ctypes.c_float * 12), ("fov_deg", ctypes.c_float), ("width", ctypes.c_int32),
-                ("height", ctypes.c_int32)]
+                ("height", ctypes.c_int32), ("model", ctypes.c_int32)]
 
 
 class BoundDesc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("p", ctypes.c_float * 6)]
+
+
+class SurfaceDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("max_bounces", ctypes.c_int32), ("centre", ctypes.c_float * 3),
+                ("radius", ctypes.c_float), ("ior", ctypes.c_float), ("bound", BoundDesc)]
 
 
 class WalkLog(ctypes.Structure):
@@ -124,12 +129,19 @@ def lib() -> ctypes.CDLL:
                                                   ctypes.POINTER(Params), P, P, P, P, ctypes.POINTER(WalkLog),
                                                   ctypes.POINTER(Quantiles), P, P, P, P, ctypes.c_int32, P]
         L.rf_locate.argtypes = [ctypes.POINTER(PackedSceneDesc), P, ctypes.c_int64, P, ctypes.c_int32, P, P]
+        L.rf_render_forward_surface.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Rays),
+                                                ctypes.POINTER(Params), ctypes.POINTER(SurfaceDesc), P, P, P,
+                                                ctypes.POINTER(WalkLog), P]
+        L.rf_render_backward_surface.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Rays),
+                                                 ctypes.POINTER(Params), ctypes.POINTER(SurfaceDesc), P, P, P, P,
+                                                 ctypes.POINTER(WalkLog), P, P, P, P]
         L.rf_packed_planes.argtypes = [ctypes.POINTER(PackedSceneDesc), P, P]
         L.rf_packed_attributes.argtypes = [ctypes.POINTER(PackedSceneDesc), P, P, P]
         for name in ("rf_packed_bytes", "rf_pack_scene", "rf_packed_errors", "rf_raygen", "rf_render_forward",
                      "rf_render_trace", "rf_render_backward", "rf_render_forward_logged",
                      "rf_render_backward_logged", "rf_quantile_forward", "rf_render_backward_quantile",
-                     "rf_locate", "rf_packed_planes", "rf_packed_attributes"):
+                     "rf_locate", "rf_render_forward_surface", "rf_render_backward_surface",
+                     "rf_packed_planes", "rf_packed_attributes"):
             getattr(L, name).restype = st
         L.rf_server_create.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Params),
                                        ctypes.POINTER(BoundDesc), ctypes.c_size_t, ctypes.c_int32,

@@ -218,7 +218,9 @@ rf_status rf_raygen(const rf_camera* cam, const rf_bound* bound, int32_t start, 
     if (!cam || !bound) return fail(RF_ERR_INVALID_ARG, "camera or bound is NULL");
     if (cam->width <= 0 || cam->height <= 0 || (int64_t)cam->width * cam->height > ((int64_t)1 << 31))
         return fail(RF_ERR_INVALID_ARG, "image size %d x %d out of range", cam->width, cam->height);
-    if (!(cam->fov_deg > 0.0f && cam->fov_deg < 180.0f)) return fail(RF_ERR_INVALID_ARG, "fov must be in (0, 180)");
+    if (cam->model != 0 && cam->model != 1) return fail(RF_ERR_INVALID_ARG, "camera model must be 0 or 1");
+    if (!rf::camera_fov_ok(cam->model, cam->fov_deg))
+        return fail(RF_ERR_INVALID_ARG, "fov must be in (0, 180) for a pinhole, (0, 360] for a fisheye");
     if (bound->kind != 0 && bound->kind != 1) return fail(RF_ERR_INVALID_ARG, "bound kind must be 0 or 1");
     if (!origin || !dir || !t_max || !start_cell) return fail(RF_ERR_INVALID_ARG, "an output array is NULL");
     rf::RaygenArgs a;
@@ -226,7 +228,8 @@ rf_status rf_raygen(const rf_camera* cam, const rf_bound* bound, int32_t start, 
         for (int c = 0; c < 3; ++c) a.rot[3 * r + c] = cam->pose[4 * r + c];
         a.pos[r] = cam->pose[4 * r + 3];
     }
-    a.focal = (float)(0.5 * cam->width / tan(0.5 * (double)cam->fov_deg * M_PI / 180.0));
+    a.model = cam->model;
+    a.focal = rf::camera_focal(cam->model, cam->fov_deg, cam->width);
     a.width = cam->width;
     a.height = cam->height;
     a.bound_kind = bound->kind;
@@ -430,6 +433,82 @@ rf_status rf_render_backward_quantile(const rf_packed_scene* scene, const rf_ray
     return hip_status(rf::launch_walk(mode == 0 ? rf::kBackwardLogReduce : rf::kBackwardLogAtomic, scene->sh_degree,
                                       scene->attr_dtype == RF_BF16, a, static_cast<hipStream_t>(stream)),
                       "backward walk with the quantile term");
+}
+
+static rf_status check_surface(const rf_surface* sf)
+{
+    if (!sf) return fail(RF_ERR_INVALID_ARG, "surface is NULL");
+    if (sf->kind != RF_SURFACE_MIRROR && sf->kind != RF_SURFACE_GLASS)
+        return fail(RF_ERR_INVALID_ARG, "surface kind must be RF_SURFACE_MIRROR or RF_SURFACE_GLASS");
+    if (sf->max_bounces < 0 || sf->max_bounces > RF_MAX_BOUNCES)
+        return fail(RF_ERR_INVALID_ARG, "max_bounces must be in [0, %d]", RF_MAX_BOUNCES);
+    if (!(sf->radius > 0.0f) || !isfinite(sf->radius) || !isfinite(sf->centre[0]) ||
+        !isfinite(sf->centre[1]) || !isfinite(sf->centre[2]))
+        return fail(RF_ERR_INVALID_ARG, "the sphere needs a finite centre and a radius > 0");
+    if (sf->kind == RF_SURFACE_GLASS && !(sf->ior > 0.0f && isfinite(sf->ior)))
+        return fail(RF_ERR_INVALID_ARG, "glass needs a refractive index > 0");
+    if (sf->bound.kind != 0 && sf->bound.kind != 1) return fail(RF_ERR_INVALID_ARG, "bound kind must be 0 or 1");
+    return RF_OK;
+}
+
+static void set_surface(rf::WalkArgs& a, const rf_surface* sf)
+{
+    a.surf.kind = sf->kind;
+    a.surf.max_bounces = sf->max_bounces;
+    for (int k = 0; k < 3; ++k) a.surf.centre[k] = sf->centre[k];
+    a.surf.radius = sf->radius;
+    a.surf.ior = sf->ior;
+    a.surf.bound_kind = sf->bound.kind;
+    for (int k = 0; k < 6; ++k) a.surf.bound[k] = sf->bound.p[k];
+}
+
+rf_status rf_render_forward_surface(const rf_packed_scene* scene, const rf_rays* rays, const rf_params* params,
+                                    const rf_surface* surface, float* rgb, float* t_final, int32_t* steps,
+                                    const rf_walk_log* log, void* stream)
+{
+    rf_status st;
+    if ((st = check_packed(scene)) != RF_OK || (st = check_rays(rays)) != RF_OK || (st = check_params(params)) != RF_OK)
+        return st;
+    if ((st = check_surface(surface)) != RF_OK) return st;
+    if (rays->n_rays > 0 && (!rgb || !t_final || !steps)) return fail(RF_ERR_INVALID_ARG, "an output array is NULL");
+    if (log && (st = check_log(log, rays->n_rays)) != RF_OK) return st;
+    rf::WalkArgs a = walk_args(scene, rays, params);
+    a.rgb = rgb;
+    a.t_final = t_final;
+    a.steps = steps;
+    set_surface(a, surface);
+    if (log) set_log(a, log);
+    return hip_status(rf::launch_walk(log ? rf::kForwardLogSurf : rf::kForwardSurf, scene->sh_degree,
+                                      scene->attr_dtype == RF_BF16, a, static_cast<hipStream_t>(stream)),
+                      "forward walk with a surface");
+}
+
+rf_status rf_render_backward_surface(const rf_packed_scene* scene, const rf_rays* rays, const rf_params* params,
+                                     const rf_surface* surface, const float* rgb, const float* t_final,
+                                     const float* grad_rgb, const float* grad_t_final, const rf_walk_log* log,
+                                     float* grad_sites, float* grad_density, float* grad_sh, void* stream)
+{
+    rf_status st;
+    if ((st = check_packed(scene)) != RF_OK || (st = check_rays(rays)) != RF_OK || (st = check_params(params)) != RF_OK)
+        return st;
+    if ((st = check_surface(surface)) != RF_OK) return st;
+    if (rays->n_rays > 0 && (!rgb || !t_final || !grad_rgb))
+        return fail(RF_ERR_INVALID_ARG, "rgb, t_final and grad_rgb are required");
+    if (!grad_sites || !grad_density || !grad_sh) return fail(RF_ERR_INVALID_ARG, "a gradient array is NULL");
+    if (log && (st = check_log(log, rays->n_rays)) != RF_OK) return st;
+    rf::WalkArgs a = walk_args(scene, rays, params);
+    a.rgb_in = rgb;
+    a.t_final_in = t_final;
+    a.grad_rgb = grad_rgb;
+    a.grad_t = grad_t_final;
+    a.g_sites = grad_sites;
+    a.g_density = grad_density;
+    a.g_sh = grad_sh;
+    set_surface(a, surface);
+    if (log) set_log(a, log);
+    return hip_status(rf::launch_walk(log ? rf::kBackwardLogSurf : rf::kBackwardSurf, scene->sh_degree,
+                                      scene->attr_dtype == RF_BF16, a, static_cast<hipStream_t>(stream)),
+                      "backward walk with a surface");
 }
 
 rf_status rf_locate(const rf_packed_scene* scene, const float* points, int64_t n_points, const int32_t* seed,

@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) void k_raygen(RaygenArgs g)
     int px, py;
     tile_pixel(r, g.width, g.height, &px, &py);
     float d[3], t;
-    camera_ray(g.rot, g.pos, g.focal, g.width, g.height, px, py, g.bound_kind, g.bound, d, &t);
+    camera_ray(g.rot, g.pos, g.model, g.focal, g.width, g.height, px, py, g.bound_kind, g.bound, d, &t);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         g.origin[3 * r + k] = g.pos[k];

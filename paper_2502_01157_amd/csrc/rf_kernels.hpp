@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 namespace rf {
@@ -13,6 +14,20 @@ struct SceneView {
     const unsigned char* rec;
     int64_t n_sites;
     int64_t n_edges;
+};
+
+// An analytic sphere that bends rays (secondary rays): kind 1 mirror,
+// 2 glass of refractive index `ior` inside (1 outside); legs after a
+// crossing end at the bound (kind 0 box lo = b[0..2], hi = b[3..5]; kind 1
+// sphere of radius b[0] about the world origin).
+struct SurfaceArgs {
+    int32_t kind;
+    int32_t max_bounces;
+    float centre[3];
+    float radius;
+    float ior;
+    int32_t bound_kind;
+    float bound[6];
 };
 
 struct WalkArgs {
@@ -41,9 +56,9 @@ struct WalkArgs {
     float* g_density;
     float* g_sh;
     // walk log: written by a logged forward, read by a logged backward
-    uint32_t* log_code;  // [log_cap][n_rays] cell | moves << 31 | clipped << 30
-    double* log_te;      // [log_cap][n_rays] clamped exit distance of the visit
-    int4* log_tail;      // [n_rays] (row of the cell after the logged visits, visited cells, 0)
+    uint32_t* log_code;  // [log_cap][n_rays] cell | moves << 31 | clipped << 30 | crossing << 29
+    double* log_te;      // [log_cap][n_rays] clamped exit distance of the visit (along its leg)
+    int4* log_tail;      // [n_rays] (row of the cell after the logged visits, visited cells, crossings)
     int32_t log_cap;
     // quantile regulariser: two draws per ray in, quantiles and their visit out
     const float* q_u;    // [n_rays][2]
@@ -52,6 +67,8 @@ struct WalkArgs {
     float* q_sig;        // [n_rays][2] that visit's density
     float* q_loss;       // [n_rays]
     const float* grad_q; // [n_rays] upstream gradient of the loss (backward)
+    // secondary rays (the kinds with a surface)
+    SurfaceArgs surf;
 };
 
 struct PackArgs {
@@ -72,7 +89,8 @@ struct PackArgs {
 struct RaygenArgs {
     float rot[9];
     float pos[3];
-    float focal;
+    int32_t model;  // 0 pinhole, 1 equidistant fisheye
+    float focal;    // pinhole: focal length in pixels; fisheye: radians per pixel
     int32_t width, height;
     int32_t bound_kind;
     float bound[6];
@@ -107,8 +125,27 @@ enum WalkKind {
     kForwardLog = 4,
     kBackwardLogReduce = 5,
     kBackwardLogAtomic = 6,
-    kQuantile = 7
+    kQuantile = 7,
+    // with a surface (secondary rays); the backward always reduces per wavefront
+    kForwardSurf = 8,
+    kForwardLogSurf = 9,
+    kBackwardSurf = 10,
+    kBackwardLogSurf = 11
 };
+
+// Camera models (host side): the field of view each accepts, and the focal
+// value the camera ray takes (pinhole: focal length in pixels; fisheye:
+// radians per pixel, so that the left and right edges are at fov/2).
+inline bool camera_fov_ok(int model, float fov_deg)
+{
+    return model == 0 ? (fov_deg > 0.0f && fov_deg < 180.0f) : (model == 1 && fov_deg > 0.0f && fov_deg <= 360.0f);
+}
+
+inline float camera_focal(int model, float fov_deg, int width)
+{
+    const double half = 0.5 * (double)fov_deg * 3.14159265358979323846 / 180.0;
+    return model == 1 ? (float)(half / (0.5 * width)) : (float)(0.5 * width / tan(half));
+}
 
 // Records an error message for rf_last_error() on this host thread.
 void set_error(const char* msg);

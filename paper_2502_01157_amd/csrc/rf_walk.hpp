@@ -243,7 +243,118 @@ struct LogView {
 
 constexpr uint32_t kLogMoves = 1u << 31;    // the exit moves with its face (t0 <= t1 < t_max)
 constexpr uint32_t kLogClipped = 1u << 30;  // no front face or t1 >= t_max: the walk ended here
-constexpr uint32_t kLogCell = kLogClipped - 1u;
+constexpr uint32_t kLogCross = 1u << 29;    // the segment ended at the surface: a new leg follows
+constexpr uint32_t kLogCell = kLogCross - 1u;
+
+// ---------------------------------------------------------------------------
+// Secondary rays: an analytic sphere (mirror or glass) that bends the walk.
+// Where the current leg (o, d) crosses the sphere inside a cell, the segment
+// ends at the crossing, and the walk continues in the same cell along the
+// reflected or refracted direction, measuring t from the crossing again, up
+// to the scene bound. The leg arithmetic is in double and shared by the
+// forward and the backward, so both build the same legs bit for bit.
+// ---------------------------------------------------------------------------
+struct Leg {
+    double ts;    // distance along the leg to its next crossing, +inf if none
+    int inside;   // the leg starts inside the sphere
+    int bounces;  // crossings so far
+};
+
+// Next crossing of the leg: the far root of |o + t d - c| = r from inside,
+// the near positive root from outside (a leg leaving the surface outwards
+// has none).
+__device__ inline double surface_hit(const SurfaceArgs& sf, float ox, float oy, float oz, float dx, float dy,
+                                     float dz, int inside, int bounces)
+{
+    if (bounces >= sf.max_bounces) return INFINITY;
+    const double cx = (double)ox - sf.centre[0], cy = (double)oy - sf.centre[1], cz = (double)oz - sf.centre[2];
+    const double b = fma(cz, (double)dz, fma(cy, (double)dy, cx * (double)dx));
+    const double r = sf.radius;
+    const double c = fma(cz, cz, fma(cy, cy, cx * cx)) - r * r;
+    const double disc = b * b - c;
+    if (!(disc > 0.0)) return INFINITY;
+    const double t = inside ? sqrt(disc) - b : -b - sqrt(disc);
+    return t > 0.0 ? t : INFINITY;
+}
+
+__device__ inline void leg_start(const SurfaceArgs& sf, float ox, float oy, float oz, float dx, float dy, float dz,
+                                 Leg& L)
+{
+    const double cx = (double)ox - sf.centre[0], cy = (double)oy - sf.centre[1], cz = (double)oz - sf.centre[2];
+    const double r = sf.radius;
+    L.inside = fma(cz, cz, fma(cy, cy, cx * cx)) < r * r;
+    L.bounces = 0;
+    L.ts = surface_hit(sf, ox, oy, oz, dx, dy, dz, L.inside, 0);
+}
+
+// Distance from o along d to the bound (box or sphere about the origin).
+__device__ inline double bound_exit(int kind, const float* b, const double o[3], const double d[3])
+{
+    if (kind == 0) {
+        double t = INFINITY;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (d[k] > 0.0) t = fmin(t, ((double)b[3 + k] - o[k]) / d[k]);
+            else if (d[k] < 0.0) t = fmin(t, ((double)b[k] - o[k]) / d[k]);
+        }
+        return fmax(t, 0.0);
+    }
+    const double bb = fma(o[2], d[2], fma(o[1], d[1], o[0] * d[0]));
+    const double c = fma(o[2], o[2], fma(o[1], o[1], o[0] * o[0])) - (double)b[0] * (double)b[0];
+    const double disc = bb * bb - c;
+    return disc > 0.0 ? fmax(sqrt(disc) - bb, 0.0) : 0.0;
+}
+
+// The leg after the crossing at t = L.ts: mirror d' = d - 2 (d.N) N; glass by
+// Snell's law with n1/n2 = 1/ior entering and ior leaving (total internal
+// reflection when the refracted cosine is imaginary). Updates the leg's
+// origin, direction, t_max and crossing state.
+__device__ inline void surface_turn(const SurfaceArgs& sf, Leg& L, float& ox, float& oy, float& oz, float& dx,
+                                    float& dy, float& dz, float& tmax)
+{
+    const double d[3] = {dx, dy, dz};
+    double p[3], N[3];
+    p[0] = fma(L.ts, d[0], (double)ox);
+    p[1] = fma(L.ts, d[1], (double)oy);
+    p[2] = fma(L.ts, d[2], (double)oz);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) N[k] = p[k] - (double)sf.centre[k];
+    const double inv = 1.0 / sqrt(fma(N[2], N[2], fma(N[1], N[1], N[0] * N[0])));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) N[k] *= inv;
+    const double dN = fma(d[2], N[2], fma(d[1], N[1], d[0] * N[0]));
+    double dn[3];
+    bool reflect = sf.kind == 1;
+    if (!reflect) {
+        const double sgn = dN < 0.0 ? 1.0 : -1.0;  // sgn N points against d
+        const double eta = dN < 0.0 ? 1.0 / (double)sf.ior : (double)sf.ior;
+        const double ci = -sgn * dN;
+        const double k = 1.0 - eta * eta * (1.0 - ci * ci);
+        if (k < 0.0) {
+            reflect = true;
+        } else {
+            const double m = (eta * ci - sqrt(k)) * sgn;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) dn[q] = fma(eta, d[q], m * N[q]);
+            L.inside = !L.inside;
+        }
+    }
+    if (reflect) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) dn[q] = fma(-2.0 * dN, N[q], d[q]);
+    }
+    const double il = 1.0 / sqrt(fma(dn[2], dn[2], fma(dn[1], dn[1], dn[0] * dn[0])));
+    ox = (float)p[0];
+    oy = (float)p[1];
+    oz = (float)p[2];
+    dx = (float)(dn[0] * il);
+    dy = (float)(dn[1] * il);
+    dz = (float)(dn[2] * il);
+    const double o2[3] = {ox, oy, oz}, d2[3] = {dx, dy, dz};
+    tmax = (float)bound_exit(sf.bound_kind, sf.bound, o2, d2);
+    ++L.bounces;
+    L.ts = surface_hit(sf, ox, oy, oz, dx, dy, dz, L.inside, L.bounces);
+}
 
 // Algorithm 1 for one ray: start in `start`, take the nearest front face of
 // each cell, composite the segment with eq. (3)-(4) while T > eps.
@@ -318,11 +429,14 @@ __device__ inline void walk_forward(const SceneView& s, float ox, float oy, floa
 // wavefront is done, so that all 64 lanes take part in each staging round;
 // `live` is false for lanes without a ray. Same arithmetic as walk_forward,
 // so the same outputs bit for bit.
-template <int DEG, bool BF16, bool TRACE, bool LOG>
+// With SURF the walk bends at the surface `sf` (see surface_turn); the
+// transmittance test is not repeated for the part of a cell after a crossing.
+template <int DEG, bool BF16, bool TRACE, bool LOG, bool SURF = false>
 __device__ inline void walk_forward_staged(const SceneView& s, bool live, float ox, float oy, float oz, float dx,
                                            float dy, float dz, float tmax, int start, float eps, int max_steps,
                                            int32_t* cells, float* t_exit, int max_len, RayResult& res,
-                                           const LogView* lg, int64_t r, lds_u8* region)
+                                           const LogView* lg, int64_t r, lds_u8* region,
+                                           const SurfaceArgs* sf = nullptr)
 {
     res.C[0] = res.C[1] = res.C[2] = 0.0f;
     res.T = 1.0f;
@@ -340,9 +454,14 @@ __device__ inline void walk_forward_staged(const SceneView& s, bool live, float 
     double t0 = 0.0;
     float T = 1.0f;
     int n = 0;
+    Leg leg = {INFINITY, 0, 0};
+    bool cont = false;  // the visit continues a cell after a crossing
+    if constexpr (SURF) {
+        if (live) leg_start(*sf, ox, oy, oz, dx, dy, dz, leg);
+    }
     while (__ballot(live)) {
         if (live) {
-            if (!(T > eps)) {
+            if (!cont && !(T > eps)) {
                 res.status = n;
                 live = false;
             } else if (n == max_steps) {
@@ -359,6 +478,17 @@ __device__ inline void walk_forward_staged(const SceneView& s, bool live, float 
             Visit<DEG> v;
             visit_cell_staged<DEG, BF16>(s, ref, face_slot, rec_slot, region, t0, tmax, ox, oy, oz, dx, dy, dz, Y,
                                          v);
+            bool cross = false;
+            if constexpr (SURF) {
+                if (leg.ts < v.te) {
+                    // the leg crosses the surface inside this cell
+                    cross = true;
+                    v.te = leg.ts;
+                    v.clipped = false;
+                    segment<DEG>(t0, Y, v);
+                }
+            }
+            cont = false;
             const float w = T * v.alpha;
             res.C[0] = fmaf(w, v.c[0], res.C[0]);
             res.C[1] = fmaf(w, v.c[1], res.C[1]);
@@ -372,9 +502,9 @@ __device__ inline void walk_forward_staged(const SceneView& s, bool live, float 
             }
             if constexpr (LOG) {
                 if (n < lg->cap) {
-                    const bool moves = !v.clipped && (v.t1 >= t0);
-                    lg->code[n * lg->stride + r] =
-                        (uint32_t)ref_cell(ref) | (moves ? kLogMoves : 0u) | (v.clipped ? kLogClipped : 0u);
+                    const bool moves = !v.clipped && !cross && (v.t1 >= t0);
+                    lg->code[n * lg->stride + r] = (uint32_t)ref_cell(ref) | (moves ? kLogMoves : 0u) |
+                                                   (v.clipped ? kLogClipped : 0u) | (cross ? kLogCross : 0u);
                     lg->te[n * lg->stride + r] = v.te;
                 }
             }
@@ -382,6 +512,14 @@ __device__ inline void walk_forward_staged(const SceneView& s, bool live, float 
             if (v.clipped) {
                 res.status = n;
                 live = false;
+            } else if (cross) {
+                if constexpr (SURF) {
+                    // a new leg from the crossing, in the same cell
+                    surface_turn(*sf, leg, ox, oy, oz, dx, dy, dz, tmax);
+                    sh_basis<DEG>(dx, dy, dz, Y);
+                    t0 = 0.0;
+                    cont = true;
+                }
             } else {
                 ref = v.h.next;
                 t0 = v.te;
@@ -394,22 +532,40 @@ __device__ inline void walk_forward_staged(const SceneView& s, bool live, float 
     if constexpr (LOG) {
         if (logged) {
             if (n <= lg->cap) tail = ref;
-            lg->tail[r] = make_int4((int)tail.x, (int)tail.y, n, 0);
+            lg->tail[r] = make_int4((int)tail.x, (int)tail.y, n, leg.bounces);
         }
     }
 }
 
-// Pinhole camera ray through the centre of pixel (px, py): direction
-// R (px + 0.5 - W/2, py + 0.5 - H/2, f) normalised; t_max is where the ray
+// Camera ray through the centre of pixel (px, py). Model 0, pinhole:
+// direction R (px + 0.5 - W/2, py + 0.5 - H/2, f) normalised; t_max is where the ray
 // leaves the bound (kind 0: box lo=b[0..2], hi=b[3..5]; kind 1: sphere of
 // radius b[0] about the world origin).
-__device__ inline void camera_ray(const float* rot, const float* pos, float focal, int W, int H, int px, int py,
-                                  int bound_kind, const float* bound, float d[3], float* tmax)
+//
+// model 1, equidistant fisheye: the angle from the optical axis is
+// proportional to the pixel's distance rho from the image centre,
+// theta = rho * focal (focal: radians per pixel), and the camera-frame
+// direction is (sin theta u/rho, sin theta v/rho, cos theta).
+__device__ inline void camera_ray(const float* rot, const float* pos, int model, float focal, int W, int H, int px,
+                                  int py, int bound_kind, const float* bound, float d[3], float* tmax)
 {
-    const float u = ((float)px + 0.5f - 0.5f * (float)W) / focal;
-    const float v = ((float)py + 0.5f - 0.5f * (float)H) / focal;
+    const float pu = (float)px + 0.5f - 0.5f * (float)W;
+    const float pv = (float)py + 0.5f - 0.5f * (float)H;
+    float u, v, w;
+    if (model == 1) {
+        const float rho = sqrtf(fmaf(pu, pu, pv * pv));
+        const float theta = rho * focal;
+        const float sr = rho > 0.0f ? sinf(theta) / rho : 0.0f;
+        u = sr * pu;
+        v = sr * pv;
+        w = cosf(theta);
+    } else {
+        u = pu / focal;
+        v = pv / focal;
+        w = 1.0f;
+    }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) d[k] = fmaf(rot[3 * k], u, fmaf(rot[3 * k + 1], v, rot[3 * k + 2]));
+    for (int k = 0; k < 3; ++k) d[k] = fmaf(rot[3 * k], u, fmaf(rot[3 * k + 1], v, rot[3 * k + 2] * w));
     const float inv = 1.0f / sqrtf(fmaf(d[0], d[0], fmaf(d[1], d[1], d[2] * d[2])));
     d[0] *= inv;
     d[1] *= inv;

@@ -49,6 +49,7 @@ constexpr int kSeedGrid = 16;           // seed grid for locating camera cells o
 struct ReqRecord {
     float rot[9];
     float pos[3];
+    int32_t model;
     float focal;
     int32_t width, height, start;
     int64_t out_offset;  // floats from the pool base
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_tiles(BatchArgs a)
     const int py = (local / tiles_x) * 8 + (lane >> 3);
     if (px >= W || py >= H) return;
     float d[3], tmax;
-    camera_ray(rq.rot, rq.pos, rq.focal, W, H, px, py, a.bound_kind, a.bound, d, &tmax);
+    camera_ray(rq.rot, rq.pos, rq.model, rq.focal, W, H, px, py, a.bound_kind, a.bound, d, &tmax);
     RayResult res;
     walk_forward<DEG, BF16, false>(a.s, rq.pos[0], rq.pos[1], rq.pos[2], d[0], d[1], d[2], tmax, rq.start, a.eps,
                                    a.max_steps, nullptr, nullptr, 0, res);
@@ -458,7 +459,7 @@ rf_status rf_server_create(const rf_packed_scene* scene, const rf_params* params
 rf_status rf_server_submit(rf_server* s, const rf_camera* cam, int32_t start_cell, uint64_t* req_id)
 {
     if (!s || !cam || !req_id) return sfail(RF_ERR_INVALID_ARG, "NULL argument");
-    if (cam->width <= 0 || cam->height <= 0 || !(cam->fov_deg > 0.0f && cam->fov_deg < 180.0f))
+    if (cam->width <= 0 || cam->height <= 0 || !rf::camera_fov_ok(cam->model, cam->fov_deg))
         return sfail(RF_ERR_INVALID_ARG, "invalid camera");
     const int64_t pixels = (int64_t)cam->width * cam->height;
     const int64_t n_tiles = (int64_t)((cam->width + 7) / 8) * ((cam->height + 7) / 8);
@@ -493,7 +494,8 @@ rf_status rf_server_submit(rf_server* s, const rf_camera* cam, int32_t start_cel
         for (int j = 0; j < 3; ++j) r.rot[3 * i + j] = cam->pose[4 * i + j];
         r.pos[i] = cam->pose[4 * i + 3];
     }
-    r.focal = (float)(0.5 * cam->width / tan(0.5 * (double)cam->fov_deg * M_PI / 180.0));
+    r.model = cam->model;
+    r.focal = rf::camera_focal(cam->model, cam->fov_deg, cam->width);
     r.width = cam->width;
     r.height = cam->height;
     r.start = start_cell;

@@ -54,7 +54,7 @@ __device__ inline int64_t ray_index()
     return xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
 }
 
-template <int DEG, bool BF16, bool TRACE, bool LOG>
+template <int DEG, bool BF16, bool TRACE, bool LOG, bool SURF = false>
 __global__ __launch_bounds__(kBlock) void k_forward(WalkArgs a)
 {
     using SL = StageLayout<DEG, BF16>;
@@ -65,10 +65,10 @@ __global__ __launch_bounds__(kBlock) void k_forward(WalkArgs a)
     const int64_t q = valid ? r : 0;
     RayResult res;
     const LogView lg = {a.log_code, a.log_te, a.log_tail, a.log_cap, a.n_rays};
-    walk_forward_staged<DEG, BF16, TRACE, LOG>(
+    walk_forward_staged<DEG, BF16, TRACE, LOG, SURF>(
         a.s, valid, a.origin[3 * q], a.origin[3 * q + 1], a.origin[3 * q + 2], a.dir[3 * q], a.dir[3 * q + 1],
         a.dir[3 * q + 2], a.t_max[q], a.start[q], a.eps, a.max_steps, TRACE ? a.cells + q * a.max_len : nullptr,
-        TRACE ? a.t_exit + q * a.max_len : nullptr, a.max_len, res, &lg, q, region);
+        TRACE ? a.t_exit + q * a.max_len : nullptr, a.max_len, res, &lg, q, region, &a.surf);
     if (!valid) return;
     a.rgb[3 * r + 0] = res.C[0];
     a.rgb[3 * r + 1] = res.C[1];
@@ -290,7 +290,12 @@ __device__ inline void exit_offsets(double t, float ox, float oy, float oz, floa
     }
 }
 
-template <int DEG, bool BF16, bool REDUCE, bool LOG>
+// With SURF the walks bend at the surface as in the forward: each crossing
+// (logged, or found again by the recomputing walk) turns the leg with the
+// same arithmetic, the colour of the next visits uses the new leg's basis,
+// and the lane's LDS basis row is switched once the last package of the old
+// leg has been emitted.
+template <int DEG, bool BF16, bool REDUCE, bool LOG, bool SURF = false>
 __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
 {
     constexpr int B = sh_count(DEG);
@@ -343,6 +348,13 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
     float Y[B];
     sh_basis<DEG>(dx, dy, dz, Y);
     if constexpr (REDUCE) em.set_basis(Y);
+    Leg leg = {INFINITY, 0, 0};
+    bool cont = false;       // the next visit continues a cell after a crossing
+    bool new_leg = false;    // the next visit is the first of a new leg
+    bool basis_due = false;  // switch the emitter's basis after this iteration's emission
+    if constexpr (SURF) {
+        if (state == 0) leg_start(a.surf, ox, oy, oz, dx, dy, dz, leg);
+    }
 
     // quantile regulariser, if requested: with D = u T_f / (1 - u + u T_f)
     // (dL/dtau_total of L = -ln(1 - u A)) and the quantile's visit k, density
@@ -395,11 +407,16 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
             if constexpr (LOG)
                 stop = (n == n_total);
             else
-                stop = !(T > a.eps) || (n == a.max_steps);
+                stop = (!cont && !(T > a.eps)) || (n == a.max_steps);
             if (!stop) {
                 Visit<DEG> v;
                 int cell;
-                bool moves;
+                bool moves, cross = false;
+                if (new_leg) {
+                    basis_due = true;
+                    new_leg = false;
+                }
+                cont = false;
                 if constexpr (LOG) {
                     // the visit as the forward logged it: same record, same te,
                     // so the same segment bit for bit, without the face scan
@@ -419,11 +436,23 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
                     v.t1 = v.te;  // a moving exit is unclamped: te = t1
                     v.clipped = (code & kLogClipped) != 0;
                     moves = (code & kLogMoves) != 0;
+                    if constexpr (SURF) {
+                        cross = (code & kLogCross) != 0;
+                        if (cross) leg.ts = v.te;  // the crossing as the forward found it
+                    }
                     segment<DEG>(t0, Y, v);
                 } else {
                     cell = ref_cell(ref);
                     visit_cell<DEG, BF16>(a.s, ref, t0, tmax, ox, oy, oz, dx, dy, dz, Y, v);
-                    moves = !v.clipped && (v.t1 >= t0);
+                    if constexpr (SURF) {
+                        if (leg.ts < v.te) {
+                            cross = true;
+                            v.te = leg.ts;
+                            v.clipped = false;
+                            segment<DEG>(t0, Y, v);
+                        }
+                    }
+                    moves = !v.clipped && !cross && (v.t1 >= t0);
                 }
                 const Attr<DEG>& at = v.at;
                 const float w = T * v.alpha;
@@ -483,6 +512,17 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
                 ++n;
                 if (v.clipped) {
                     stop = true;
+                } else if (cross) {
+                    if constexpr (SURF) {
+                        // a new leg from the crossing, in the same cell; the
+                        // crossing's exit does not move, so nothing links the
+                        // two legs' gradients
+                        surface_turn(a.surf, leg, ox, oy, oz, dx, dy, dz, tmax);
+                        sh_basis<DEG>(dx, dy, dz, Y);
+                        t0 = 0.0;
+                        cont = true;
+                        new_leg = true;
+                    }
                 } else {
                     if (!LOG) ref = v.h.next;
                     t0 = v.te;
@@ -521,6 +561,12 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
             em.emit(has, out);
         else
             emit_atomic<DEG>(has, out, Y, a);
+        if constexpr (SURF && REDUCE) {
+            if (basis_due) {
+                em.set_basis(Y);
+                basis_due = false;
+            }
+        }
     }
     if constexpr (REDUCE) em.flush();
 }
@@ -589,7 +635,9 @@ __global__ __launch_bounds__(kBlock) void k_quantile(WalkArgs a)
         q.L[0] = -log1pf(-a.q_u[2 * r] * A);
         q.L[1] = -log1pf(-a.q_u[2 * r + 1] * A);
         const int4 tl = a.log_tail[r];
-        if (tl.z >= 0 && tl.z <= a.log_cap) {
+        if (tl.w != 0) {
+            // a bent walk (surface crossings): the quantiles are defined along one leg only
+        } else if (tl.z >= 0 && tl.z <= a.log_cap) {
             double t0 = 0.0;
             for (int n = 0; n < tl.z; ++n) {
                 const uint32_t code = a.log_code[(int64_t)n * a.n_rays + r];
@@ -666,6 +714,19 @@ static hipError_t launch_walk_t(WalkKind kind, const WalkArgs& a, hipStream_t st
         break;
     case kQuantile:
         hipLaunchKernelGGL((k_quantile<DEG, BF16>), grid, block, 0, stream, a);
+        break;
+    case kForwardSurf:
+        hipLaunchKernelGGL((k_forward<DEG, BF16, false, false, true>), grid, block, 0, stream, a);
+        break;
+    case kForwardLogSurf:
+        hipLaunchKernelGGL((k_forward<DEG, BF16, false, true, true>), grid, block, 0, stream, a);
+        break;
+    case kBackwardSurf:
+        hipLaunchKernelGGL((k_backward<DEG, BF16, true, false, true>), grid, block, 0, stream, a);
+        break;
+    case kBackwardLogSurf:
+        hipLaunchKernelGGL((k_backward<DEG, BF16, true, true, true>), grid, block, 0, stream, a);
+        hipLaunchKernelGGL((k_backward<DEG, BF16, true, false, true>), grid, block, 0, stream, a);
         break;
     }
     return hipGetLastError();

@@ -111,13 +111,17 @@ def _params(eps: float, max_steps: int) -> L.Params:
     return L.Params(float(eps), int(max_steps))
 
 
-def camera_desc(pose12, fov_deg: float, width: int, height: int) -> L.CameraDesc:
+CAMERA_MODELS = {"pinhole": 0, "fisheye": 1}
+
+
+def camera_desc(pose12, fov_deg: float, width: int, height: int, model: str = "pinhole") -> L.CameraDesc:
     c = L.CameraDesc()
     for k, v in enumerate(pose12):
         c.pose[k] = float(v)
     c.fov_deg = float(fov_deg)
     c.width = int(width)
     c.height = int(height)
+    c.model = CAMERA_MODELS[model]
     return c
 
 
@@ -138,8 +142,8 @@ def bound_desc(bound: tuple) -> L.BoundDesc:
 
 
 def raygen(pose12, fov_deg: float, width: int, height: int, bound: tuple, start: int,
-           device="cuda", with_pixel: bool = True):
-    """Camera rays in 8x8 tile order: (origin, dir, t_max, start_cell, pixel)."""
+           device="cuda", with_pixel: bool = True, model: str = "pinhole"):
+    """Camera rays (pinhole or equidistant fisheye) in 8x8 tile order: (origin, dir, t_max, start_cell, pixel)."""
     R = int(width) * int(height)
     dev = torch.device(device)
     o = torch.empty((R, 3), dtype=torch.float32, device=dev)
@@ -147,11 +151,36 @@ def raygen(pose12, fov_deg: float, width: int, height: int, bound: tuple, start:
     t = torch.empty(R, dtype=torch.float32, device=dev)
     s = torch.empty(R, dtype=torch.int32, device=dev)
     px = torch.empty(R, dtype=torch.int32, device=dev) if with_pixel else None
-    cam = camera_desc(pose12, fov_deg, width, height)
+    cam = camera_desc(pose12, fov_deg, width, height, model)
     b = bound_desc(bound)
     L.check(L.lib().rf_raygen(ctypes.byref(cam), ctypes.byref(b), int(start), o.data_ptr(), d.data_ptr(),
                               t.data_ptr(), s.data_ptr(), _ptr(px), _stream(dev)))
     return o, d, t, s, px
+
+
+SURFACE_KINDS = {"mirror": 1, "glass": 2}
+
+
+class Surface:
+    """An analytic sphere that bends rays (``rf_surface``): a ``"mirror"`` or
+    ``"glass"`` of refractive index ``ior`` inside; legs after a crossing end
+    at ``bound`` (as in ``raygen``); crossings after the first
+    ``max_bounces`` are ignored."""
+
+    def __init__(self, kind: str, centre, radius: float, bound: tuple, ior: float = 1.5, max_bounces: int = 8):
+        if kind not in SURFACE_KINDS:
+            raise ValueError(f"surface kind must be one of {sorted(SURFACE_KINDS)}")
+        self.kind, self.centre, self.radius, self.ior = kind, tuple(float(c) for c in centre), radius, ior
+        self.bound, self.max_bounces = bound, max_bounces
+        d = L.SurfaceDesc()
+        d.kind = SURFACE_KINDS[kind]
+        d.max_bounces = int(max_bounces)
+        for k in range(3):
+            d.centre[k] = self.centre[k]
+        d.radius = float(radius)
+        d.ior = float(ior)
+        d.bound = bound_desc(bound)
+        self.desc = d
 
 
 class Quantiles:
@@ -226,8 +255,10 @@ class WalkLog:
 
 
 def render_forward(scene: PackedScene, origin, direction, t_max, start, eps: float = DEFAULT_EPS,
-                   max_steps: int = DEFAULT_MAX_STEPS, out=None, log: Optional[WalkLog] = None):
-    """rgb [R,3], t_final [R], steps [R] (int32; < 0 flags RF_RAY_*); also fills ``log`` if given."""
+                   max_steps: int = DEFAULT_MAX_STEPS, out=None, log: Optional[WalkLog] = None,
+                   surface: Optional[Surface] = None):
+    """rgb [R,3], t_final [R], steps [R] (int32; < 0 flags RF_RAY_*); also fills ``log`` if given.
+    With ``surface`` the rays bend at it (secondary rays)."""
     R = int(direction.shape[0])
     dev = direction.device
     if out is None:
@@ -237,7 +268,14 @@ def render_forward(scene: PackedScene, origin, direction, t_max, start, eps: flo
     rgb, tf, steps = out
     rays = _rays(origin, direction, t_max, start)
     p = _params(eps, max_steps)
-    if log is None:
+    if surface is not None:
+        if log is not None:
+            log.check(R)
+        L.check(L.lib().rf_render_forward_surface(ctypes.byref(scene.desc), ctypes.byref(rays), ctypes.byref(p),
+                                                  ctypes.byref(surface.desc), rgb.data_ptr(), tf.data_ptr(),
+                                                  steps.data_ptr(), ctypes.byref(log.desc) if log is not None else None,
+                                                  _stream(dev)))
+    elif log is None:
         L.check(L.lib().rf_render_forward(ctypes.byref(scene.desc), ctypes.byref(rays), ctypes.byref(p),
                                           rgb.data_ptr(), tf.data_ptr(), steps.data_ptr(), _stream(dev)))
     else:
@@ -268,7 +306,7 @@ def render_trace(scene: PackedScene, origin, direction, t_max, start, eps: float
 def render_backward(scene: PackedScene, origin, direction, t_max, start, rgb, t_final, grad_rgb,
                     grad_t_final=None, eps: float = DEFAULT_EPS, max_steps: int = DEFAULT_MAX_STEPS,
                     mode: int = 0, grads=None, log: Optional[WalkLog] = None,
-                    quantiles: Optional["Quantiles"] = None, grad_loss=None):
+                    quantiles: Optional["Quantiles"] = None, grad_loss=None, surface: Optional[Surface] = None):
     """Gradients (sites [N,3], density [N], sh [N,B,3]); accumulated into ``grads`` if given.
 
     With ``log`` (filled by ``render_forward`` on the same scene, rays and
@@ -293,7 +331,19 @@ def render_backward(scene: PackedScene, origin, direction, t_max, start, rgb, t_
     _dev(gsh, torch.float32, (n, B, 3), "grad_sh")
     rays = _rays(origin, direction, t_max, start)
     p = _params(eps, max_steps)
-    if quantiles is not None:
+    if surface is not None:
+        if quantiles is not None:
+            raise ValueError("the quantile regulariser is defined for unbent rays only")
+        if mode != 0:
+            raise ValueError("with a surface the backward always reduces per wavefront (mode 0)")
+        if log is not None:
+            log.check(R)
+        L.check(L.lib().rf_render_backward_surface(ctypes.byref(scene.desc), ctypes.byref(rays), ctypes.byref(p),
+                                                   ctypes.byref(surface.desc), rgb.data_ptr(), t_final.data_ptr(),
+                                                   grad_rgb.data_ptr(), _ptr(grad_t_final),
+                                                   ctypes.byref(log.desc) if log is not None else None,
+                                                   gs.data_ptr(), gd.data_ptr(), gsh.data_ptr(), _stream(dev)))
+    elif quantiles is not None:
         if log is None or grad_loss is None:
             raise ValueError("the quantile term needs the walk log and grad_loss")
         log.check(R)
@@ -322,7 +372,7 @@ class RadFoamRender(torch.autograd.Function):
     """Differentiable render of rays through a Voronoi scene.
 
     forward(sites, density, sh, off, idx, origin, dir, t_max, start, sh_degree,
-            attr_dtype, eps, max_steps, log_capacity, quantile_draws)
+            attr_dtype, eps, max_steps, log_capacity, quantile_draws, surface)
         -> (rgb [R,3], t_final [R], steps [R], quantile_loss [R])
 
     Packs the scene (face planes from the current sites, attributes in
@@ -330,19 +380,24 @@ class RadFoamRender(torch.autograd.Function):
     ``log_capacity`` visits per ray (0: none; the backward then recomputes
     every walk). With ``quantile_draws`` [R,2] it also returns the quantile
     regulariser |W^-1(u1) - W^-1(u2)| per ray (Sec. 3.4; zeros otherwise).
+    With ``surface`` (a ``Surface``) the rays bend at it; the quantile
+    regulariser is then not available.
     Gradients flow to sites, density and sh; none to the rays or the adjacency.
     """
 
     @staticmethod
     def forward(ctx, sites, density, sh, off, idx, origin, direction, t_max, start, sh_degree: int = 3,
                 attr_dtype: str = "f32", eps: float = DEFAULT_EPS, max_steps: int = DEFAULT_MAX_STEPS,
-                log_capacity: int = DEFAULT_LOG_CAPACITY, quantile_draws=None):
+                log_capacity: int = DEFAULT_LOG_CAPACITY, quantile_draws=None, surface=None):
+        if surface is not None and quantile_draws is not None:
+            raise ValueError("the quantile regulariser is defined for unbent rays only")
         sites_c, dens_c, sh_c = sites.detach().contiguous(), density.detach().contiguous(), sh.detach().contiguous()
         scene = PackedScene(sites_c, off, idx, dens_c, sh_c, sh_degree, attr_dtype, validate=False)
         R = int(direction.shape[0])
         want_log = log_capacity > 0 or quantile_draws is not None
         log = WalkLog(R, max(log_capacity, 0), direction.device) if want_log else None
-        rgb, tf, steps = render_forward(scene, origin, direction, t_max, start, eps, max_steps, log=log)
+        rgb, tf, steps = render_forward(scene, origin, direction, t_max, start, eps, max_steps, log=log,
+                                        surface=surface)
         q = None
         if quantile_draws is not None:
             q, qloss = quantile_forward(scene, origin, direction, t_max, start, tf, log,
@@ -352,6 +407,7 @@ class RadFoamRender(torch.autograd.Function):
         ctx.scene = scene
         ctx.log = log
         ctx.q = q
+        ctx.surface = surface
         ctx.hyper = (eps, max_steps)
         ctx.save_for_backward(origin, direction, t_max, start, rgb, tf)
         ctx.mark_non_differentiable(steps)
@@ -372,17 +428,18 @@ class RadFoamRender(torch.autograd.Function):
                                       grad_rgb.contiguous().float(),
                                       None if grad_tf is None else grad_tf.contiguous().float(), eps, max_steps,
                                       log=ctx.log, quantiles=q,
-                                      grad_loss=None if q is None else grad_q.contiguous().float())
+                                      grad_loss=None if q is None else grad_q.contiguous().float(),
+                                      surface=ctx.surface)
         ctx.log = None
         ctx.q = None
-        return gs, gd, gsh, None, None, None, None, None, None, None, None, None, None, None, None
+        return gs, gd, gsh, None, None, None, None, None, None, None, None, None, None, None, None, None
 
 
 def render(sites, density, sh, off, idx, origin, direction, t_max, start, sh_degree: int = 3,
            attr_dtype: str = "f32", eps: float = DEFAULT_EPS, max_steps: int = DEFAULT_MAX_STEPS,
-           log_capacity: int = DEFAULT_LOG_CAPACITY, quantile_draws=None):
+           log_capacity: int = DEFAULT_LOG_CAPACITY, quantile_draws=None, surface=None):
     """Autograd entry point: (rgb, t_final, steps), plus the per-ray quantile
-    loss when ``quantile_draws`` [R,2] is given."""
+    loss when ``quantile_draws`` [R,2] is given; ``surface`` bends the rays."""
     out = RadFoamRender.apply(sites, density, sh, off, idx, origin, direction, t_max, start, sh_degree,
-                              attr_dtype, eps, max_steps, log_capacity, quantile_draws)
+                              attr_dtype, eps, max_steps, log_capacity, quantile_draws, surface)
     return out if quantile_draws is not None else out[:3]

@@ -35,9 +35,10 @@ class Server:
         self._ids = (ctypes.c_uint64 * self.max_inflight)()
         self.sizes: Dict[int, tuple] = {}
 
-    def submit(self, pose12, fov_deg: float, width: int, height: int, start_cell: int) -> Optional[int]:
+    def submit(self, pose12, fov_deg: float, width: int, height: int, start_cell: int,
+               model: str = "pinhole") -> Optional[int]:
         """Request id, or None if not admissible now (no free slot or pool space)."""
-        cam = camera_desc(pose12, fov_deg, width, height)
+        cam = camera_desc(pose12, fov_deg, width, height, model)
         rid = ctypes.c_uint64()
         st = L.lib().rf_server_submit(self._h, ctypes.byref(cam), int(start_cell), ctypes.byref(rid))
         if st == L.RF_ERR_BUSY:
