@@ -104,6 +104,8 @@ def main() -> int:
     ap.add_argument("--no-serving", action="store_true", help="skip the serving replay (512 Poisson requests)")
     ap.add_argument("--no-locate", action="store_true", help="skip the start-cell location timing")
     ap.add_argument("--no-quantile", action="store_true", help="skip the quantile regulariser timing")
+    ap.add_argument("--no-effects", action="store_true", help="skip the secondary-ray and fisheye timing")
+    ap.add_argument("--no-training", action="store_true", help="skip the optimizer / densification timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -287,10 +289,106 @@ def main() -> int:
         out["locate"] = locate(rf, scenes["f32"], bound, dev)
     if not args.no_quantile and walk_log is not None:
         out["quantile"] = quantile_cost(rf, scenes["f32"], rays, grad_rgb, walk_log, dev, args.steps)
+    if not args.no_training:
+        out["training"] = training_cost(rf, scene, sites, off, idx, dens, sh, grads, dev, args.steps)
+    if not args.no_effects and walk_log is not None:
+        out["effects"] = effects_cost(rf, scenes["f32"], rays, grad_rgb, walk_log, bound, pose, fov, W, H, start, dev,
+                                      args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, cam, bound, start, g_np, visits / R, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def training_cost(rf, scene, sites, off, idx, dens, sh, grads, dev, reps: int):
+    """The optimizer step (Adam over positions, density and SH with the
+    paper's schedule, mid-run) against the HBM roofline (28 bytes per value:
+    x, g, m, v read; x, m, v written), and the densification score, the
+    sampling of 10% of the cells as candidates and the pruning mask."""
+    import torch
+
+    p = [sites.clone(), dens.clone(), sh.clone()]
+    st = rf.AdamState(scene.n_sites, scene.sh_deg, dev)
+    args = rf.train_schedule(10000, 20000)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            ev[0].record()
+            fn()
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms.append(ev[0].elapsed_time(ev[1]))
+        return float(np.mean(ms))
+
+    ms_adam = timed(lambda: rf.adam_step(args, st, p[0], p[1], p[2], grads[0], grads[1], grads[2]))
+    values = p[0].numel() + p[1].numel() + p[2].numel()
+    gbs = values * 28 / (ms_adam * 1e-3) / 1e9
+    g = torch.Generator(device=dev)
+    g.manual_seed(13)
+    gsites = torch.randn((scene.n_sites, 3), device=dev, generator=g)
+    draws = torch.rand(scene.n_sites // 10, device=dev, generator=g)
+    ms_score = timed(lambda: rf.densify_scores(sites, off, idx, gsites))
+    scores = rf.densify_scores(sites, off, idx, gsites)
+    ms_sample = timed(lambda: rf.sample_cells(scores, draws))
+    ms_prune = timed(lambda: rf.prune_mask(dens, off, idx, 0.01))
+    log(f"adam step: {values} values in {ms_adam:.3f} ms ({gbs:.0f} GB/s of {HBM_PEAK_GBS:.0f}); densify score "
+        f"{ms_score:.3f} ms, sampling {len(draws)} candidates {ms_sample:.3f} ms, prune mask {ms_prune:.3f} ms")
+    return {"adam_ms": round(ms_adam, 4), "adam_values": values,
+            "adam_roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_value": 28},
+            "densify_score_ms": round(ms_score, 4), "sample_ms": round(ms_sample, 4),
+            "sample_draws": len(draws), "prune_mask_ms": round(ms_prune, 4)}
+
+
+def effects_cost(rf, packed, rays, grad_rgb, walk_log, bound, pose, fov, W, H, start, dev, reps: int):
+    """Ray-based effects on the same frame (FP32 attributes): the logged
+    training step (forward + backward) with a glass sphere (index 1.5,
+    radius 0.3 at the scene's centre, filling the middle of the view) and
+    with a mirror sphere, and a 180-degree fisheye camera's raygen + forward."""
+    import torch
+
+    o, d, t, s = rays
+    R = int(d.shape[0])
+    n, B = packed.n_sites, (packed.sh_degree + 1) ** 2
+    grads = (torch.zeros((n, 3), device=dev), torch.zeros(n, device=dev), torch.zeros((n, B, 3), device=dev))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    out = {}
+    for kind in ("glass", "mirror"):
+        sf = rf.Surface(kind, (0.0, 0.0, 0.0), 0.3, bound, ior=1.5, max_bounces=8)
+        fw, bw = [], []
+        for k in range(reps + 1):
+            ev[0].record()
+            rgb, tf, _ = rf.render_forward(packed, o, d, t, s, log=walk_log, surface=sf)
+            ev[1].record()
+            rf.render_backward(packed, o, d, t, s, rgb, tf, grad_rgb, grads=grads, log=walk_log, surface=sf)
+            ev[2].record()
+            torch.cuda.synchronize()
+            if k:
+                fw.append(ev[0].elapsed_time(ev[1]))
+                bw.append(ev[1].elapsed_time(ev[2]))
+        bent = float((walk_log.tail[:, 3] > 0).float().mean())
+        ms = float(np.mean(fw) + np.mean(bw))
+        out[kind] = {"forward_ms": round(float(np.mean(fw)), 4), "backward_ms": round(float(np.mean(bw)), 4),
+                     "fwd_bwd_mrays_s": round(R / ms / 1e3, 2), "rays_bent": round(bent, 4)}
+        log(f"{kind} sphere: forward {np.mean(fw):.3f} ms, backward {np.mean(bw):.3f} ms "
+            f"({R / ms / 1e3:.1f} Mrays/s fwd+bwd), {bent:.1%} of rays bent")
+    fe = []
+    for k in range(reps + 1):
+        ev[0].record()
+        fo, fd, ft, fs, _ = rf.raygen(pose, 180.0, W, H, bound, start, device=dev, with_pixel=False, model="fisheye")
+        rf.render_forward(packed, fo, fd, ft, fs)
+        ev[1].record()
+        torch.cuda.synchronize()
+        if k:
+            fe.append(ev[0].elapsed_time(ev[1]))
+    out["fisheye_180"] = {"raygen_forward_ms": round(float(np.mean(fe)), 4),
+                          "fwd_mrays_s": round(R / float(np.mean(fe)) / 1e3, 2)}
+    log(f"fisheye 180 deg: raygen + forward {np.mean(fe):.3f} ms")
+    return out
 
 
 def quantile_cost(rf, packed, rays, grad_rgb, walk_log, dev, reps: int):

@@ -98,7 +98,15 @@ typedef struct {
     int64_t n_sites;
     int64_t n_edges;
     int32_t sh_degree; /* 0..3 */
+    int32_t density_activation; /* RF_DENSITY_PLAIN: density is sigma (>= 0);
+                                   RF_DENSITY_SOFTPLUS: density holds the raw
+                                   parameter x, sigma = ln(1 + e^{10 x}) / 10
+                                   (the paper's softplus with beta = 10, Sec. 3.4),
+                                   applied by rf_pack_scene */
 } rf_scene;
+
+#define RF_DENSITY_PLAIN 0
+#define RF_DENSITY_SOFTPLUS 1
 
 /* ------------------------------------------------------------------------
  * Packed scene: device-resident records that the walk reads.
@@ -389,6 +397,77 @@ rf_status rf_render_backward_surface(const rf_packed_scene *scene, const rf_rays
 rf_status rf_render_trace(const rf_packed_scene *scene, const rf_rays *rays, const rf_params *params,
                           int32_t max_len, float *rgb, float *t_final, int32_t *steps, int32_t *cells,
                           float *t_exit, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Training-step pieces around the walk (Sec. 3.3 and the implementation
+ * details of Sec. 3.4). Parameters are grouped as positions, density, SH of
+ * order 0 and SH of the higher orders.
+ *
+ * rf_train_schedule fills the Adam settings of 0-based `iteration` of a
+ * `total`-iteration run with the paper's schedule: cosine annealing of each
+ * group's learning rate, lr_end + (lr_0 - lr_end)(1 + cos(pi it / total))/2,
+ * from 2e-4 to 2e-6 (positions), 1e-1 to 1e-2 (density), 5e-3 to 5e-4 (SH);
+ * the higher SH orders held (lr 0) for the first total/4 iterations and the
+ * positions from iteration total - total/10 on (the paper's last 2k of 20k);
+ * t = each group's step count including this step (held steps do not
+ * count); betas 0.9 and 0.999; eps 1e-15; softplus density.
+ *
+ * rf_adam_step applies one Adam step in place: for each value of a group with
+ * lr > 0, m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * x -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps); a held group
+ * (lr = 0) keeps its values and moments. With softplus_density, `density`
+ * holds the raw parameter x and grad_density is taken w.r.t. sigma (what the
+ * backward returns), chained by d sigma / dx = 1 / (1 + e^{-10 x}). Arrays:
+ * sites [n][3], density [n], sh [n][B][3], their gradients, and the moments
+ * of each (caller-zeroed before the first step, caller-owned device memory;
+ * 16-byte aligned arrays are streamed four values per thread). FP32.
+ *
+ * rf_densify_scores: per cell, |dL/dx_i| times its approximate radius, half
+ * the mean distance to its Delaunay neighbours (0 for a cell without any).
+ *
+ * rf_sample_cells: n_draws densification candidates from the multinomial
+ * distribution proportional to `scores` (>= 0, not all 0): draw k (u in
+ * [0, 1)) picks the first cell whose cumulative score exceeds u times the
+ * total, so a cell owns [C_{i-1}, C_i) and a zero score is never picked.
+ * The cumulative sum is formed in double in the caller's workspace of
+ * rf_sample_workspace(n) bytes (8-byte aligned).
+ *
+ * rf_prune_mask: mask[i] = 1 where density[i] (sigma) and the density of
+ * every Delaunay neighbour are below `threshold` (cells that neither carry
+ * nor bound a surface), else 0.
+ *
+ * The score and the mask skip neighbour ids outside [0, n_sites) (the CSR
+ * is not validated here; rf_pack_scene does that for the walk). Offsets must
+ * be monotone and within the idx array.
+ *
+ * All run on `stream`; errors: RF_ERR_INVALID_ARG for NULL arrays, negative
+ * sizes, a schedule iteration outside [0, total), betas outside [0, 1),
+ * eps < 0, lr < 0, or a moving group with t < 1.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    float lr[4];      /* positions, density, SH order 0, SH orders >= 1; 0 holds the group */
+    int32_t t[4];     /* each group's Adam step count including this step */
+    float beta1, beta2, eps;
+    int32_t softplus_density;
+} rf_adam_args;
+
+typedef struct {
+    float *m_sites, *v_sites;      /* [n][3] */
+    float *m_density, *v_density;  /* [n] */
+    float *m_sh, *v_sh;            /* [n][B][3] */
+} rf_adam_state;
+
+rf_status rf_train_schedule(int32_t iteration, int32_t total, rf_adam_args *out);
+rf_status rf_adam_step(int64_t n_sites, int32_t sh_degree, const rf_adam_args *args, float *sites, float *density,
+                       float *sh, const float *grad_sites, const float *grad_density, const float *grad_sh,
+                       const rf_adam_state *state, void *stream);
+rf_status rf_densify_scores(const float *sites, const int32_t *nbr_off, const int32_t *nbr_idx, int64_t n_sites,
+                            const float *grad_sites, float *scores, void *stream);
+rf_status rf_sample_workspace(int64_t n, size_t *bytes);
+rf_status rf_sample_cells(const float *scores, int64_t n, const float *draws, int64_t n_draws, int32_t *cells,
+                          void *workspace, size_t workspace_bytes, void *stream);
+rf_status rf_prune_mask(const float *density, const int32_t *nbr_off, const int32_t *nbr_idx, int64_t n_sites,
+                        float threshold, uint8_t *mask, void *stream);
 
 /* Copies the packed face planes (float4 per directed edge, CSR order) into
  * planes[n_edges][4]; for tests of the packing step. */

@@ -15,18 +15,24 @@ from .ops import (  # noqa: E402,F401
     DEFAULT_EPS,
     DEFAULT_LOG_CAPACITY,
     DEFAULT_MAX_STEPS,
+    AdamState,
     PackedScene,
     Quantiles,
     RadFoamRender,
     Surface,
     WalkLog,
+    adam_step,
+    densify_scores,
     locate,
+    prune_mask,
     quantile_forward,
     raygen,
     render,
     render_backward,
     render_forward,
     render_trace,
+    sample_cells,
+    train_schedule,
 )
 
 __version__ = "0.1.0"

@@ -19,6 +19,8 @@ RF_OK = 0
 RF_ERR_INVALID_ARG = 1
 RF_F32 = 0
 RF_BF16 = 1
+RF_DENSITY_PLAIN = 0
+RF_DENSITY_SOFTPLUS = 1
 RF_RAY_BAD_START = -1
 RF_RAY_MAX_STEPS = -2
 STATUS_NAMES = {0: "RF_OK", 1: "RF_ERR_INVALID_ARG", 2: "RF_ERR_HIP", 3: "RF_ERR_OOM",
@@ -35,7 +37,16 @@ class RfError(RuntimeError):
 class Scene(ctypes.Structure):
     _fields_ = [("sites", ctypes.c_void_p), ("nbr_off", ctypes.c_void_p), ("nbr_idx", ctypes.c_void_p),
                 ("density", ctypes.c_void_p), ("sh", ctypes.c_void_p), ("n_sites", ctypes.c_int64),
-                ("n_edges", ctypes.c_int64), ("sh_degree", ctypes.c_int32)]
+                ("n_edges", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("density_activation", ctypes.c_int32)]
+
+
+class AdamArgs(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float * 4), ("t", ctypes.c_int32 * 4), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("softplus_density", ctypes.c_int32)]
+
+
+class AdamState(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("m_sites", "v_sites", "m_density", "v_density", "m_sh", "v_sh")]
 
 
 class PackedSceneDesc(ctypes.Structure):
@@ -129,6 +140,13 @@ def lib() -> ctypes.CDLL:
                                                   ctypes.POINTER(Params), P, P, P, P, ctypes.POINTER(WalkLog),
                                                   ctypes.POINTER(Quantiles), P, P, P, P, ctypes.c_int32, P]
         L.rf_locate.argtypes = [ctypes.POINTER(PackedSceneDesc), P, ctypes.c_int64, P, ctypes.c_int32, P, P]
+        L.rf_train_schedule.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(AdamArgs)]
+        L.rf_adam_step.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(AdamArgs), P, P, P, P, P, P,
+                                   ctypes.POINTER(AdamState), P]
+        L.rf_densify_scores.argtypes = [P, P, P, ctypes.c_int64, P, P, P]
+        L.rf_sample_workspace.argtypes = [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
+        L.rf_sample_cells.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P, ctypes.c_size_t, P]
+        L.rf_prune_mask.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_float, P, P]
         L.rf_render_forward_surface.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Rays),
                                                 ctypes.POINTER(Params), ctypes.POINTER(SurfaceDesc), P, P, P,
                                                 ctypes.POINTER(WalkLog), P]
@@ -141,6 +159,8 @@ def lib() -> ctypes.CDLL:
                      "rf_render_trace", "rf_render_backward", "rf_render_forward_logged",
                      "rf_render_backward_logged", "rf_quantile_forward", "rf_render_backward_quantile",
                      "rf_locate", "rf_render_forward_surface", "rf_render_backward_surface",
+                     "rf_train_schedule", "rf_adam_step", "rf_densify_scores", "rf_sample_workspace",
+                     "rf_sample_cells", "rf_prune_mask",
                      "rf_packed_planes", "rf_packed_attributes"):
             getattr(L, name).restype = st
         L.rf_server_create.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Params),

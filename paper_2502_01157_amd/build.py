@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librf.so")
 OBJ_DIR = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "walk.hip", "pack.hip", "serve.hip", "locate.hip"]
+SOURCES = ["api.hip", "walk.hip", "pack.hip", "serve.hip", "locate.hip", "train.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -156,12 +156,15 @@ rf_status rf_pack_scene(const rf_scene* scene, rf_dtype attr_dtype, void* worksp
     if (!workspace || workspace_bytes < need)
         return fail(RF_ERR_INVALID_ARG, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, need);
     if (((uintptr_t)workspace & 255) != 0) return fail(RF_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (scene->density_activation != RF_DENSITY_PLAIN && scene->density_activation != RF_DENSITY_SOFTPLUS)
+        return fail(RF_ERR_INVALID_ARG, "density_activation must be RF_DENSITY_PLAIN or RF_DENSITY_SOFTPLUS");
     if (!scene->sites || !scene->nbr_off || !scene->density || !scene->sh || (scene->n_edges > 0 && !scene->nbr_idx))
         return fail(RF_ERR_INVALID_ARG, "a scene array is NULL");
     const bool bf16 = attr_dtype == RF_BF16;
     const Layout L = layout(scene->n_sites, scene->n_edges, scene->sh_degree, bf16);
     unsigned char* b = static_cast<unsigned char*>(workspace);
     rf::PackArgs a;
+    a.density_act = scene->density_activation;
     a.sites = scene->sites;
     a.off = scene->nbr_off;
     a.idx = scene->nbr_idx;
@@ -531,6 +534,122 @@ rf_status rf_locate(const rf_packed_scene* scene, const float* points, int64_t n
     return hip_status(rf::launch_locate(scene->sh_degree, scene->attr_dtype == RF_BF16, a,
                                         static_cast<hipStream_t>(stream)),
                       "locate");
+}
+
+rf_status rf_train_schedule(int32_t iteration, int32_t total, rf_adam_args* out)
+{
+    if (!out) return fail(RF_ERR_INVALID_ARG, "out is NULL");
+    if (total < 1 || iteration < 0 || iteration >= total)
+        return fail(RF_ERR_INVALID_ARG, "iteration %d outside [0, %d)", iteration, total);
+    static const double lr0[4] = {2e-4, 1e-1, 5e-3, 5e-3}, lr1[4] = {2e-6, 1e-2, 5e-4, 5e-4};
+    const int32_t warm = total / 4, freeze = total - total / 10;
+    const double w = (1.0 + cos(M_PI * (double)iteration / (double)total)) / 2.0;
+    for (int g = 0; g < 4; ++g) out->lr[g] = (float)(lr1[g] + (lr0[g] - lr1[g]) * w);
+    out->t[0] = iteration + 1 < freeze ? iteration + 1 : freeze;
+    out->t[1] = iteration + 1;
+    out->t[2] = iteration + 1;
+    out->t[3] = iteration + 1 - warm > 0 ? iteration + 1 - warm : 0;
+    if (iteration >= freeze) out->lr[0] = 0.0f;
+    if (iteration < warm) out->lr[3] = 0.0f;
+    out->beta1 = 0.9f;
+    out->beta2 = 0.999f;
+    out->eps = 1e-15f;
+    out->softplus_density = 1;
+    return ok();
+}
+
+rf_status rf_adam_step(int64_t n_sites, int32_t sh_degree, const rf_adam_args* args, float* sites, float* density,
+                       float* sh, const float* grad_sites, const float* grad_density, const float* grad_sh,
+                       const rf_adam_state* state, void* stream)
+{
+    if (!args || !state) return fail(RF_ERR_INVALID_ARG, "args or state is NULL");
+    if (n_sites < 0 || sh_degree < 0 || sh_degree > 3) return fail(RF_ERR_INVALID_ARG, "bad n_sites or sh_degree");
+    if (n_sites == 0) return ok();
+    if (!sites || !density || !sh || !grad_sites || !grad_density || !grad_sh || !state->m_sites ||
+        !state->v_sites || !state->m_density || !state->v_density || !state->m_sh || !state->v_sh)
+        return fail(RF_ERR_INVALID_ARG, "a parameter, gradient or moment array is NULL");
+    if (!(args->beta1 >= 0.0f && args->beta1 < 1.0f && args->beta2 >= 0.0f && args->beta2 < 1.0f &&
+          args->eps >= 0.0f))
+        return fail(RF_ERR_INVALID_ARG, "betas must be in [0, 1) and eps >= 0");
+    for (int g = 0; g < 4; ++g)
+        if (!(args->lr[g] >= 0.0f) || (args->lr[g] > 0.0f && args->t[g] < 1))
+            return fail(RF_ERR_INVALID_ARG, "group %d: lr must be >= 0, with a step count >= 1 when it moves", g);
+    const int B = (sh_degree + 1) * (sh_degree + 1);
+    auto corr = [](float beta, int32_t t) { return t > 0 ? (float)(1.0 / (1.0 - pow((double)beta, t))) : 1.0f; };
+    rf::AdamGroup a;
+    a.beta1 = args->beta1;
+    a.beta2 = args->beta2;
+    a.eps = args->eps;
+    a.B = B;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    // positions
+    a.x = sites; a.g = grad_sites; a.m = state->m_sites; a.v = state->v_sites; a.n = 3 * n_sites; a.kind = 0;
+    a.lr[0] = a.lr[1] = args->lr[0];
+    a.c1[0] = a.c1[1] = corr(args->beta1, args->t[0]);
+    a.c2[0] = a.c2[1] = corr(args->beta2, args->t[0]);
+    hipError_t e = rf::launch_adam(a, s);
+    // density
+    if (e == hipSuccess) {
+        a.x = density; a.g = grad_density; a.m = state->m_density; a.v = state->v_density; a.n = n_sites;
+        a.kind = args->softplus_density ? 1 : 0;
+        a.lr[0] = a.lr[1] = args->lr[1];
+        a.c1[0] = a.c1[1] = corr(args->beta1, args->t[1]);
+        a.c2[0] = a.c2[1] = corr(args->beta2, args->t[1]);
+        e = rf::launch_adam(a, s);
+    }
+    // SH: order 0 and the higher orders
+    if (e == hipSuccess) {
+        a.x = sh; a.g = grad_sh; a.m = state->m_sh; a.v = state->v_sh; a.n = 3 * (int64_t)B * n_sites; a.kind = 2;
+        for (int q = 0; q < 2; ++q) {
+            a.lr[q] = args->lr[2 + q];
+            a.c1[q] = corr(args->beta1, args->t[2 + q]);
+            a.c2[q] = corr(args->beta2, args->t[2 + q]);
+        }
+        e = rf::launch_adam(a, s);
+    }
+    return hip_status(e, "adam step");
+}
+
+rf_status rf_densify_scores(const float* sites, const int32_t* nbr_off, const int32_t* nbr_idx, int64_t n_sites,
+                            const float* grad_sites, float* scores, void* stream)
+{
+    if (n_sites < 0) return fail(RF_ERR_INVALID_ARG, "n_sites < 0");
+    if (n_sites > 0 && (!sites || !nbr_off || !nbr_idx || !grad_sites || !scores))
+        return fail(RF_ERR_INVALID_ARG, "an array is NULL");
+    return hip_status(rf::launch_densify_score(sites, nbr_off, nbr_idx, n_sites, grad_sites, scores,
+                                               static_cast<hipStream_t>(stream)),
+                      "densification scores");
+}
+
+rf_status rf_sample_workspace(int64_t n, size_t* bytes)
+{
+    if (n < 0 || !bytes) return fail(RF_ERR_INVALID_ARG, "n < 0 or bytes is NULL");
+    *bytes = (size_t)rf::sample_workspace_doubles(n) * sizeof(double);
+    return ok();
+}
+
+rf_status rf_sample_cells(const float* scores, int64_t n, const float* draws, int64_t n_draws, int32_t* cells,
+                          void* workspace, size_t workspace_bytes, void* stream)
+{
+    if (n < 1 || n > INT32_MAX || n_draws < 0) return fail(RF_ERR_INVALID_ARG, "need 1 <= n <= 2^31 - 1, n_draws >= 0");
+    if (n_draws == 0) return ok();
+    if (!scores || !draws || !cells || !workspace) return fail(RF_ERR_INVALID_ARG, "an array is NULL");
+    if (workspace_bytes < (size_t)rf::sample_workspace_doubles(n) * sizeof(double) ||
+        (reinterpret_cast<uintptr_t>(workspace) & 7))
+        return fail(RF_ERR_INVALID_ARG, "workspace too small (see rf_sample_workspace) or not 8-byte aligned");
+    return hip_status(rf::launch_sample(scores, n, draws, n_draws, cells, static_cast<double*>(workspace),
+                                        static_cast<hipStream_t>(stream)),
+                      "candidate sampling");
+}
+
+rf_status rf_prune_mask(const float* density, const int32_t* nbr_off, const int32_t* nbr_idx, int64_t n_sites,
+                        float threshold, uint8_t* mask, void* stream)
+{
+    if (n_sites < 0) return fail(RF_ERR_INVALID_ARG, "n_sites < 0");
+    if (n_sites > 0 && (!density || !nbr_off || !nbr_idx || !mask)) return fail(RF_ERR_INVALID_ARG, "an array is NULL");
+    return hip_status(rf::launch_prune_mask(density, nbr_off, nbr_idx, n_sites, threshold, mask,
+                                            static_cast<hipStream_t>(stream)),
+                      "pruning mask");
 }
 
 rf_status rf_packed_planes(const rf_packed_scene* scene, float* planes, void* stream)

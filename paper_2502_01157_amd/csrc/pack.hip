@@ -54,6 +54,16 @@ __global__ __launch_bounds__(256) void k_pack_rows(PackArgs a)
 
 // One thread per 16-byte chunk of a cell record, so that consecutive threads
 // write consecutive chunks and read consecutive SH values.
+// Density activation (Sec. 3.4, implementation details): softplus with
+// beta = 10, ln(1 + e^{10 x}) / 10, which is x itself to FP32 precision once
+// 10 x > 20. Evaluated in double: in FP32 the rounding of 10 x alone would
+// put a relative error of |10 x| eps32 on e^{10 x}.
+__device__ inline float softplus10(float x)
+{
+    const double z = 10.0 * (double)x;
+    return z > 20.0 ? x : (float)(log1p(exp(z)) / 10.0);
+}
+
 template <int DEG, bool BF16>
 __global__ __launch_bounds__(256) void k_pack_records(PackArgs a)
 {
@@ -63,6 +73,7 @@ __global__ __launch_bounds__(256) void k_pack_records(PackArgs a)
     const int c = (int)(t - i * R::CHUNKS);
     if (i >= a.n_sites) return;
     const float* sh = a.sh + i * R::NSH;
+    const float sigma = a.density_act ? softplus10(a.density[i]) : a.density[i];
     uint32_t w[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -76,12 +87,12 @@ __global__ __launch_bounds__(256) void k_pack_records(PackArgs a)
             for (int h = 0; h < 2; ++h) {
                 const int k = byte / 2 + h;  // bf16 element index
                 if (k < R::NSH) v |= f32_to_bf16_rne(sh[k]) << (16 * h);
-                else if (k == R::NSH) v |= f32_to_bf16_rne(a.density[i]) << (16 * h);
+                else if (k == R::NSH) v |= f32_to_bf16_rne(sigma) << (16 * h);
             }
         } else {
             const int k = byte / 4;
             if (k < R::NSH) v = __float_as_uint(sh[k]);
-            else if (k == R::NSH) v = __float_as_uint(a.density[i]);
+            else if (k == R::NSH) v = __float_as_uint(sigma);
         }
         w[q] = v;
     }

@@ -76,6 +76,7 @@ struct PackArgs {
     const int32_t* off;
     const int32_t* idx;
     const float* density;
+    int32_t density_act;  // 1: density holds x, sigma = softplus_10(x)
     const float* sh;
     int64_t n_sites;
     int64_t n_edges;
@@ -154,6 +155,31 @@ hipError_t launch_walk(WalkKind kind, int sh_degree, bool bf16, const WalkArgs& 
 hipError_t launch_pack(int sh_degree, bool bf16, const PackArgs& a, hipStream_t stream);
 hipError_t launch_raygen(const RaygenArgs& a, hipStream_t stream);
 hipError_t launch_locate(int sh_degree, bool bf16, const LocateArgs& a, hipStream_t stream);
+
+// Training-step kernels (train.hip).
+// One parameter group of an Adam step over n floats: lr == 0 holds a value
+// (neither it nor its moments change); c1, c2 are the bias corrections
+// 1 / (1 - beta^t) of the group's step count t.
+struct AdamGroup {
+    float* x;
+    const float* g;
+    float* m;
+    float* v;
+    int64_t n;
+    // SH values with basis index b > 0 use the second set
+    float lr[2], c1[2], c2[2];
+    int32_t kind;  // 0 plain, 1 density under softplus (chain the gradient), 2 SH with B basis functions
+    int32_t B;
+    float beta1, beta2, eps;
+};
+hipError_t launch_adam(const AdamGroup& a, hipStream_t stream);
+hipError_t launch_densify_score(const float* sites, const int32_t* off, const int32_t* idx, int64_t n,
+                                const float* grad_sites, float* score, hipStream_t stream);
+hipError_t launch_prune_mask(const float* density, const int32_t* off, const int32_t* idx, int64_t n,
+                             float threshold, uint8_t* mask, hipStream_t stream);
+int64_t sample_workspace_doubles(int64_t n);
+hipError_t launch_sample(const float* score, int64_t n, const float* draws, int64_t n_draws, int32_t* out,
+                         double* workspace, hipStream_t stream);
 hipError_t launch_unpack(int sh_degree, bool bf16, const SceneView& s, float* planes_out, float* density_out,
                          float* sh_out, hipStream_t stream);
 

@@ -1,0 +1,242 @@
+// Training-step kernels around the walk (Sec. 3.3 and the implementation
+// details of Sec. 3.4): the Adam update of positions, density and SH with
+// per-group learning rates, the densification score and multinomial
+// sampling of densification candidates, and the pruning mask.
+//
+// Adam is a pure stream over the parameters (read x, g, m, v; write x, m, v:
+// 28 bytes per value), so it is written for HBM: one launch per group, each
+// thread four consecutive values with 16-byte loads and stores where the
+// group's arrays are 16-byte aligned. The score and the mask read each
+// cell's CSR row (one thread per cell). Sampling scans the scores in double
+// (per block of 1024, then the block totals, then the offsets) and inverts
+// the cumulative sum at each draw by binary search.
+
+#include "rf_device.hpp"
+#include "rf_kernels.hpp"
+
+namespace rf {
+
+constexpr int kTrainBlock = 256;
+
+// ---------------------------------------------------------------------------
+// Adam.
+// ---------------------------------------------------------------------------
+__device__ inline void adam_one(const AdamGroup& a, int64_t k, float& x, float g, float& m, float& v)
+{
+    int s = 0;
+    if (a.kind == 2) s = ((k / 3) % a.B) != 0;
+    const float lr = a.lr[s];
+    if (lr == 0.0f) return;  // a held group keeps its values and moments
+    if (a.kind == 1) {
+        // softplus_10(x) has derivative 1 / (1 + e^{-10 x}) (in double, as the pack's softplus)
+        g = (float)((double)g / (1.0 + exp(-10.0 * (double)x)));
+    }
+    m = fmaf(a.beta1, m, (1.0f - a.beta1) * g);
+    v = fmaf(a.beta2, v, (1.0f - a.beta2) * g * g);
+    x = x - lr * (m * a.c1[s]) / (sqrtf(v * a.c2[s]) + a.eps);
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(kTrainBlock) void k_adam(AdamGroup a)
+{
+    const int64_t t = (int64_t)blockIdx.x * kTrainBlock + threadIdx.x;
+    const int64_t k0 = 4 * t;
+    if (k0 >= a.n) return;
+    if (VEC && k0 + 4 <= a.n) {
+        float4 x = reinterpret_cast<const float4*>(a.x)[t];
+        const float4 g = reinterpret_cast<const float4*>(a.g)[t];
+        float4 m = reinterpret_cast<const float4*>(a.m)[t];
+        float4 v = reinterpret_cast<const float4*>(a.v)[t];
+        adam_one(a, k0 + 0, x.x, g.x, m.x, v.x);
+        adam_one(a, k0 + 1, x.y, g.y, m.y, v.y);
+        adam_one(a, k0 + 2, x.z, g.z, m.z, v.z);
+        adam_one(a, k0 + 3, x.w, g.w, m.w, v.w);
+        reinterpret_cast<float4*>(a.x)[t] = x;
+        reinterpret_cast<float4*>(a.m)[t] = m;
+        reinterpret_cast<float4*>(a.v)[t] = v;
+        return;
+    }
+    for (int64_t k = k0; k < k0 + 4 && k < a.n; ++k) {
+        float x = a.x[k], m = a.m[k], v = a.v[k];
+        adam_one(a, k, x, a.g[k], m, v);
+        a.x[k] = x;
+        a.m[k] = m;
+        a.v[k] = v;
+    }
+}
+
+hipError_t launch_adam(const AdamGroup& a, hipStream_t stream)
+{
+    const int64_t threads = (a.n + 3) / 4;
+    const int64_t blocks = (threads + kTrainBlock - 1) / kTrainBlock;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const bool vec = ((reinterpret_cast<uintptr_t>(a.x) | reinterpret_cast<uintptr_t>(a.g) |
+                       reinterpret_cast<uintptr_t>(a.m) | reinterpret_cast<uintptr_t>(a.v)) & 15) == 0;
+    if (vec)
+        hipLaunchKernelGGL(k_adam<true>, dim3((unsigned)blocks), dim3(kTrainBlock), 0, stream, a);
+    else
+        hipLaunchKernelGGL(k_adam<false>, dim3((unsigned)blocks), dim3(kTrainBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Densification score and pruning mask (one thread per cell).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kTrainBlock) void k_densify_score(const float* __restrict__ sites,
+                                                               const int32_t* __restrict__ off,
+                                                               const int32_t* __restrict__ idx, int64_t n,
+                                                               const float* __restrict__ grad_sites,
+                                                               float* __restrict__ score)
+{
+    const int64_t i = (int64_t)blockIdx.x * kTrainBlock + threadIdx.x;
+    if (i >= n) return;
+    const float xi = sites[3 * i], yi = sites[3 * i + 1], zi = sites[3 * i + 2];
+    const int beg = off[i], end = off[i + 1];
+    float sum = 0.0f;
+    int cnt = 0;
+    for (int k = beg; k < end; ++k) {
+        const int64_t j = idx[k];
+        if (j < 0 || j >= n) continue;  // an invalid neighbour id is skipped
+        const float dx = sites[3 * j] - xi, dy = sites[3 * j + 1] - yi, dz = sites[3 * j + 2] - zi;
+        sum += sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+        ++cnt;
+    }
+    const float r = cnt > 0 ? 0.5f * sum / (float)cnt : 0.0f;
+    const float gx = grad_sites[3 * i], gy = grad_sites[3 * i + 1], gz = grad_sites[3 * i + 2];
+    score[i] = sqrtf(fmaf(gz, gz, fmaf(gy, gy, gx * gx))) * r;
+}
+
+__global__ __launch_bounds__(kTrainBlock) void k_prune_mask(const float* __restrict__ density,
+                                                            const int32_t* __restrict__ off,
+                                                            const int32_t* __restrict__ idx, int64_t n,
+                                                            float threshold, uint8_t* __restrict__ mask)
+{
+    const int64_t i = (int64_t)blockIdx.x * kTrainBlock + threadIdx.x;
+    if (i >= n) return;
+    bool prune = density[i] < threshold;
+    for (int k = off[i]; prune && k < off[i + 1]; ++k) {
+        const int64_t j = idx[k];
+        if (j >= 0 && j < n) prune = density[j] < threshold;  // an invalid neighbour id is skipped
+    }
+    mask[i] = prune ? 1 : 0;
+}
+
+hipError_t launch_densify_score(const float* sites, const int32_t* off, const int32_t* idx, int64_t n,
+                                const float* grad_sites, float* score, hipStream_t stream)
+{
+    const int64_t blocks = (n + kTrainBlock - 1) / kTrainBlock;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_densify_score, dim3((unsigned)blocks), dim3(kTrainBlock), 0, stream, sites, off, idx, n,
+                       grad_sites, score);
+    return hipGetLastError();
+}
+
+hipError_t launch_prune_mask(const float* density, const int32_t* off, const int32_t* idx, int64_t n,
+                             float threshold, uint8_t* mask, hipStream_t stream)
+{
+    const int64_t blocks = (n + kTrainBlock - 1) / kTrainBlock;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prune_mask, dim3((unsigned)blocks), dim3(kTrainBlock), 0, stream, density, off, idx, n,
+                       threshold, mask);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Multinomial sampling by inverting the cumulative score (double).
+// ---------------------------------------------------------------------------
+constexpr int kScanPer = 4;                          // values per thread
+constexpr int kScanTile = kTrainBlock * kScanPer;    // values per block
+
+// Inclusive scan of one tile of scores into cdf; the tile's total into totals[block].
+__global__ __launch_bounds__(kTrainBlock) void k_scan_tiles(const float* __restrict__ score, int64_t n,
+                                                            double* __restrict__ cdf, double* __restrict__ totals)
+{
+    __shared__ double wave_sum[kTrainBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    double v[kScanPer];
+    double run = 0.0;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+        run += base + q < n ? (double)score[base + q] : 0.0;
+        v[q] = run;
+    }
+    // exclusive prefix of the threads' sums: within the wavefront, then across wavefronts
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    double incl = run;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const double o = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += o;
+    }
+    if (lane == kWave - 1) wave_sum[w] = incl;
+    __syncthreads();
+    double before = incl - run;
+    for (int q = 0; q < w; ++q) before += wave_sum[q];
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q)
+        if (base + q < n) cdf[base + q] = before + v[q];
+    if (threadIdx.x == kTrainBlock - 1) totals[blockIdx.x] = before + run;
+}
+
+// Exclusive prefix of the tile totals, in place (one thread: a few thousand tiles).
+__global__ void k_scan_totals(double* totals, int64_t n_tiles)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double acc = 0.0;
+    for (int64_t b = 0; b < n_tiles; ++b) {
+        const double t = totals[b];
+        totals[b] = acc;
+        acc += t;
+    }
+}
+
+__global__ __launch_bounds__(kTrainBlock) void k_scan_add(double* __restrict__ cdf, int64_t n,
+                                                          const double* __restrict__ offsets)
+{
+    const int64_t k = (int64_t)blockIdx.x * kTrainBlock + threadIdx.x;
+    if (k >= n) return;
+    cdf[k] += offsets[k / kScanTile];
+}
+
+// Cell of each draw: the first index whose cumulative score exceeds u * total.
+__global__ __launch_bounds__(kTrainBlock) void k_sample(const double* __restrict__ cdf, int64_t n,
+                                                        const float* __restrict__ draws, int64_t n_draws,
+                                                        int32_t* __restrict__ out)
+{
+    const int64_t k = (int64_t)blockIdx.x * kTrainBlock + threadIdx.x;
+    if (k >= n_draws) return;
+    const double target = (double)draws[k] * cdf[n - 1];
+    int64_t lo = 0, hi = n;  // the answer lies in [lo, hi]
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (cdf[mid] > target)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    out[k] = (int32_t)(lo < n ? lo : n - 1);
+}
+
+int64_t sample_workspace_doubles(int64_t n)
+{
+    return n + (n + kScanTile - 1) / kScanTile;
+}
+
+hipError_t launch_sample(const float* score, int64_t n, const float* draws, int64_t n_draws, int32_t* out,
+                         double* workspace, hipStream_t stream)
+{
+    if (n == 0 || n_draws == 0) return hipSuccess;
+    double* cdf = workspace;
+    double* totals = workspace + n;
+    const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(kTrainBlock), 0, stream, score, n, cdf, totals);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kWave), 0, stream, totals, tiles);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + kTrainBlock - 1) / kTrainBlock)), dim3(kTrainBlock), 0,
+                       stream, cdf, n, totals);
+    hipLaunchKernelGGL(k_sample, dim3((unsigned)((n_draws + kTrainBlock - 1) / kTrainBlock)), dim3(kTrainBlock), 0,
+                       stream, cdf, n, draws, n_draws, out);
+    return hipGetLastError();
+}
+
+}  // namespace rf

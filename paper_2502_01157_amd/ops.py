@@ -51,7 +51,11 @@ class PackedScene:
     """
 
     def __init__(self, sites: torch.Tensor, off: torch.Tensor, idx: torch.Tensor, density: torch.Tensor,
-                 sh: torch.Tensor, sh_degree: int, attr_dtype: str = "f32", validate: bool = True):
+                 sh: torch.Tensor, sh_degree: int, attr_dtype: str = "f32", validate: bool = True,
+                 density_activation: str = "plain"):
+        """``density_activation="softplus"``: ``density`` holds the raw parameter x and the
+        walk sees sigma = ln(1 + e^{10 x}) / 10 (applied by the pack)."""
+        self.density_activation = {"plain": L.RF_DENSITY_PLAIN, "softplus": L.RF_DENSITY_SOFTPLUS}[density_activation]
         self.n_sites = int(sites.shape[0])
         self.n_edges = int(idx.shape[0])
         self.sh_degree = int(sh_degree)
@@ -73,7 +77,7 @@ class PackedScene:
         _dev(density, torch.float32, (n,), "density")
         _dev(sh, torch.float32, (n, B, 3), "sh")
         sc = L.Scene(sites.data_ptr(), self.off.data_ptr(), self.idx.data_ptr(), density.data_ptr(),
-                     sh.data_ptr(), n, self.n_edges, self.sh_degree)
+                     sh.data_ptr(), n, self.n_edges, self.sh_degree, self.density_activation)
         L.check(L.lib().rf_pack_scene(ctypes.byref(sc), self.attr_dtype, self.workspace.data_ptr(),
                                       self.workspace.numel(), int(validate), ctypes.byref(self.desc),
                                       _stream(sites.device)))
@@ -443,3 +447,79 @@ def render(sites, density, sh, off, idx, origin, direction, t_max, start, sh_deg
     out = RadFoamRender.apply(sites, density, sh, off, idx, origin, direction, t_max, start, sh_degree,
                               attr_dtype, eps, max_steps, log_capacity, quantile_draws, surface)
     return out if quantile_draws is not None else out[:3]
+
+
+# ---------------------------------------------------------------------------
+# Training-step pieces (Sec. 3.3-3.4): schedule, Adam, densification, pruning.
+# ---------------------------------------------------------------------------
+
+def train_schedule(iteration: int, total: int) -> L.AdamArgs:
+    """Adam settings of 0-based ``iteration`` of a ``total``-iteration run (the paper's schedule)."""
+    a = L.AdamArgs()
+    L.check(L.lib().rf_train_schedule(int(iteration), int(total), ctypes.byref(a)))
+    return a
+
+
+class AdamState:
+    """First and second moments of the positions, density and SH (zeros at the start)."""
+
+    def __init__(self, n_sites: int, sh_degree: int, device=None):
+        B = sh_count(sh_degree)
+        self.tensors = {k: torch.zeros(shape, dtype=torch.float32, device=device) for k, shape in
+                        (("m_sites", (n_sites, 3)), ("v_sites", (n_sites, 3)), ("m_density", (n_sites,)),
+                         ("v_density", (n_sites,)), ("m_sh", (n_sites, B, 3)), ("v_sh", (n_sites, B, 3)))}
+        self.desc = L.AdamState(*[_ptr(self.tensors[k]) for k in ("m_sites", "v_sites", "m_density", "v_density",
+                                                                   "m_sh", "v_sh")])
+
+
+def adam_step(args: L.AdamArgs, state: AdamState, sites, density, sh, grad_sites, grad_density, grad_sh) -> None:
+    """One Adam step of the three parameter tensors, in place (see ``rf_adam_step``)."""
+    n = int(sites.shape[0])
+    B = int(sh.shape[1])
+    for t, shape, name in ((sites, (n, 3), "sites"), (density, (n,), "density"), (sh, (n, B, 3), "sh"),
+                           (grad_sites, (n, 3), "grad_sites"), (grad_density, (n,), "grad_density"),
+                           (grad_sh, (n, B, 3), "grad_sh")):
+        _dev(t, torch.float32, shape, name)
+    deg = int(round(B ** 0.5)) - 1
+    L.check(L.lib().rf_adam_step(n, deg, ctypes.byref(args), sites.data_ptr(), density.data_ptr(), sh.data_ptr(),
+                                 grad_sites.data_ptr(), grad_density.data_ptr(), grad_sh.data_ptr(),
+                                 ctypes.byref(state.desc), _stream(sites.device)))
+
+
+def densify_scores(sites, off, idx, grad_sites) -> torch.Tensor:
+    """|dL/dx_i| times the cell's approximate radius, per cell."""
+    n = int(sites.shape[0])
+    _dev(sites, torch.float32, (n, 3), "sites")
+    _dev(off, torch.int32, (n + 1,), "off")
+    _dev(idx, torch.int32, (int(idx.shape[0]),), "idx")
+    _dev(grad_sites, torch.float32, (n, 3), "grad_sites")
+    out = torch.empty(n, dtype=torch.float32, device=sites.device)
+    L.check(L.lib().rf_densify_scores(sites.data_ptr(), off.data_ptr(), _ptr(idx) if idx.numel() else None, n,
+                                      grad_sites.data_ptr(), out.data_ptr(), _stream(sites.device)))
+    return out
+
+
+def sample_cells(scores, draws) -> torch.Tensor:
+    """Multinomial candidates proportional to ``scores`` at uniform ``draws`` in [0, 1) (int32)."""
+    n, k = int(scores.shape[0]), int(draws.shape[0])
+    _dev(scores, torch.float32, (n,), "scores")
+    _dev(draws, torch.float32, (k,), "draws")
+    nbytes = ctypes.c_size_t()
+    L.check(L.lib().rf_sample_workspace(n, ctypes.byref(nbytes)))
+    ws = torch.empty(max(int(nbytes.value) // 8, 1), dtype=torch.float64, device=scores.device)
+    out = torch.empty(k, dtype=torch.int32, device=scores.device)
+    L.check(L.lib().rf_sample_cells(scores.data_ptr(), n, draws.data_ptr(), k, out.data_ptr(), ws.data_ptr(),
+                                    ws.numel() * 8, _stream(scores.device)))
+    return out
+
+
+def prune_mask(density, off, idx, threshold: float) -> torch.Tensor:
+    """True where the cell's density (sigma) and all its neighbours' are below ``threshold``."""
+    n = int(density.shape[0])
+    _dev(density, torch.float32, (n,), "density")
+    _dev(off, torch.int32, (n + 1,), "off")
+    _dev(idx, torch.int32, (int(idx.shape[0]),), "idx")
+    out = torch.empty(n, dtype=torch.uint8, device=density.device)
+    L.check(L.lib().rf_prune_mask(density.data_ptr(), off.data_ptr(), _ptr(idx) if idx.numel() else None, n,
+                                  float(threshold), out.data_ptr(), _stream(density.device)))
+    return out.bool()
