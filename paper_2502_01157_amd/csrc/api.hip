@@ -576,37 +576,35 @@ rf_status rf_adam_step(int64_t n_sites, int32_t sh_degree, const rf_adam_args* a
             return fail(RF_ERR_INVALID_ARG, "group %d: lr must be >= 0, with a step count >= 1 when it moves", g);
     const int B = (sh_degree + 1) * (sh_degree + 1);
     auto corr = [](float beta, int32_t t) { return t > 0 ? (float)(1.0 / (1.0 - pow((double)beta, t))) : 1.0f; };
-    rf::AdamGroup a;
-    a.beta1 = args->beta1;
-    a.beta2 = args->beta2;
-    a.eps = args->eps;
-    a.B = B;
-    const hipStream_t s = static_cast<hipStream_t>(stream);
+    rf::AdamGroup g[3];
+    for (int q = 0; q < 3; ++q) {
+        g[q].beta1 = args->beta1;
+        g[q].beta2 = args->beta2;
+        g[q].eps = args->eps;
+        g[q].B = B;
+    }
     // positions
-    a.x = sites; a.g = grad_sites; a.m = state->m_sites; a.v = state->v_sites; a.n = 3 * n_sites; a.kind = 0;
-    a.lr[0] = a.lr[1] = args->lr[0];
-    a.c1[0] = a.c1[1] = corr(args->beta1, args->t[0]);
-    a.c2[0] = a.c2[1] = corr(args->beta2, args->t[0]);
-    hipError_t e = rf::launch_adam(a, s);
+    g[0].x = sites; g[0].g = grad_sites; g[0].m = state->m_sites; g[0].v = state->v_sites; g[0].n = 3 * n_sites;
+    g[0].kind = 0;
     // density
-    if (e == hipSuccess) {
-        a.x = density; a.g = grad_density; a.m = state->m_density; a.v = state->v_density; a.n = n_sites;
-        a.kind = args->softplus_density ? 1 : 0;
-        a.lr[0] = a.lr[1] = args->lr[1];
-        a.c1[0] = a.c1[1] = corr(args->beta1, args->t[1]);
-        a.c2[0] = a.c2[1] = corr(args->beta2, args->t[1]);
-        e = rf::launch_adam(a, s);
-    }
-    // SH: order 0 and the higher orders
-    if (e == hipSuccess) {
-        a.x = sh; a.g = grad_sh; a.m = state->m_sh; a.v = state->v_sh; a.n = 3 * (int64_t)B * n_sites; a.kind = 2;
-        for (int q = 0; q < 2; ++q) {
-            a.lr[q] = args->lr[2 + q];
-            a.c1[q] = corr(args->beta1, args->t[2 + q]);
-            a.c2[q] = corr(args->beta2, args->t[2 + q]);
+    g[1].x = density; g[1].g = grad_density; g[1].m = state->m_density; g[1].v = state->v_density;
+    g[1].n = n_sites;
+    g[1].kind = args->softplus_density ? 1 : 0;
+    for (int q = 0; q < 2; ++q)
+        for (int s2 = 0; s2 < 2; ++s2) {
+            g[q].lr[s2] = args->lr[q];
+            g[q].c1[s2] = corr(args->beta1, args->t[q]);
+            g[q].c2[s2] = corr(args->beta2, args->t[q]);
         }
-        e = rf::launch_adam(a, s);
+    // SH: order 0 and the higher orders
+    g[2].x = sh; g[2].g = grad_sh; g[2].m = state->m_sh; g[2].v = state->v_sh; g[2].n = 3 * (int64_t)B * n_sites;
+    g[2].kind = 2;
+    for (int s2 = 0; s2 < 2; ++s2) {
+        g[2].lr[s2] = args->lr[2 + s2];
+        g[2].c1[s2] = corr(args->beta1, args->t[2 + s2]);
+        g[2].c2[s2] = corr(args->beta2, args->t[2 + s2]);
     }
+    const hipError_t e = rf::launch_adam(g, static_cast<hipStream_t>(stream));
     return hip_status(e, "adam step");
 }
 

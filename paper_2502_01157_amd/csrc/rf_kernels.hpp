@@ -172,7 +172,7 @@ struct AdamGroup {
     int32_t B;
     float beta1, beta2, eps;
 };
-hipError_t launch_adam(const AdamGroup& a, hipStream_t stream);
+hipError_t launch_adam(const AdamGroup groups[3], hipStream_t stream);  // positions, density, SH
 hipError_t launch_densify_score(const float* sites, const int32_t* off, const int32_t* idx, int64_t n,
                                 const float* grad_sites, float* score, hipStream_t stream);
 hipError_t launch_prune_mask(const float* density, const int32_t* off, const int32_t* idx, int64_t n,

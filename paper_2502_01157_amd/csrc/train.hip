@@ -4,9 +4,9 @@
 // sampling of densification candidates, and the pruning mask.
 //
 // Adam is a pure stream over the parameters (read x, g, m, v; write x, m, v:
-// 28 bytes per value), so it is written for HBM: one launch per group, each
-// thread four consecutive values with 16-byte loads and stores where the
-// group's arrays are 16-byte aligned. The score and the mask read each
+// 28 bytes per value), so it is written for HBM: one launch for all groups,
+// each thread four consecutive values with non-temporal 16-byte loads and
+// stores where the group's arrays are 16-byte aligned. The score and the mask read each
 // cell's CSR row (one thread per cell). Sampling scans the scores in double
 // (per block of 1024, then the block totals, then the offsets) and inverts
 // the cumulative sum at each draw by binary search.
@@ -19,12 +19,13 @@ namespace rf {
 constexpr int kTrainBlock = 256;
 
 // ---------------------------------------------------------------------------
-// Adam.
+// Adam: one launch over the three groups (positions, density, SH); block b
+// belongs to the group whose block range holds it. Each thread streams four
+// consecutive values with non-temporal 16-byte accesses (nothing is reused
+// within the step) when the group's arrays are 16-byte aligned.
 // ---------------------------------------------------------------------------
-__device__ inline void adam_one(const AdamGroup& a, int64_t k, float& x, float g, float& m, float& v)
+__device__ inline void adam_one(const AdamGroup& a, int s, float& x, float g, float& m, float& v)
 {
-    int s = 0;
-    if (a.kind == 2) s = ((k / 3) % a.B) != 0;
     const float lr = a.lr[s];
     if (lr == 0.0f) return;  // a held group keeps its values and moments
     if (a.kind == 1) {
@@ -36,47 +37,83 @@ __device__ inline void adam_one(const AdamGroup& a, int64_t k, float& x, float g
     x = x - lr * (m * a.c1[s]) / (sqrtf(v * a.c2[s]) + a.eps);
 }
 
-template <bool VEC>
-__global__ __launch_bounds__(kTrainBlock) void k_adam(AdamGroup a)
+__device__ inline float4 ld_nt(const float* p, int64_t i)
 {
-    const int64_t t = (int64_t)blockIdx.x * kTrainBlock + threadIdx.x;
+    const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p) + i);
+    return make_float4(v[0], v[1], v[2], v[3]);
+}
+
+__device__ inline void st_nt(float* p, int64_t i, float4 v)
+{
+    __builtin_nontemporal_store(f32x4{v.x, v.y, v.z, v.w}, reinterpret_cast<f32x4*>(p) + i);
+}
+
+struct AdamLaunch {
+    AdamGroup g[3];
+    int64_t first_block[3];  // first block of each group
+    int32_t vec[3];          // the group's arrays are 16-byte aligned
+};
+
+__global__ __launch_bounds__(kTrainBlock) void k_adam(AdamLaunch L)
+{
+    const int gi = blockIdx.x >= L.first_block[2] ? 2 : (blockIdx.x >= L.first_block[1] ? 1 : 0);
+    const AdamGroup& a = L.g[gi];
+    const int64_t t = ((int64_t)blockIdx.x - L.first_block[gi]) * kTrainBlock + threadIdx.x;
     const int64_t k0 = 4 * t;
     if (k0 >= a.n) return;
-    if (VEC && k0 + 4 <= a.n) {
-        float4 x = reinterpret_cast<const float4*>(a.x)[t];
-        const float4 g = reinterpret_cast<const float4*>(a.g)[t];
-        float4 m = reinterpret_cast<const float4*>(a.m)[t];
-        float4 v = reinterpret_cast<const float4*>(a.v)[t];
-        adam_one(a, k0 + 0, x.x, g.x, m.x, v.x);
-        adam_one(a, k0 + 1, x.y, g.y, m.y, v.y);
-        adam_one(a, k0 + 2, x.z, g.z, m.z, v.z);
-        adam_one(a, k0 + 3, x.w, g.w, m.w, v.w);
-        reinterpret_cast<float4*>(a.x)[t] = x;
-        reinterpret_cast<float4*>(a.m)[t] = m;
-        reinterpret_cast<float4*>(a.v)[t] = v;
+    // SH values pick their order's parameters by basis index b = (k / 3) mod B,
+    // stepped along the thread's four values (32-bit: n < 2^32)
+    int sel[4] = {0, 0, 0, 0};
+    if (a.kind == 2) {
+        const uint32_t q = (uint32_t)k0 / 3u;
+        uint32_t r3 = (uint32_t)k0 - 3u * q, b = q % (uint32_t)a.B;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            sel[u] = b != 0;
+            if (++r3 == 3u) {
+                r3 = 0;
+                if (++b == (uint32_t)a.B) b = 0;
+            }
+        }
+    }
+    if (L.vec[gi] && k0 + 4 <= a.n) {
+        float4 x = ld_nt(a.x, t), m = ld_nt(a.m, t), v = ld_nt(a.v, t);
+        const float4 g = ld_nt(a.g, t);
+        adam_one(a, sel[0], x.x, g.x, m.x, v.x);
+        adam_one(a, sel[1], x.y, g.y, m.y, v.y);
+        adam_one(a, sel[2], x.z, g.z, m.z, v.z);
+        adam_one(a, sel[3], x.w, g.w, m.w, v.w);
+        st_nt(a.x, t, x);
+        st_nt(a.m, t, m);
+        st_nt(a.v, t, v);
         return;
     }
-    for (int64_t k = k0; k < k0 + 4 && k < a.n; ++k) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t k = k0 + u;
+        if (k >= a.n) break;
         float x = a.x[k], m = a.m[k], v = a.v[k];
-        adam_one(a, k, x, a.g[k], m, v);
+        adam_one(a, sel[u], x, a.g[k], m, v);
         a.x[k] = x;
         a.m[k] = m;
         a.v[k] = v;
     }
 }
 
-hipError_t launch_adam(const AdamGroup& a, hipStream_t stream)
+hipError_t launch_adam(const AdamGroup groups[3], hipStream_t stream)
 {
-    const int64_t threads = (a.n + 3) / 4;
-    const int64_t blocks = (threads + kTrainBlock - 1) / kTrainBlock;
+    AdamLaunch L;
+    int64_t blocks = 0;
+    for (int q = 0; q < 3; ++q) {
+        L.g[q] = groups[q];
+        L.first_block[q] = blocks;
+        blocks += ((groups[q].n + 3) / 4 + kTrainBlock - 1) / kTrainBlock;
+        L.vec[q] = ((reinterpret_cast<uintptr_t>(groups[q].x) | reinterpret_cast<uintptr_t>(groups[q].g) |
+                     reinterpret_cast<uintptr_t>(groups[q].m) | reinterpret_cast<uintptr_t>(groups[q].v)) & 15) == 0;
+    }
     if (blocks == 0) return hipSuccess;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    const bool vec = ((reinterpret_cast<uintptr_t>(a.x) | reinterpret_cast<uintptr_t>(a.g) |
-                       reinterpret_cast<uintptr_t>(a.m) | reinterpret_cast<uintptr_t>(a.v)) & 15) == 0;
-    if (vec)
-        hipLaunchKernelGGL(k_adam<true>, dim3((unsigned)blocks), dim3(kTrainBlock), 0, stream, a);
-    else
-        hipLaunchKernelGGL(k_adam<false>, dim3((unsigned)blocks), dim3(kTrainBlock), 0, stream, a);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(kTrainBlock), 0, stream, L);
     return hipGetLastError();
 }
 
