@@ -148,13 +148,22 @@ __device__ inline float face_den(const float* xi, const float* xj, float dx, flo
 // 16-byte chunk per lane), and every lane then reads its own cell's copy.
 // Cells that do not fit the region are read from global memory as before.
 // ---------------------------------------------------------------------------
+// Each wavefront's region is 10 KiB, so that four blocks of four wavefronts
+// fill the 160 KiB of LDS (four wavefronts per SIMD, what the registers
+// allow). The split between face and record slots is chosen on traces of
+// the clustered 1M-site frame, where a wavefront step touches 9.5 distinct
+// cells on average (p90: 17): FP32 (256-byte records at degree 3) 320 faces
+// and 20 records leave 6.7 % of the steps with a lane that does not fit
+// (352 + 16: 13 %); BF16 (128-byte records) 448 and 24 leave 0.9 %.
 template <int DEG, bool BF16>
 struct StageLayout {
     using R = Rec<DEG, BF16>;
-    static constexpr int kFaces = 352;                 // face slots (16 B each)
-    static constexpr int kRecs = 16;                   // record slots
+    static constexpr int kBudget = 10240;
+    static constexpr int kRecs = BF16 ? 24 : 20;                       // record slots
+    static constexpr int kFaces = (kBudget - kRecs * R::BYTES) / 16 / 4 * 4;  // face slots (16 B each)
     static constexpr int kRecOff = kFaces * 16;
     static constexpr int kBytes = kRecOff + kRecs * R::BYTES;
+    static_assert(kBytes <= kBudget, "stage region over budget");
 };
 
 // Called with every lane of the wavefront active. Lanes with `want` stage the
