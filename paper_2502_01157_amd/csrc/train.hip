@@ -8,7 +8,7 @@
 // each thread four consecutive values with non-temporal 16-byte loads and
 // stores where the group's arrays are 16-byte aligned. The score and the mask read each
 // cell's CSR row (one thread per cell). Sampling scans the scores in double
-// (per block of 1024, then the block totals, then the offsets) and inverts
+// (per block of 1024, then the block totals in one block, then the offsets) and inverts
 // the cumulative sum at each draw by binary search.
 
 #include "rf_device.hpp"
@@ -215,12 +215,28 @@ __global__ __launch_bounds__(kTrainBlock) void k_scan_tiles(const float* __restr
     if (threadIdx.x == kTrainBlock - 1) totals[blockIdx.x] = before + run;
 }
 
-// Exclusive prefix of the tile totals, in place (one thread: a few thousand tiles).
-__global__ void k_scan_totals(double* totals, int64_t n_tiles)
+// Exclusive prefix of the tile totals, in place, by one block: each thread
+// sums a contiguous run of totals, the block scans the runs' sums, and each
+// thread rewrites its run with the offsets.
+__global__ __launch_bounds__(kTrainBlock) void k_scan_totals(double* totals, int64_t n_tiles)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double acc = 0.0;
-    for (int64_t b = 0; b < n_tiles; ++b) {
+    __shared__ double wave_sum[kTrainBlock / kWave];
+    const int64_t per = (n_tiles + kTrainBlock - 1) / kTrainBlock;
+    const int64_t beg = (int64_t)threadIdx.x * per;
+    const int64_t end = beg + per < n_tiles ? beg + per : n_tiles;
+    double run = 0.0;
+    for (int64_t b = beg; b < end; ++b) run += totals[b];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    double incl = run;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const double o = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += o;
+    }
+    if (lane == kWave - 1) wave_sum[w] = incl;
+    __syncthreads();
+    double acc = incl - run;
+    for (int q = 0; q < w; ++q) acc += wave_sum[q];
+    for (int64_t b = beg; b < end; ++b) {
         const double t = totals[b];
         totals[b] = acc;
         acc += t;
@@ -268,7 +284,7 @@ hipError_t launch_sample(const float* score, int64_t n, const float* draws, int6
     const int64_t tiles = (n + kScanTile - 1) / kScanTile;
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(kTrainBlock), 0, stream, score, n, cdf, totals);
-    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kWave), 0, stream, totals, tiles);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kTrainBlock), 0, stream, totals, tiles);
     hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + kTrainBlock - 1) / kTrainBlock)), dim3(kTrainBlock), 0,
                        stream, cdf, n, totals);
     hipLaunchKernelGGL(k_sample, dim3((unsigned)((n_draws + kTrainBlock - 1) / kTrainBlock)), dim3(kTrainBlock), 0,
