@@ -155,7 +155,7 @@ def main() -> int:
     ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for k in ("raygen", "pack", "forward", "backward")}
 
-    def step(dt: str, backward: bool, timed: dict = None):
+    def step(dt: str, backward: bool, timed: dict = None, use_log: bool = True):
         def mark(k, i):
             if timed is not None:
                 ev[k][i].record()
@@ -168,7 +168,7 @@ def main() -> int:
         mark("pack", 1)
         mark("forward", 0)
         # a training step's forward keeps the walk log for its backward
-        log = walk_log if backward else None
+        log = walk_log if backward and use_log else None
         rgb, tf, steps = rf.render_forward(scenes[dt], o, d, t, s, out=fwd_out, log=log)
         mark("forward", 1)
         if backward:
@@ -185,21 +185,21 @@ def main() -> int:
                     continue
                 timed.setdefault(k, []).append(ev[k][0].elapsed_time(ev[k][1]))
 
-    def run(dt: str, backward: bool):
+    def run(dt: str, backward: bool, use_log: bool = True):
         for _ in range(args.warmup):
-            step(dt, backward)
+            step(dt, backward, use_log=use_log)
         torch.cuda.synchronize()
         # whole-job throughput: K steps bracketed by synchronisation
         t_start = time.perf_counter()
         for _ in range(args.steps):
-            step(dt, backward)
+            step(dt, backward, use_log=use_log)
         torch.cuda.synchronize()
         total = time.perf_counter() - t_start
         # per-kernel and per-step latency: the same steps again with events
         timed, lat = {}, []
         for _ in range(args.steps):
             a = time.perf_counter()
-            step(dt, backward, timed)
+            step(dt, backward, timed, use_log=use_log)
             lat.append((time.perf_counter() - a) * 1e3)
         return total / args.steps * 1e3, {k: float(np.mean(v)) for k, v in timed.items()}, lat
 
@@ -237,6 +237,15 @@ def main() -> int:
             log(f"{dt} {'fwd+bwd' if bwd else 'fwd'}: {ms:.3f} ms/step, {R / ms / 1e3:.1f} Mrays/s, "
                 f"kernels(ms) {json.dumps({k: round(v, 4) for k, v in kern.items()})}")
 
+    recompute = None
+    if walk_log is not None:
+        # the same training step with the backward recomputing every walk (no walk log)
+        ms_r, kern_r, _ = run("f32" if args.only is None else args.only, True, use_log=False)
+        recompute = {"mrays_s": round(R / ms_r / 1e3, 3), "ms_per_step": round(ms_r, 4),
+                     "backward_ms": round(kern_r["backward"], 4)}
+        log(f"fwd+bwd with the recomputing backward: {ms_r:.3f} ms/step, {R / ms_r / 1e3:.1f} Mrays/s, "
+            f"backward {kern_r['backward']:.3f} ms")
+
     main_dt = "f32" if args.only is None else args.only
     dts = [k[0] for k in results if k[1]]
     ms, kern, lat = results[(main_dt, True)]
@@ -268,6 +277,7 @@ def main() -> int:
                    "parallelism": "single GPU"},
         "fwd_mrays_s": {dt: round(R / results[(dt, False)][0] / 1e3, 3) for dt in dts},
         "fwd_bwd_mrays_s": {dt: round(R / results[(dt, True)][0] / 1e3, 3) for dt in dts},
+        "fwd_bwd_recompute": recompute,
         "bf16_speedup_fwd_bwd": (round(results[("f32", True)][0] / results[("bf16", True)][0], 4)
                                  if len(dts) == 2 else None),
         "step_latency_ms": {f"{dt}_{'fwd_bwd' if b else 'fwd'}": {

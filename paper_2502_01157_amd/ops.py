@@ -475,7 +475,9 @@ class AdamState:
 def adam_step(args: L.AdamArgs, state: AdamState, sites, density, sh, grad_sites, grad_density, grad_sh) -> None:
     """One Adam step of the three parameter tensors, in place (see ``rf_adam_step``)."""
     n = int(sites.shape[0])
-    B = int(sh.shape[1])
+    B = int(sh.shape[1]) if sh.dim() == 3 else -1
+    if B not in (1, 4, 9, 16):
+        raise ValueError("sh must be [n, B, 3] with B = (degree + 1)^2, degree 0..3")
     for t, shape, name in ((sites, (n, 3), "sites"), (density, (n,), "density"), (sh, (n, B, 3), "sh"),
                            (grad_sites, (n, 3), "grad_sites"), (grad_density, (n,), "grad_density"),
                            (grad_sh, (n, B, 3), "grad_sh")):

@@ -119,7 +119,8 @@ def replay(server: Server, requests: Sequence[dict], keep: Sequence[int] = (), t
         while queue:
             i = queue[0]
             r = requests[i]
-            rid = server.submit(r["pose12"], r["fov_deg"], r["width"], r["height"], r["start_cell"])
+            rid = server.submit(r["pose12"], r["fov_deg"], r["width"], r["height"], r["start_cell"],
+                                r.get("model", "pinhole"))
             if rid is None:
                 break
             queue.popleft()

@@ -147,3 +147,33 @@ def test_device_located_start_cells(setup):
         out = replay(srv, located, keep=range(len(reqs)), timeout_s=20)
     for i in range(len(reqs)):
         np.testing.assert_array_equal(out["images"][i], alone[i], err_msg=f"request {i}")
+
+
+def test_fisheye_requests_in_the_mix(setup):
+    """Fisheye requests (180 and 360 degrees) served among pinhole ones give the
+    batch path's images (fisheye raygen + forward walk) bit for bit."""
+    import torch
+
+    rf, scene, packed, reqs, alone = setup
+    from paper_2502_01157_amd.serve import Server, replay
+
+    mixed, ref = [], []
+    for k, r in enumerate(reqs[:12]):
+        if k % 3 == 0:
+            r = dict(r, model="fisheye", fov_deg=180.0 if k % 2 == 0 else 360.0)
+            o, d, t, s, px = rf.raygen(r["pose12"], r["fov_deg"], r["width"], r["height"], scene.bound,
+                                       r["start_cell"], model="fisheye")
+            rgb, tf, _ = rf.render_forward(packed, o, d, t, s)
+            img = np.zeros((r["height"] * r["width"], 4), dtype=np.float32)
+            img[px.cpu().numpy()] = np.concatenate([rgb.cpu().numpy(), tf.cpu().numpy()[:, None]], 1)
+            ref.append(img.reshape(r["height"], r["width"], 4))
+        else:
+            ref.append(alone[k])
+        mixed.append(dict(r, arrival=0.0))
+    torch.cuda.synchronize()
+    with Server(packed, scene.bound, pool_bytes=8 << 20, max_inflight=16) as srv:
+        out = replay(srv, mixed, keep=range(len(mixed)), timeout_s=20)
+        with pytest.raises(rf.RfError):
+            srv.submit(reqs[0]["pose12"], 400.0, 8, 8, 0, model="fisheye")
+    for i in range(len(mixed)):
+        np.testing.assert_array_equal(out["images"][i], ref[i], err_msg=f"request {i}")
