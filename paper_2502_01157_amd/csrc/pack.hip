@@ -123,13 +123,31 @@ __global__ __launch_bounds__(256) void k_pack_faces(PackArgs a)
         lo_e = min(lo_e, __shfl_xor(lo_e, m));
         hi_e = max(hi_e, __shfl_xor(hi_e, m));
     }
+    // row starts for the owner search: lanes past the last cell sort last
+    const int key = mine < a.n_sites ? beg : INT_MAX;
     for (int64_t base = lo_e; base < hi_e; base += kWave) {
         const int64_t k = base + lane;
-        // owner: the lane q whose row [beg_q, beg_q + deg_q) contains k
-        int owner = -1;
-        for (int q = 0; q < kWave; ++q) {
-            const int bq = __shfl(beg, q), dq = __shfl(deg, q);
-            if (k >= bq && k < bq + dq) owner = q;
+        // owner: the lane q whose row [beg_q, beg_q + deg_q) contains k. In a
+        // valid CSR the row starts rise with q, so it is the last q with
+        // beg_q <= k (binary search over the wavefront's registers); where
+        // that row does not contain k (a corrupted CSR), a scan of all 64 rows
+        // keeps every edge of every row owned, as the walk needs.
+        int q = 0;
+#pragma unroll
+        for (int step = kWave / 2; step >= 1; step >>= 1) {
+            const int cand = q + step;
+            if (__shfl(key, cand) <= k) q = cand;
+        }
+        const int bq = __shfl(beg, q), dq = __shfl(deg, q);
+        int owner = (k >= bq && k < bq + dq) ? q : -1;
+        if (__ballot(k < hi_e && owner < 0)) {
+            // (wavefront-uniform, so every lane takes part in the shuffles)
+            int scan = -1;
+            for (int r = 0; r < kWave; ++r) {
+                const int br = __shfl(beg, r), dr = __shfl(deg, r);
+                if (k >= br && k < br + dr) scan = r;
+            }
+            if (owner < 0) owner = scan;
         }
         if (k >= hi_e || owner < 0) continue;
         const int64_t i = c0 + owner;
