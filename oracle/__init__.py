@@ -39,7 +39,7 @@ def build(force: bool = True) -> str:
 class _Surface(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("max_bounces", ctypes.c_int32), ("centre", ctypes.c_double * 3),
                 ("radius", ctypes.c_double), ("ior", ctypes.c_double), ("bound_kind", ctypes.c_int32),
-                ("bound", ctypes.c_double * 6)]
+                ("bound", ctypes.c_double * 6), ("fp32_legs", ctypes.c_int32)]
 
 
 class _Scene(ctypes.Structure):
@@ -54,14 +54,18 @@ SURFACE_KINDS = {"none": 0, "mirror": 1, "glass": 2}
 class Surface:
     """An analytic sphere in the scene that bends rays (mirror, or glass of
     refractive index ``ior`` inside); legs after a crossing end at ``bound``
-    (the raygen bound); crossings after the first ``max_bounces`` are ignored."""
+    (the raygen bound); crossings after the first ``max_bounces`` are ignored.
+    ``fp32_legs`` rounds each new leg's origin and direction to FP32, as the
+    GPU library's interface defines its legs (every leg is then a ray with FP32
+    origin and direction, like the caller's); by default legs are exact."""
 
-    def __init__(self, kind: str, centre, radius: float, bound: tuple, ior: float = 1.5, max_bounces: int = 8):
+    def __init__(self, kind: str, centre, radius: float, bound: tuple, ior: float = 1.5, max_bounces: int = 8,
+                 fp32_legs: bool = False):
         self.kind, self.centre, self.radius, self.ior = kind, tuple(float(c) for c in centre), float(radius), float(ior)
         self.bound, self.max_bounces = bound, int(max_bounces)
         bk, bp = encode_bound(bound)
         self._c = _Surface(SURFACE_KINDS[kind], self.max_bounces, (ctypes.c_double * 3)(*self.centre), self.radius,
-                           self.ior, bk, (ctypes.c_double * 6)(*bp))
+                           self.ior, bk, (ctypes.c_double * 6)(*bp), int(bool(fp32_legs)))
 
 
 _lib = None
@@ -87,7 +91,7 @@ def _load():
         lib.orc_forward.argtypes = [ctypes.POINTER(_Scene), P, P, P, P, ctypes.c_int64, ctypes.c_double,
                                     ctypes.c_int32, ctypes.c_int, P, P, P]
         lib.orc_trace.argtypes = [ctypes.POINTER(_Scene), P, P, P, P, ctypes.c_int64, ctypes.c_double,
-                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int, P, P, P, P, P, P, P, P, P, P, P, P]
+                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int, P, P, P, P, P, P, P, P, P, P, P, P, P]
         lib.orc_backward.argtypes = [ctypes.POINTER(_Scene), P, P, P, P, ctypes.c_int64, ctypes.c_double,
                                      ctypes.c_int32, P, P, ctypes.c_int, P, P, P]
         _lib = lib
@@ -253,20 +257,21 @@ def trace(scene: OracleScene, o, d, tmax, start, eps: float = DEFAULT_EPS,
           max_steps: int = DEFAULT_MAX_STEPS, max_len: int = 1024, threads: Optional[int] = None,
           legs: bool = False) -> dict:
     """Forward plus per-visit cells, exit distances (along each visit's leg), decision margins,
-    per-visit surface crossings (``bounce``) and the surface decisions' margin (``surf_margin``);
+    per-visit surface crossings (``bounce``), the surface decisions' margin (``surf_margin``) and the
+    smallest |cos| of an exit face whose exit moves (``exit_cos``);
     with ``legs`` also each visit's leg origin and direction [R, max_len, 6]."""
     o, d, t, s, R = _rays(o, d, tmax, start)
     out = dict(rgb=np.empty((R, 3)), t_final=np.empty(R), steps=np.empty(R, dtype=np.int32),
                cells=np.full((R, max_len), -1, dtype=np.int32), t_exit=np.full((R, max_len), np.nan),
                len=np.empty(R, dtype=np.int32), margin=np.empty(R), graze=np.empty(R), term=np.empty(R),
-               bounce=np.zeros((R, max_len), dtype=np.int8), surf_margin=np.empty(R))
+               bounce=np.zeros((R, max_len), dtype=np.int8), surf_margin=np.empty(R), exit_cos=np.empty(R))
     if legs:
         out["legs"] = np.full((R, max_len, 6), np.nan)
     _check(_load().orc_trace(ctypes.byref(scene._c), _ptr(o), _ptr(d), _ptr(t), _ptr(s), R, float(eps),
                              int(max_steps), int(max_len), threads or default_threads(),
                              *[_ptr(out.get(k)) for k in ("rgb", "t_final", "steps", "cells", "t_exit", "len",
                                                           "margin", "graze", "term", "bounce", "legs",
-                                                          "surf_margin")]), "trace")
+                                                          "surf_margin", "exit_cos")]), "trace")
     return out
 
 

@@ -73,6 +73,9 @@ typedef struct {
     double ior;          /* glass: refractive index inside the sphere (outside: 1) */
     int32_t bound_kind;  /* where the legs after a crossing end (see exit_distance) */
     double bound[6];
+    int32_t fp32_legs;   /* 1: each new leg's origin and direction are rounded to FP32
+                            (a leg is then a ray like the caller's, whose origin and
+                            direction are FP32); 0: exact FP64 legs */
 } orc_surface;
 
 typedef struct {
@@ -321,6 +324,8 @@ typedef struct {
     double term;     /* min |ln T - ln eps| over the transmittance tests */
     double surf;     /* min over surface decisions: |cos| at a crossing, |1 - eta^2 sin^2| at a
                         refraction, the scaled gap between the crossing and the nearest face / t_max */
+    double exit_cos; /* min |cos| of the exit faces whose exits move (the conditioning of the
+                        site gradient, which divides by the exit face's n.d) */
 } margins_t;
 
 static void push_visit(visit_buf *b, const visit_t *v)
@@ -403,6 +408,7 @@ static int32_t walk_ray(const orc_scene *s, const double o[3], const double d[3]
         mg->graze = INFINITY;
         mg->term = INFINITY;
         mg->surf = INFINITY;
+        mg->exit_cos = INFINITY;
     }
     if (start < 0 || start >= s->n_sites) return ORC_BAD_START;
 
@@ -497,6 +503,7 @@ static int32_t walk_ray(const orc_scene *s, const double o[3], const double d[3]
                 mg->margin = fmin(mg->margin, m);
             }
             mg->margin = fmin(mg->margin, fabs(t1 - tmax) * cos1 / scale);
+            if (!clipped && t1 >= t0) mg->exit_cos = fmin(mg->exit_cos, cos1);
         }
         if (rec) {
             visit_t v;
@@ -530,8 +537,8 @@ static int32_t walk_ray(const orc_scene *s, const double o[3], const double d[3]
             inside = surface_turn(sf, p, ld, inside, dn, &ci, &root);
             if (mg) mg->surf = fmin(mg->surf, fmin(ci, root));
             for (int a = 0; a < 3; ++a) {
-                lo[a] = p[a];
-                ld[a] = dn[a];
+                lo[a] = sf->fp32_legs ? (double)(float)p[a] : p[a];
+                ld[a] = sf->fp32_legs ? (double)(float)dn[a] : dn[a];
             }
             sh_basis(s->sh_deg, ld, Y);
             tmax = exit_distance(sf->bound_kind, sf->bound, lo, ld);
@@ -636,6 +643,7 @@ typedef struct {
     int8_t *bounce;   /* [R][max_len], nullable */
     double *legs;     /* [R][max_len][6]: each visit's leg origin and direction, nullable */
     double *surf_margin;
+    double *exit_cos;
     /* backward */
     const double *grad_rgb, *grad_t;
     double *gsites, *gdens, *gsh;
@@ -691,6 +699,7 @@ static void *forward_worker(void *arg)
             j->graze[r] = mg.graze;
             j->term[r] = mg.term;
             if (j->surf_margin) j->surf_margin[r] = mg.surf;
+            if (j->exit_cos) j->exit_cos[r] = mg.exit_cos;
         }
     }
     free(buf.v);
@@ -878,11 +887,11 @@ int orc_forward(const orc_scene *s, const double *o, const double *d, const doub
     return run_jobs(&j, n_rays, nthreads, forward_worker, 0);
 }
 
-/* bounce, legs and surf_margin are optional (NULL) outputs. */
+/* bounce, legs, surf_margin and exit_cos are optional (NULL) outputs. */
 int orc_trace(const orc_scene *s, const double *o, const double *d, const double *tmax, const int32_t *start,
               int64_t n_rays, double eps, int32_t max_steps, int32_t max_len, int nthreads, double *rgb,
               double *t_final, int32_t *steps, int32_t *cells, double *t_exit, int32_t *len, double *margin,
-              double *graze, double *term, int8_t *bounce, double *legs, double *surf_margin)
+              double *graze, double *term, int8_t *bounce, double *legs, double *surf_margin, double *exit_cos)
 {
     if (check_inputs(s, d, n_rays) != ORC_OK || max_steps < 1 || max_len < 1) return ORC_EINVAL;
     job_t j;
@@ -907,6 +916,7 @@ int orc_trace(const orc_scene *s, const double *o, const double *d, const double
     j.bounce = bounce;
     j.legs = legs;
     j.surf_margin = surf_margin;
+    j.exit_cos = exit_cos;
     return run_jobs(&j, n_rays, nthreads, forward_worker, 0);
 }
 

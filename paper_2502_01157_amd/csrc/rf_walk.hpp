@@ -129,12 +129,17 @@ __device__ inline void visit_cell(const SceneView& s, uint2 ref, double t0, floa
     segment<DEG>(t0, Y, v);
 }
 
-// n.d of the face between cells with sites xi and xj, n = xj - xi: the same
-// rounding as the packed plane's normal and the scan's dot product.
-__device__ inline float face_den(const float* xi, const float* xj, float dx, float dy, float dz)
+// n.d of the face between cells with sites xi and xj, n = xj - xi, for the
+// exit-distance derivative dt/dx = (p - x)/(n.d) of the backward. Formed in
+// double: the difference of two FP32 sites is exact there, so n.d keeps full
+// precision even for a nearly grazing exit face, where an FP32 dot product
+// would lose a relative ~2^-24/cos to cancellation (and that face's site
+// gradient is the largest of the ray's).
+__device__ inline double face_den(const float* xi, const float* xj, float dx, float dy, float dz)
 {
-    const float nx = xj[0] - xi[0], ny = xj[1] - xi[1], nz = xj[2] - xi[2];
-    return fmaf(nz, dz, fmaf(ny, dy, nx * dx));
+    const double nx = (double)xj[0] - (double)xi[0], ny = (double)xj[1] - (double)xi[1],
+                 nz = (double)xj[2] - (double)xi[2];
+    return fma(nz, (double)dz, fma(ny, (double)dy, nx * (double)dx));
 }
 
 // ---------------------------------------------------------------------------

@@ -32,8 +32,8 @@
 // step-major walk log; the backward then reads the visits instead of
 // repeating the face scans (same records, same te, so the same segments bit
 // for bit), and a second launch recomputes only the walks that outgrew the
-// log. The exit face's n.d is rebuilt from the two sites with the pack's
-// rounding, so both paths use the same value.
+// log. The exit face's n.d is rebuilt from the two sites (in double), so both
+// paths use the same value.
 // Each visit's gradients for one cell (3B SH values, density, site) form a
 // package that is emitted one iteration later, when the following visit has
 // fixed the exit gradient. Packages are summed across the wavefront per cell
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
                     if (p_moves) {
                         // exit point relative to both sites, in double: p - x = (o - x) + t d
                         const float gt = p_sdt - sdt + gt_q;
-                        const float s = gt / face_den(p_site, at.site, dx, dy, dz);
+                        const float s = (float)((double)gt / face_den(p_site, at.site, dx, dy, dz));
                         float pa[3], pb[3];
                         exit_offsets(p_t1, ox, oy, oz, dx, dy, dz, p_site, at.site, pa, pb);
                         prev.dx[0] = fmaf(s, pa[0], prev.dx[0]);
@@ -536,7 +536,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
                     // cannot address outside the scene)
                     entry.cell = min(ref_cell(ref), (int)(a.s.n_sites - 1));
                     load_site<DEG, BF16>(a.s.rec, entry.cell, xj);
-                    const float s = p_sdt / face_den(p_site, xj, dx, dy, dz);
+                    const float s = (float)((double)p_sdt / face_den(p_site, xj, dx, dy, dz));
                     exit_offsets(p_t1, ox, oy, oz, dx, dy, dz, p_site, xj, pa, pb);
                     prev.dx[0] = fmaf(s, pa[0], prev.dx[0]);
                     prev.dx[1] = fmaf(s, pa[1], prev.dx[1]);

@@ -1,12 +1,16 @@
 """Ray-based effects on the GPU (Fig. 3) against the FP64 oracle: secondary
 rays at a mirror or glass sphere, and the equidistant fisheye camera.
 
-Tolerances are those of the plain walk, with stricter decidability: after a
-crossing the GPU's leg starts from the crossing point and direction rounded
-to FP32 (the oracle keeps them in FP64), an extra relative error of ~eps32
-per leg, so rays are compared where the face decisions clear 10 KAPPA_T and
-the surface decisions (grazing crossings, near-critical refraction, a
-crossing next to a face) clear 1e-4.
+The library defines each leg after a crossing as a ray with FP32 origin and
+direction (the crossing point and the new direction, computed in double,
+rounded), like the caller's rays; the oracle is run with the same rounding
+(fp32_legs), so every leg is the same FP32 ray on both sides and the plain
+walk's tolerances apply. (Against exact FP64 legs the GPU's later exit
+distances would carry an error of ~2^-24 t / cos of the exit face, which
+near-grazing faces amplify past the colour tolerance on a few rays of a full
+frame.) Rays are compared where the face decisions clear KAPPA_T and the
+surface decisions (grazing crossings, near-critical refraction, a crossing
+next to a face) clear 1e-4.
 """
 
 import numpy as np
@@ -15,12 +19,13 @@ import pytest
 import oracle
 import synth
 
-from parity import COLOUR_RTOL, GRAD_RTOL, KAPPA_G, KAPPA_T, KAPPA_TERM, colour_err, grad_err
+from parity import COLOUR_RTOL, GRAD_RTOL, KAPPA_G, KAPPA_T, KAPPA_TERM, KAPPA_X, colour_err, grad_err
 
 pytestmark = pytest.mark.gpu
 
-CENTRE = (0.05, -0.1, 0.0)
-RADIUS = 0.35
+# the library takes the sphere in FP32: both sides get the same FP32 values
+CENTRE = tuple(float(np.float32(c)) for c in (0.05, -0.1, 0.0))
+RADIUS = float(np.float32(0.35))
 BOX = ("box", -1.0, 1.0)
 KAPPA_SURF = 1e-4
 EPS = 1e-4
@@ -57,8 +62,9 @@ def setup():
 
 
 def _surfaces(rf, kind, ior=1.5, max_bounces=8):
+    ior = float(np.float32(ior))
     return (rf.Surface(kind, CENTRE, RADIUS, BOX, ior=ior, max_bounces=max_bounces),
-            oracle.Surface(kind, CENTRE, RADIUS, BOX, ior=ior, max_bounces=max_bounces))
+            oracle.Surface(kind, CENTRE, RADIUS, BOX, ior=ior, max_bounces=max_bounces, fp32_legs=True))
 
 
 def _packed(rf, scene, dtype="f32", density=None):
@@ -67,7 +73,7 @@ def _packed(rf, scene, dtype="f32", density=None):
 
 
 def _decidable_bent(tr):
-    return ((tr["margin"] > 10 * KAPPA_T) & (tr["graze"] > KAPPA_G) & (tr["term"] > KAPPA_TERM)
+    return ((tr["margin"] > KAPPA_T) & (tr["graze"] > KAPPA_G) & (tr["term"] > KAPPA_TERM)
             & (tr["surf_margin"] > KAPPA_SURF))
 
 
@@ -165,7 +171,7 @@ def test_bent_backward_matches_oracle(setup, kind, cap):
     sf, osf = _surfaces(rf, kind, ior=1.45)
     osc = oracle.OracleScene.from_scene(scene, surface=osf)
     tr = oracle.trace(osc, *rays, eps=EPS, max_len=1024)
-    keep = _decidable_bent(tr)
+    keep = _decidable_bent(tr) & (tr["exit_cos"] > KAPPA_X)
     rays_k = tuple(a[keep] for a in rays)
     n = len(rays_k[2])
     rng = np.random.default_rng(73)

@@ -16,8 +16,8 @@ import pytest
 import oracle
 import synth
 
-from parity import (COLOUR_RTOL, GRAD_RTOL, T_ATOL, camera_rays, colour_err, compare_sequences, decidable,
-                    grad_err)
+from parity import (COLOUR_RTOL, GRAD_RTOL, KAPPA_X, T_ATOL, camera_rays, colour_err, compare_sequences, decidable,
+                    grad_err, gradient_decidable)
 
 pytestmark = pytest.mark.gpu
 
@@ -78,8 +78,8 @@ def test_full_frame_forward_backward(name, dtype):
     gst = tr["steps"].cpu().numpy()
     assert compare_sequences(cells, np.where(gst >= 0, gst, 0), ref, decidable(ref, 1e-4)) == 0
 
-    # full-frame gradients
-    gm = np.where(dec[:, None], g, 0.0).astype(np.float32)
+    # full-frame gradients (upstream gradients on the rays whose gradients are compared)
+    gm = np.where(gradient_decidable(full, 1e-4)[:, None], g, 0.0).astype(np.float32)
     t2 = time.time()
     ref_g = oracle.backward(osc, o, d, t, s, gm, eps=1e-4)
     print(f"oracle backward in {time.time() - t2:.1f}s", flush=True)
@@ -88,6 +88,15 @@ def test_full_frame_forward_backward(name, dtype):
     torch.cuda.synchronize()
     errs = [grad_err(x.cpu().numpy(), y) for x, y in zip(grads, ref_g)]
     print(f"gradient errors (sites, density, sh): {errs}", flush=True)
+    assert max(errs) <= GRAD_RTOL
+    # the training step as the benchmark times it: logged forward, logged backward
+    log = rf.WalkLog(R, rf.DEFAULT_LOG_CAPACITY, od.device)
+    rgb_l, tf_l, _ = rf.render_forward(p, od, dd, td, sd, log=log)
+    assert torch.equal(rgb_l, rgb_d) and torch.equal(tf_l, tf_d)
+    grads = rf.render_backward(p, od, dd, td, sd, rgb_l, tf_l, _dv(gm), log=log)
+    torch.cuda.synchronize()
+    errs = [grad_err(x.cpu().numpy(), y) for x, y in zip(grads, ref_g)]
+    print(f"gradient errors with the walk log: {errs}", flush=True)
     assert max(errs) <= GRAD_RTOL
 
 
@@ -156,7 +165,8 @@ def test_shell_3m_eight_cameras_sampled():
 
     g = np.zeros((R, 3), dtype=np.float32)
     g_sel = synth.make_upstream_grads(rng, len(sel))
-    g[sel[dec]] = g_sel[dec]
+    gdec = gradient_decidable(ref, 1e-4)
+    g[sel[gdec]] = g_sel[gdec]
     t2 = time.time()
     ref_g = oracle.backward(osc, o[sel], d[sel], t[sel], s[sel], g[sel], eps=1e-4)
     print(f"oracle backward on the sample in {time.time() - t2:.1f}s", flush=True)
@@ -165,3 +175,102 @@ def test_shell_3m_eight_cameras_sampled():
     errs = [grad_err(x.cpu().numpy(), y) for x, y in zip(grads, ref_g)]
     print(f"gradient errors (sites, density, sh): {errs}", flush=True)
     assert max(errs) <= GRAD_RTOL
+
+
+def test_bent_full_frame_glass_sphere():
+    """The clustered_1m frame with the benchmark's glass sphere (index 1.5,
+    radius 0.3 at the centre): every ray's colour against the oracle on
+    decidable rays, and the full-frame gradients of the logged backward."""
+    import torch
+
+    import paper_2502_01157_amd as rf
+
+    scene, rng = synth.make_scene("clustered_1m", return_rng=True)
+    cam = synth.make_cameras("clustered_1m", rng)[0]
+    R = cam.width * cam.height
+    g = synth.make_upstream_grads(rng, R)
+    o, d, t, s, _ = camera_rays(scene, cam)
+    bound = synth.CONFIGS["clustered_1m"]["bound"]
+    # the sphere in FP32 as the library takes it, legs rounded to FP32 as it defines them (see test_gpu_effects)
+    radius = float(np.float32(0.3))
+    osc = oracle.OracleScene.from_scene(scene, surface=oracle.Surface("glass", (0.0, 0.0, 0.0), radius, bound,
+                                                                      ior=1.5, max_bounces=8, fp32_legs=True))
+    t1 = time.time()
+    full = oracle.trace(osc, o, d, t, s, eps=1e-4, max_len=1)
+    dec = decidable(full, 1e-4) & (full["surf_margin"] > 1e-4)
+    print(f"\noracle bent frame in {time.time() - t1:.1f}s; decidable {dec.mean():.5f}", flush=True)
+    assert dec.mean() > 0.8
+    p = rf.PackedScene(*map(_dv, (scene.sites, scene.off, scene.idx, scene.density, scene.sh)), 3, "f32")
+    od, dd, td, sd = map(_dv, (o, d, t, s))
+    sf = rf.Surface("glass", (0.0, 0.0, 0.0), radius, bound, ior=1.5, max_bounces=8)
+    log = rf.WalkLog(R, rf.DEFAULT_LOG_CAPACITY, od.device)
+    rgb, tf, steps = rf.render_forward(p, od, dd, td, sd, log=log, surface=sf)
+    torch.cuda.synchronize()
+    bent = (log.tail[:, 3] > 0).cpu().numpy()
+    rgb_n, tf_n = rgb.cpu().numpy(), tf.cpu().numpy()
+    scale = np.abs(full["rgb"]).max()
+    assert np.abs(rgb_n[dec] - full["rgb"][dec]).max() <= COLOUR_RTOL * scale
+    assert np.abs(tf_n[dec] - full["t_final"][dec]).max() <= T_ATOL
+    np.testing.assert_array_equal(steps.cpu().numpy()[dec], full["steps"][dec])
+    assert bent.mean() > 0.5
+    gm = np.where((dec & (full["exit_cos"] > KAPPA_X))[:, None], g, 0.0).astype(np.float32)
+    t2 = time.time()
+    ref_g = oracle.backward(osc, o, d, t, s, gm, eps=1e-4)
+    print(f"oracle bent backward in {time.time() - t2:.1f}s", flush=True)
+    grads = rf.render_backward(p, od, dd, td, sd, rgb, tf, _dv(gm), log=log, surface=sf)
+    torch.cuda.synchronize()
+    errs = [grad_err(x.cpu().numpy(), y) for x, y in zip(grads, ref_g)]
+    print(f"bent gradient errors (sites, density, sh): {errs}", flush=True)
+    assert max(errs) <= GRAD_RTOL
+
+
+def test_training_kernels_full_size():
+    """The optimizer step, densification scores, candidate sampling and the
+    pruning mask on the 1M-site scene's full arrays, as the benchmark runs
+    them, against the oracle on every value."""
+    import torch
+
+    import paper_2502_01157_amd as rf
+    from oracle import training as otr
+
+    scene = synth.make_scene("clustered_1m")
+    n = scene.n_sites
+    rng = np.random.default_rng(91)
+    x = {"sites": scene.sites.astype(np.float32), "density": rng.normal(0, 1, n).astype(np.float32),
+         "sh": scene.sh.astype(np.float32)}
+    gr = {"sites": rng.standard_normal((n, 3)).astype(np.float32),
+          "density": rng.standard_normal(n).astype(np.float32),
+          "sh": rng.standard_normal((n, 16, 3)).astype(np.float32)}
+    gp = {k: _dv(v) for k, v in x.items()}
+    st = rf.AdamState(n, 3, gp["sites"].device)
+    it, total = 10000, 20000
+    rf.adam_step(rf.train_schedule(it, total), st, gp["sites"], gp["density"], gp["sh"], _dv(gr["sites"]),
+                 _dv(gr["density"]), _dv(gr["sh"]))
+    zeros = {k: np.zeros(v.shape) for k, v in x.items()}
+    ref, _, _ = otr.adam_step({k: v.astype(np.float64) for k, v in x.items()},
+                              {k: v.astype(np.float64) for k, v in gr.items()}, zeros, dict(zeros), it, total,
+                              beta1=float(np.float32(0.9)), beta2=float(np.float32(0.999)),
+                              eps=float(np.float32(1e-15)))
+    torch.cuda.synchronize()
+    for k in ("sites", "density", "sh"):
+        np.testing.assert_allclose(gp[k].cpu().numpy(), ref[k], rtol=1e-5, atol=2e-6, err_msg=k)
+    g = rng.standard_normal((n, 3)).astype(np.float32)
+    sites, off, idx = map(_dv, (scene.sites, scene.off, scene.idx))
+    score = rf.densify_scores(sites, off, idx, _dv(g))
+    ref_score = otr.densify_scores(scene.sites, scene.off, scene.idx, g)
+    np.testing.assert_allclose(score.cpu().numpy(), ref_score, rtol=2e-6, atol=0)
+    draws = rng.uniform(0, 1, n // 10).astype(np.float32)
+    got = rf.sample_cells(score, _dv(draws)).cpu().numpy()
+    sc = score.cpu().numpy()
+    ref_s = otr.sample_cells(sc, draws)
+    c = np.cumsum(sc.astype(np.float64))
+    target = draws.astype(np.float64) * c[-1]
+    near = (np.abs(c[ref_s] - target) < 1e-9 * c[-1]) | (np.abs(c[np.maximum(ref_s - 1, 0)] - target) < 1e-9 * c[-1])
+    np.testing.assert_array_equal(got[~near], ref_s[~near])
+    # most cells emptied, so that a good share is pruned (a cell and all its neighbours empty)
+    dens = scene.density.astype(np.float32).copy()
+    dens[rng.uniform(0, 1, n) < 0.9] = 0.0
+    thr = 1e-3
+    mask = rf.prune_mask(_dv(dens), off, idx, thr).cpu().numpy()
+    np.testing.assert_array_equal(mask, otr.prune_mask(dens, scene.off, scene.idx, thr))
+    assert 0.05 < mask.mean() < 0.5

@@ -12,7 +12,7 @@ import oracle
 import synth
 
 from parity import (COLOUR_RTOL, GRAD_RTOL, T_ATOL, T_EXIT_ATOL, camera_rays, colour_err, compare_sequences,
-                    decidable, grad_err, inside_rays)
+                    decidable, grad_err, gradient_decidable, inside_rays)
 
 pytestmark = pytest.mark.gpu
 
@@ -247,7 +247,7 @@ def check_backward(rf, scene, rays, eps, mode=0, dtype="f32", with_gt=True, seed
         osc = oracle.OracleScene.from_scene(scene, density=oracle.bf16_to_f32(oracle.bf16_round(scene.density)),
                                             sh=oracle.bf16_to_f32(oracle.bf16_round(scene.sh)))
     ref = oracle.trace(osc, *rays, eps=eps, max_len=1024)
-    dec = decidable(ref, eps)
+    dec = gradient_decidable(ref, eps)
     rays = tuple(a[dec] for a in rays)
     rng = np.random.default_rng(seed)
     g = rng.standard_normal((len(rays[1]), 3)).astype(np.float32)

@@ -17,7 +17,7 @@ import pytest
 import oracle
 import synth
 
-from parity import GRAD_RTOL, camera_rays, decidable, grad_err, inside_rays
+from parity import GRAD_RTOL, camera_rays, decidable, grad_err, gradient_decidable, inside_rays
 
 pytestmark = pytest.mark.gpu
 
@@ -112,7 +112,7 @@ def test_gradients_with_quantile_term_match_oracle(setup, cap):
     osc = oracle.OracleScene.from_scene(scene)
     tr = oracle.trace(osc, *rays, eps=1e-4, max_len=1024)
     tq_ref, _ = oracle.quantile(osc, *rays, u.astype(np.float64), eps=1e-4)
-    keep = decidable(tr, 1e-4) & (np.abs(tq_ref[:, 0] - tq_ref[:, 1]) > 1e-3)
+    keep = gradient_decidable(tr, 1e-4) & (np.abs(tq_ref[:, 0] - tq_ref[:, 1]) > 1e-3)
     for r in np.nonzero(keep)[0]:
         tau = _boundary_depths(osc, tr, r)
         A = 1.0 - tr["t_final"][r]

@@ -175,6 +175,41 @@ def test_every_segment_lies_in_its_cell(scene, kind):
 
 
 @pytest.mark.parametrize("kind", ["mirror", "glass"])
+def test_fp32_legs_are_rounded_exact_legs(scene, kind):
+    """With fp32_legs every leg after a crossing starts from the exact leg's
+    origin and direction rounded to FP32, and the walk along it still obeys
+    eq. (5) (brute-force nearest sites at every segment midpoint)."""
+    rng = np.random.default_rng(41)
+    o, d, tmax, start = aimed_rays(rng, 60, scene.sites)
+    o, d = o.astype(np.float32).astype(np.float64), d.astype(np.float32).astype(np.float64)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    ex = oracle.trace(oracle.OracleScene.from_scene(scene, surface=surface(kind)), o, d, tmax, start, eps=0.0,
+                      legs=True)
+    sf32 = oracle.Surface(kind, CENTRE, RADIUS, BOX, ior=1.5, max_bounces=8, fp32_legs=True)
+    f32 = oracle.trace(oracle.OracleScene.from_scene(scene, surface=sf32), o, d, tmax, start, eps=0.0, legs=True)
+    x = scene.sites.astype(np.float64)
+    checked = 0
+    for r in range(len(d)):
+        cells, te, bounce, lo_, ld_ = _legs(f32, r)
+        e_cells, e_te, e_bounce, e_lo, e_ld = _legs(ex, r)
+        n1 = np.nonzero(bounce)[0]
+        if len(n1) == 0:
+            continue
+        b = n1[0]
+        # the first crossing is the same; the leg after it is the exact one rounded
+        assert e_bounce[b] and abs(te[b] - e_te[b]) <= 1e-12
+        np.testing.assert_array_equal(lo_[b + 1], e_lo[b + 1].astype(np.float32).astype(np.float64))
+        np.testing.assert_array_equal(ld_[b + 1], e_ld[b + 1].astype(np.float32).astype(np.float64))
+        t0 = 0.0
+        for n in range(len(cells)):
+            if te[n] - t0 > 1e-9:
+                assert brute_nn(x, lo_[n] + 0.5 * (t0 + te[n]) * ld_[n])[0][0] == cells[n]
+                checked += 1
+            t0 = 0.0 if bounce[n] else te[n]
+    assert checked > 300
+
+
+@pytest.mark.parametrize("kind", ["mirror", "glass"])
 def test_reversed_path_retraces_the_cells(scene, kind):
     """Light paths are reversible: from the end of the last leg, walking back
     along its reversed direction crosses the sphere at the same points and
