@@ -71,6 +71,12 @@ def measured_traffic(kernel: str, workload: str, dtype: str):
     return int(round((float(m.group(1)) + float(m.group(2))) * 1e6))
 
 
+def visit_bytes(mean_deg: float, B: int, dt: str) -> float:
+    """Algorithmic bytes of one visited cell: its row offsets (4), neighbour ids
+    (4 per face) and positions (12 per face), and its SH and density."""
+    return 4 + 16 * mean_deg + (3 * B + 1) * (2 if dt == "bf16" else 4)
+
+
 def flops_per_visit(mean_deg: float, B: int, kernel: str) -> float:
     """Arithmetic the walk itself requires per visited cell (FMA = 2 flops).
 
@@ -286,6 +292,10 @@ def main() -> int:
             for b in (True, False)},
         "kernel_ms": {f"{dt}_{'fwd_bwd' if b else 'fwd'}": {k: round(v, 4) for k, v in results[(dt, b)][1].items()}
                       for dt in dts for b in (True, False)},
+        # the method's own bytes per visited cell (row offsets, neighbour ids and
+        # positions, the cell's attributes) times visits, over the plain forward's time
+        "effective_visit_gbs": {dt: round(visits * visit_bytes(mean_deg, B, dt) / (results[(dt, False)][1]["forward"]
+                                                                                 * 1e-3) / 1e9, 1) for dt in dts},
         "roofline": {"bound": "alu", "kernel": f"{dominant} walk ({main_dt} attributes)",
                      "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s",
                      "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
@@ -540,10 +550,21 @@ def cpu_baseline(scene, cam, bound, start, g_np, visits_per_ray, target_s):
                     np.full(n, start, dtype=np.int32), g_np[sl], threads=threads)
     tb = time.perf_counter() - a
     log(f"oracle on {n} rays with {threads} threads: fwd {tf:.2f}s, bwd (recomputes the walk) {tb:.2f}s")
+    # one core, on the first sixteenth of the same sample
+    n1 = max(64, n // 16 // 64 * 64)
+    s1 = slice(mid, mid + n1)
+    a = time.perf_counter()
+    oracle.forward(osc, o[s1].astype(np.float32), d[s1].astype(np.float32), t[s1].astype(np.float32), start,
+                   threads=1)
+    oracle.backward(osc, o[s1].astype(np.float32), d[s1].astype(np.float32), t[s1].astype(np.float32),
+                    np.full(n1, start, dtype=np.int32), g_np[s1], threads=1)
+    t1 = time.perf_counter() - a
+    log(f"oracle on {n1} rays with 1 thread: forward + backward {t1:.2f}s")
     return {"value": round(n / (tf + tb) / 1e6, 5), "unit": "Mrays/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} rays ({n // 64} consecutive 8x8 tiles starting a quarter into the same frame), "
                       f"forward then backward, FP64 C oracle",
-            "fwd_mrays_s": round(n / tf / 1e6, 5)}
+            "fwd_mrays_s": round(n / tf / 1e6, 5),
+            "one_core": {"value": round(n1 / t1 / 1e6, 5), "sample": f"the first {n1} rays of that sample"}}
 
 
 if __name__ == "__main__":
