@@ -112,6 +112,8 @@ def main() -> int:
     ap.add_argument("--no-quantile", action="store_true", help="skip the quantile regulariser timing")
     ap.add_argument("--no-effects", action="store_true", help="skip the secondary-ray and fisheye timing")
     ap.add_argument("--no-training", action="store_true", help="skip the optimizer / densification timing")
+    ap.add_argument("--no-recompute-compare", action="store_true",
+                    help="skip timing the training step with the recomputing backward")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -244,13 +246,26 @@ def main() -> int:
                 f"kernels(ms) {json.dumps({k: round(v, 4) for k, v in kern.items()})}")
 
     recompute = None
-    if walk_log is not None:
+    if walk_log is not None and not args.no_recompute_compare:
         # the same training step with the backward recomputing every walk (no walk log)
         ms_r, kern_r, _ = run("f32" if args.only is None else args.only, True, use_log=False)
         recompute = {"mrays_s": round(R / ms_r / 1e3, 3), "ms_per_step": round(ms_r, 4),
                      "backward_ms": round(kern_r["backward"], 4)}
         log(f"fwd+bwd with the recomputing backward: {ms_r:.3f} ms/step, {R / ms_r / 1e3:.1f} Mrays/s, "
             f"backward {kern_r['backward']:.3f} ms")
+
+    # the colour error BF16-stored attributes introduce, against the FP32-attribute frame
+    bf16_err = None
+    if args.only is None:
+        o, d, t, s = rays
+        c32 = rf.render_forward(scenes["f32"], o, d, t, s)[0]
+        c16 = rf.render_forward(scenes["bf16"], o, d, t, s)[0]
+        diff = (c16 - c32).abs()
+        scale = float(c32.abs().max())
+        bf16_err = {"max_rel": round(float(diff.max()) / scale, 6), "mean_rel": round(float(diff.mean()) / scale, 8),
+                    "p99_rel": round(float(torch.quantile(diff.flatten()[:: 7].float(), 0.99)) / scale, 7)}
+        log(f"bf16 colour error against the fp32-attribute frame: max {bf16_err['max_rel']:.2e}, "
+            f"p99 {bf16_err['p99_rel']:.2e}, mean {bf16_err['mean_rel']:.2e} of the largest colour")
 
     main_dt = "f32" if args.only is None else args.only
     dts = [k[0] for k in results if k[1]]
@@ -284,6 +299,7 @@ def main() -> int:
         "fwd_mrays_s": {dt: round(R / results[(dt, False)][0] / 1e3, 3) for dt in dts},
         "fwd_bwd_mrays_s": {dt: round(R / results[(dt, True)][0] / 1e3, 3) for dt in dts},
         "fwd_bwd_recompute": recompute,
+        "bf16_colour_error": bf16_err,
         "bf16_speedup_fwd_bwd": (round(results[("f32", True)][0] / results[("bf16", True)][0], 4)
                                  if len(dts) == 2 else None),
         "step_latency_ms": {f"{dt}_{'fwd_bwd' if b else 'fwd'}": {

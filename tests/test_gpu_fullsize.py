@@ -68,6 +68,13 @@ def test_full_frame_forward_backward(name, dtype):
     assert colour_err(rgb, full["rgb"]) <= 10 * COLOUR_RTOL
     assert np.abs(tf[dec] - full["t_final"][dec]).max() <= T_ATOL
     np.testing.assert_array_equal(steps[dec], full["steps"][dec])
+    if dtype == "bf16":
+        # the total error of BF16 storage: against the oracle on the original FP32 attributes
+        ref32 = oracle.forward(oracle.OracleScene.from_scene(scene), o, d, t, s, eps=1e-4)[0]
+        err = np.abs(rgb - ref32)
+        print(f"bf16 total colour error against the FP32-attribute oracle: max {err.max() / scale:.3e}, "
+              f"p99 {np.quantile(err, 0.99) / scale:.3e}, mean {err.mean() / scale:.3e} of the largest colour",
+              flush=True)
 
     # visited cells of 64 tiles spread over the frame
     tiles = np.random.default_rng(0).choice(R // 64, size=64, replace=False)
