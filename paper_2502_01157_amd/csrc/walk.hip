@@ -111,31 +111,32 @@ __device__ inline void emit_atomic(bool has, const Package& p, const float* Y, c
 
 // Gradient emission of one wavefront, called with every lane active.
 //
-// Lanes holding a package for the same cell are grouped (leader by ballot);
-// for each group, lane q < 3B+4 sums column q over the group's members from
-// the wave's LDS rows (one row per lane: Y[0..B-1], gw[0..2], dsig, dx[0..2],
-// 1; members read four or eight at a time, padded with an all-zero row).
+// Lanes holding a package for the same cell are grouped (leader by ballot).
+// Every lane writes its row (Y[0..B-1], gw[0..2], dsig, dx[0..2], 1) once,
+// at a position that makes each group's rows contiguous (groups in the order
+// of their lowest lane, members in lane order), and for each group lane
+// q < 3B+4 sums column q over the group's rows (row addresses are immediate
+// offsets from the group's first row, no per-member index arithmetic).
 // The group's sums then go into a per-wavefront cache of gradient rows in LDS
 // (kSlots rows keyed by cell, first-in first-out): the 64 rays of a tile
 // visit only a few hundred distinct cells over their whole walks, each many
 // times, so summing in LDS and flushing a row with one coalesced atomic
 // instruction when it is evicted (or at the end) replaces most atomics.
 // The slot keys live in one register across lanes 0..kSlots-1, so a lookup is
-// one ballot.
+// one ballot. Members are summed in lane order, one fused multiply-add each.
 template <int DEG>
 struct EmitLayout {
     static constexpr int B = sh_count(DEG);
-    static constexpr int S = (B + 8) | 1;
-    static constexpr int ROWS = kWave + 1;
+    static constexpr int S = (B + 8 + 3) & ~3;  // row stride: whole float4s
     static constexpr int NOUT = 3 * B + 4;
     static constexpr int kSlots = 32;
-    static constexpr int FLOATS = ROWS * S + kSlots * NOUT;  // per wavefront
+    static constexpr int FLOATS = kWave * S + kSlots * NOUT;  // per wavefront
 };
 
 template <int DEG>
 struct Emitter {
     using E = EmitLayout<DEG>;
-    float* rows;   // LDS, ROWS x S
+    float* rows;   // LDS, kWave x S
     float* cache;  // LDS, kSlots x NOUT
     int lane;
     int colA, colB;  // this lane's column: row[colA] * row[colB]
@@ -144,12 +145,12 @@ struct Emitter {
     int slot_key;    // key of slot `lane` (lanes < kSlots), -1 empty
     int next_slot;   // wavefront-uniform FIFO position
 
-    // lds: the wavefront's E::FLOATS floats of LDS
+    // lds: the wavefront's E::FLOATS floats of LDS (16-byte aligned)
     __device__ void init(float* lds, int lane_, const WalkArgs& a)
     {
         constexpr int B = E::B;
         rows = lds;
-        cache = lds + E::ROWS * E::S;
+        cache = lds + kWave * E::S;
         lane = lane_;
         if (lane < 3 * B) {
             colA = lane / 3;
@@ -170,32 +171,40 @@ struct Emitter {
         }
         slot_key = -1;
         next_slot = 0;
-        // the padding row read by member batches that are not full
-        if (lane < E::S) rows[kWave * E::S + lane] = 0.0f;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
     }
 
-    // Sum over the members `mm` of this lane's column, W members per LDS batch.
-    template <int W>
-    __device__ float column_sum(uint64_t mm) const
+    // Sum over the group's rows first..first+m-1 of this lane's column product,
+    // in row order. The last batch of fewer than four rows reads past the
+    // group (at most two rows past the wavefront's 64, into its cache rows)
+    // and keeps only its own rows' terms.
+    __device__ float column_sum(int first, int m) const
     {
+        const float* pa = rows + first * E::S + colA;
+        const float* pb = rows + first * E::S + colB;
         float acc = 0.0f;
-        while (mm) {
-            int idx[W];
+        int q = 0;
+        for (; q + 4 <= m; q += 4) {
+            float va[4], vb[4];
 #pragma unroll
-            for (int q = 0; q < W; ++q) {
-                idx[q] = mm ? __builtin_ctzll(mm) : kWave;  // row kWave is all zeros
-                mm &= mm - 1;
-            }
-            float va[W], vb[W];
-#pragma unroll
-            for (int q = 0; q < W; ++q) {
-                va[q] = rows[idx[q] * E::S + colA];
-                vb[q] = rows[idx[q] * E::S + colB];
+            for (int u = 0; u < 4; ++u) {
+                va[u] = pa[(q + u) * E::S];
+                vb[u] = pb[(q + u) * E::S];
             }
 #pragma unroll
-            for (int q = 0; q < W; ++q) acc = fmaf(va[q], vb[q], acc);
+            for (int u = 0; u < 4; ++u) acc = fmaf(va[u], vb[u], acc);
+        }
+        if (q < m) {
+            float va[3], vb[3];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                va[u] = pa[(q + u) * E::S];
+                vb[u] = pb[(q + u) * E::S];
+            }
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const float t = fmaf(va[u], vb[u], acc);
+                acc = q + u < m ? t : acc;
+            }
         }
         return acc;
     }
@@ -224,43 +233,64 @@ struct Emitter {
         if (lane == slot) slot_key = key;
     }
 
-    // The ray's SH basis, constant over its walk: written into the lane's row once.
-    __device__ void set_basis(const float* Y)
-    {
-        float* row = rows + lane * E::S;
-#pragma unroll
-        for (int b = 0; b < E::B; ++b) row[b] = Y[b];
-    }
-
-    __device__ void emit(bool has, const Package& p)
+    // Emits the lanes' packages; Y is each lane's SH basis for its package.
+    __device__ void emit(bool has, const Package& p, const float* Y)
     {
         constexpr int B = E::B;
         uint64_t pend = __ballot(has);
         if (pend == 0) return;
+        const int key_cell = has ? p.cell : -1;
+        // each member's row: the groups in the order of their lowest lane,
+        // the members of a group in lane order
+        int pos = 0;
+        {
+            uint64_t rest = pend;
+            int first = 0;
+            while (rest) {
+                const int key = __builtin_amdgcn_readlane(key_cell, __builtin_ctzll(rest));
+                const uint64_t ma = __ballot(key_cell == key) & rest;
+                rest &= ~ma;
+                if (key_cell == key)
+                    pos = first + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0u));
+                first += __popcll(ma);
+            }
+        }
         if (has) {
-            float* row = rows + lane * E::S;  // row[0..B-1] = Y, written once by set_basis
-            row[B + 0] = p.gw[0];
-            row[B + 1] = p.gw[1];
-            row[B + 2] = p.gw[2];
-            row[B + 3] = p.dsig;
-            row[B + 4] = p.dx[0];
-            row[B + 5] = p.dx[1];
-            row[B + 6] = p.dx[2];
-            row[B + 7] = 1.0f;
+            float v[E::S];
+#pragma unroll
+            for (int b = 0; b < B; ++b) v[b] = Y[b];
+            v[B + 0] = p.gw[0];
+            v[B + 1] = p.gw[1];
+            v[B + 2] = p.gw[2];
+            v[B + 3] = p.dsig;
+            v[B + 4] = p.dx[0];
+            v[B + 5] = p.dx[1];
+            v[B + 6] = p.dx[2];
+            v[B + 7] = 1.0f;
+#pragma unroll
+            for (int c = B + 8; c < E::S; ++c) v[c] = 0.0f;
+            float4* row = reinterpret_cast<float4*>(rows + pos * E::S);
+#pragma unroll
+            for (int c = 0; c < E::S / 4; ++c) row[c] = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int key_cell = has ? p.cell : -1;
+        int first = 0;
         while (pend) {
-            const int key_a = __builtin_amdgcn_readlane(key_cell, __builtin_ctzll(pend));
-            const uint64_t ma = __ballot(key_cell == key_a) & pend;
+            const int key = __builtin_amdgcn_readlane(key_cell, __builtin_ctzll(pend));
+            const uint64_t ma = __ballot(key_cell == key) & pend;
             pend &= ~ma;
-            const float acc_a = __popcll(ma) <= 4 ? column_sum<4>(ma) : column_sum<8>(ma);
-            accumulate(key_a, acc_a);
+            const int m = __popcll(ma);
+            const float acc = column_sum(first, m);
+            first += m;
+            accumulate(key, acc);
         }
+        // the next emission's rows overwrite these
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 
     // Flushes every cached row (at the end of the wavefront's walks).
@@ -292,15 +322,16 @@ __device__ inline void exit_offsets(double t, float ox, float oy, float oz, floa
 
 // With SURF the walks bend at the surface as in the forward: each crossing
 // (logged, or found again by the recomputing walk) turns the leg with the
-// same arithmetic, the colour of the next visits uses the new leg's basis,
-// and the lane's LDS basis row is switched once the last package of the old
-// leg has been emitted.
+// same arithmetic, and the colour of the next visits uses the new leg's
+// basis; the crossing visit's package is emitted in its own iteration, before
+// the lane's basis turns, since nothing after the crossing changes it.
 template <int DEG, bool BF16, bool REDUCE, bool LOG, bool SURF = false>
-__global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_backward(WalkArgs a)
 {
     constexpr int B = sh_count(DEG);
     using E = EmitLayout<DEG>;
-    __shared__ float lds[REDUCE ? (kBlock / kWave) * E::FLOATS : 1];
+    static_assert(REDUCE || !SURF, "bent walks emit through the wavefront reduction");
+    __shared__ __align__(16) float lds[REDUCE ? (kBlock / kWave) * E::FLOATS : 1];
     const int lane = threadIdx.x & (kWave - 1);
     Emitter<DEG> em;
     if constexpr (REDUCE) em.init(lds + (threadIdx.x / kWave) * E::FLOATS, lane, a);
@@ -347,11 +378,9 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
     }
     float Y[B];
     sh_basis<DEG>(dx, dy, dz, Y);
-    if constexpr (REDUCE) em.set_basis(Y);
     Leg leg = {INFINITY, 0, 0};
-    bool cont = false;       // the next visit continues a cell after a crossing
-    bool new_leg = false;    // the next visit is the first of a new leg
-    bool basis_due = false;  // switch the emitter's basis after this iteration's emission
+    bool cont = false;    // the next visit continues a cell after a crossing
+    bool turned = false;  // this visit ended at the surface: the leg has turned, Y has not yet
     if constexpr (SURF) {
         if (state == 0) leg_start(a.surf, ox, oy, oz, dx, dy, dz, leg);
     }
@@ -412,10 +441,6 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
                 Visit<DEG> v;
                 int cell;
                 bool moves, cross = false;
-                if (new_leg) {
-                    basis_due = true;
-                    new_leg = false;
-                }
                 cont = false;
                 if constexpr (LOG) {
                     // the visit as the forward logged it: same record, same te,
@@ -516,12 +541,12 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
                     if constexpr (SURF) {
                         // a new leg from the crossing, in the same cell; the
                         // crossing's exit does not move, so nothing links the
-                        // two legs' gradients
+                        // two legs' gradients (the basis turns after this
+                        // iteration's emissions, which still need the old one)
                         surface_turn(a.surf, leg, ox, oy, oz, dx, dy, dz, tmax);
-                        sh_basis<DEG>(dx, dy, dz, Y);
                         t0 = 0.0;
                         cont = true;
-                        new_leg = true;
+                        turned = true;
                     }
                 } else {
                     if (!LOG) ref = v.h.next;
@@ -558,13 +583,20 @@ __global__ __launch_bounds__(kBlock) void k_backward(WalkArgs a)
             state = 3;
         }
         if constexpr (REDUCE)
-            em.emit(has, out);
+            em.emit(has, out, Y);
         else
             emit_atomic<DEG>(has, out, Y, a);
-        if constexpr (SURF && REDUCE) {
-            if (basis_due) {
-                em.set_basis(Y);
-                basis_due = false;
+        if constexpr (SURF) {
+            // a crossing's package is complete when its visit ends (its exit
+            // does not move), so it goes out now, with the old leg's basis,
+            // and the lane's basis turns with the leg
+            if (__ballot(turned)) {
+                em.emit(turned, prev, Y);
+                if (turned) {
+                    sh_basis<DEG>(dx, dy, dz, Y);
+                    have_prev = false;
+                    turned = false;
+                }
             }
         }
     }
