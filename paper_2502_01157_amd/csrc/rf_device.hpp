@@ -213,20 +213,20 @@ __device__ inline int ref_deg(uint2 r) { return (int)(r.x >> 24); }
 __device__ inline int ref_beg(uint2 r) { return (int)r.y; }
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD b % 8).
-// Remap so that each XCD walks chunks of kXcdChunk consecutive blocks (32
-// screen tiles: neighbouring tiles walk the same cells, so a chunk's records
-// are shared in one XCD's L2), with the chunks dealt to the XCDs in turn so
-// that every XCD gets work from all over the frame. (One contiguous eighth of
-// the frame per XCD leaves the XCDs with the lighter bands idle at the end:
-// 15% slower walks on a 1080p frame.) Blocks past the last whole round of
-// chunks keep their place.
-constexpr int64_t kXcdChunk = 8;
+// Remap so that each XCD works on chunks of CHUNK consecutive blocks (the
+// walks use 32 one-tile blocks: neighbouring tiles walk the same cells, so a
+// chunk's records are shared in one XCD's L2), with the chunks dealt to the
+// XCDs in turn so that every XCD gets work from all over the frame. (One
+// contiguous eighth of the frame per XCD leaves the XCDs with the lighter
+// bands idle at the end: 15% slower walks on a 1080p frame.) Blocks past the
+// last whole round of chunks keep their place.
+template <int64_t CHUNK = 8>
 __device__ inline int64_t xcd_block(int64_t b, int64_t nb)
 {
-    const int64_t full = nb / (8 * kXcdChunk) * (8 * kXcdChunk);
+    const int64_t full = nb / (8 * CHUNK) * (8 * CHUNK);
     if (b >= full) return b;
     const int64_t x = b % 8, m = b / 8;
-    return ((m / kXcdChunk) * 8 + x) * kXcdChunk + m % kXcdChunk;
+    return ((m / CHUNK) * 8 + x) * CHUNK + m % CHUNK;
 }
 
 }  // namespace rf

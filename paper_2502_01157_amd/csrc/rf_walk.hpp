@@ -153,7 +153,7 @@ __device__ inline double face_den(const float* xi, const float* xj, float dx, fl
 // 16-byte chunk per lane), and every lane then reads its own cell's copy.
 // Cells that do not fit the region are read from global memory as before.
 // ---------------------------------------------------------------------------
-// Each wavefront's region is 10 KiB, so that four blocks of four wavefronts
+// Each wavefront's region is 10 KiB, so that sixteen one-wavefront blocks
 // fill the 160 KiB of LDS (four wavefronts per SIMD, what the registers
 // allow). The split between face and record slots is chosen on traces of
 // the clustered 1M-site frame, where a wavefront step touches 9.5 distinct

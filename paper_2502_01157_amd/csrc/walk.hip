@@ -49,16 +49,20 @@ namespace rf {
 // ---------------------------------------------------------------------------
 // Forward (and traced forward).
 // ---------------------------------------------------------------------------
+// One wavefront (one screen tile) per block: a block's LDS and slots are
+// released as soon as its own walks end (a block of four tiles holds them
+// until the longest of its four walks ends: 5-6% slower walks).
+constexpr int kWalkBlock = kWave;
 __device__ inline int64_t ray_index()
 {
-    return xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    return xcd_block<32>(blockIdx.x, gridDim.x) * kWalkBlock + threadIdx.x;
 }
 
 template <int DEG, bool BF16, bool TRACE, bool LOG, bool SURF = false>
-__global__ __launch_bounds__(kBlock) void k_forward(WalkArgs a)
+__global__ __launch_bounds__(kWalkBlock) void k_forward(WalkArgs a)
 {
     using SL = StageLayout<DEG, BF16>;
-    __shared__ __align__(16) unsigned char stage_mem[(kBlock / kWave) * SL::kBytes];
+    __shared__ __align__(16) unsigned char stage_mem[(kWalkBlock / kWave) * SL::kBytes];
     lds_u8* region = (lds_u8*)(stage_mem + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave) * SL::kBytes);
     const int64_t r = ray_index();
     const bool valid = r < a.n_rays;  // lanes past the end still take part in the staging
@@ -326,12 +330,12 @@ __device__ inline void exit_offsets(double t, float ox, float oy, float oz, floa
 // basis; the crossing visit's package is emitted in its own iteration, before
 // the lane's basis turns, since nothing after the crossing changes it.
 template <int DEG, bool BF16, bool REDUCE, bool LOG, bool SURF = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_backward(WalkArgs a)
+__global__ __launch_bounds__(kWalkBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_backward(WalkArgs a)
 {
     constexpr int B = sh_count(DEG);
     using E = EmitLayout<DEG>;
     static_assert(REDUCE || !SURF, "bent walks emit through the wavefront reduction");
-    __shared__ __align__(16) float lds[REDUCE ? (kBlock / kWave) * E::FLOATS : 1];
+    __shared__ __align__(16) float lds[REDUCE ? (kWalkBlock / kWave) * E::FLOATS : 1];
     const int lane = threadIdx.x & (kWave - 1);
     Emitter<DEG> em;
     if constexpr (REDUCE) em.init(lds + (threadIdx.x / kWave) * E::FLOATS, lane, a);
@@ -656,7 +660,7 @@ struct QuantileScan {
 };
 
 template <int DEG, bool BF16>
-__global__ __launch_bounds__(kBlock) void k_quantile(WalkArgs a)
+__global__ __launch_bounds__(kWalkBlock) void k_quantile(WalkArgs a)
 {
     const int64_t r = ray_index();
     if (r >= a.n_rays) return;
@@ -715,10 +719,10 @@ __global__ __launch_bounds__(kBlock) void k_quantile(WalkArgs a)
 template <int DEG, bool BF16>
 static hipError_t launch_walk_t(WalkKind kind, const WalkArgs& a, hipStream_t stream)
 {
-    const int64_t blocks = (a.n_rays + kBlock - 1) / kBlock;
+    const int64_t blocks = (a.n_rays + kWalkBlock - 1) / kWalkBlock;
     if (blocks == 0) return hipSuccess;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)blocks), block(kBlock);
+    const dim3 grid((unsigned)blocks), block(kWalkBlock);
     switch (kind) {
     case kForward:
         hipLaunchKernelGGL((k_forward<DEG, BF16, false, false>), grid, block, 0, stream, a);
