@@ -67,11 +67,13 @@ struct BatchArgs {
     float* pool;            // pinned host output pool (device-visible pointer)
 };
 
+// One tile per wavefront and per block, so that a block's slots are released
+// when its own tile is done.
 template <int DEG, bool BF16>
-__global__ __launch_bounds__(kBlock) void k_serve_tiles(BatchArgs a)
+__global__ __launch_bounds__(kWave) void k_serve_tiles(BatchArgs a)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int tile = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x;
+    const int tile = blockIdx.x;
     if (tile >= a.n_tiles) return;
     const uint32_t desc = a.desc[tile];
     const int slot = (int)(desc >> kLocalTileBits);
@@ -94,8 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_tiles(BatchArgs a)
 template <int DEG, bool BF16>
 static hipError_t launch_batch_t(const BatchArgs& a, hipStream_t stream)
 {
-    const unsigned blocks = (unsigned)((a.n_tiles + kBlock / kWave - 1) / (kBlock / kWave));
-    hipLaunchKernelGGL((k_serve_tiles<DEG, BF16>), dim3(blocks), dim3(kBlock), 0, stream, a);
+    hipLaunchKernelGGL((k_serve_tiles<DEG, BF16>), dim3((unsigned)a.n_tiles), dim3(kWave), 0, stream, a);
     return hipGetLastError();
 }
 
