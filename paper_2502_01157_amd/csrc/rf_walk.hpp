@@ -157,17 +157,21 @@ __device__ inline double face_den(const float* xi, const float* xj, float dx, fl
 // fill the 160 KiB of LDS (four wavefronts per SIMD, what the registers
 // allow). The split between face and record slots is chosen on traces of
 // the clustered 1M-site frame, where a wavefront step touches 9.5 distinct
-// cells on average (p90: 17): FP32 (256-byte records at degree 3) 320 faces
-// and 20 records leave 6.7 % of the steps with a lane that does not fit
-// (352 + 16: 13 %); BF16 (128-byte records) 448 and 24 leave 0.9 %.
+// cells on average (p90: 17). A staged record takes only its used bytes (208
+// of the 256 of an FP32 record at degree 3, 112 of 128 in BF16), which leaves
+// room for 380 faces beside 20 FP32 records (472 beside 24 in BF16). With
+// 320 faces and 256-byte record slots, 6.7 % of the FP32 steps had a lane
+// whose cell did not fit (then the wavefront also runs the scan from global
+// memory); the larger face region made the FP32 forward 4 % faster.
 template <int DEG, bool BF16>
 struct StageLayout {
     using R = Rec<DEG, BF16>;
     static constexpr int kBudget = 10240;
     static constexpr int kRecs = BF16 ? 24 : 20;                       // record slots
-    static constexpr int kFaces = (kBudget - kRecs * R::BYTES) / 16 / 4 * 4;  // face slots (16 B each)
+    static constexpr int kRecStride = R::CHUNKS * 16;                         // the record's used bytes
+    static constexpr int kFaces = (kBudget - kRecs * kRecStride) / 16 / 4 * 4;  // face slots (16 B each)
     static constexpr int kRecOff = kFaces * 16;
-    static constexpr int kBytes = kRecOff + kRecs * R::BYTES;
+    static constexpr int kBytes = kRecOff + kRecs * kRecStride;
     static_assert(kBytes <= kBudget, "stage region over budget");
 };
 
@@ -199,7 +203,7 @@ __device__ inline void stage_cells(const SceneView& s, bool want, uint2 ref, lds
             if (k0 + lane < gdeg)
                 copy16_to_lds(s.planes + gbeg + k0, 16u * kWave, lane16, region + (off + k0) * 16);
         if (lane < R::CHUNKS)
-            copy16_to_lds(s.rec + (size_t)key * R::BYTES, R::BYTES, lane16, region + SL::kRecOff + nrec * R::BYTES);
+            copy16_to_lds(s.rec + (size_t)key * R::BYTES, R::BYTES, lane16, region + SL::kRecOff + nrec * SL::kRecStride);
         if ((members >> lane) & 1) {
             face_slot = off;
             rec_slot = nrec;
@@ -231,7 +235,7 @@ __device__ inline void visit_cell_staged(const SceneView& s, uint2 ref, int face
         v.h.next = s.adj[beg + v.h.k];
     }
     if (rec_slot >= 0)
-        unpack_record<DEG, BF16>(reinterpret_cast<lds_u32x4*>(region + SL::kRecOff + rec_slot * R::BYTES), v.at);
+        unpack_record<DEG, BF16>(reinterpret_cast<lds_u32x4*>(region + SL::kRecOff + rec_slot * SL::kRecStride), v.at);
     else
         load_record<DEG, BF16>(s.rec, cell, v.at);
     v.t1 = INFINITY;
