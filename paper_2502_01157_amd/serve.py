@@ -93,7 +93,9 @@ def replay(server: Server, requests: Sequence[dict], keep: Sequence[int] = (), t
     ``fov_deg``, ``width``, ``height`` and ``start_cell``. A request enters the
     queue at its arrival time; the head of the queue is submitted as soon as the
     server admits it. Latency is arrival -> completion observed by the host
-    (polling); the copy-out of the image is timed separately. Returns latencies,
+    (polling; requests that finish together are observed together, and new
+    arrivals are submitted before their images are copied out); the copy-out
+    of the image is timed separately. Returns latencies,
     throughput and the images of the requests whose indices are in ``keep``.
     """
     n = len(requests)
@@ -109,10 +111,11 @@ def replay(server: Server, requests: Sequence[dict], keep: Sequence[int] = (), t
     done = 0
     rays = 0
     t0 = time.perf_counter()
-    while done < n:
+
+    def admit() -> None:
+        # arrivals join the queue; its head is submitted while the server admits it
+        nonlocal nxt
         now = time.perf_counter() - t0
-        if now > timeout_s:
-            raise TimeoutError(f"replay: {done}/{n} requests finished after {timeout_s} s")
         while nxt < n and requests[order[nxt]]["arrival"] * time_scale <= now:
             queue.append(int(order[nxt]))
             nxt += 1
@@ -126,20 +129,32 @@ def replay(server: Server, requests: Sequence[dict], keep: Sequence[int] = (), t
             queue.popleft()
             rid_of[rid] = i
             admitted_at[i] = time.perf_counter() - t0
+
+    while done < n:
+        if time.perf_counter() - t0 > timeout_s:
+            raise TimeoutError(f"replay: {done}/{n} requests finished after {timeout_s} s")
+        admit()
         finished = server.poll()
-        if not finished and queue:
-            time.sleep(5e-5)  # the head waits for a slot or pool space
-        for rid in finished:
-            i = rid_of.pop(rid)
+        if finished:
+            # completions are observed together; new arrivals are submitted
+            # before the copies out, so that no copy holds the GPU's next work
             t_done = time.perf_counter() - t0
-            latency[i] = t_done - requests[i]["arrival"] * time_scale
-            a = time.perf_counter()
-            img = server.result(rid, copy=True)
-            copy_ms[i] = (time.perf_counter() - a) * 1e3
-            if i in keep:
-                images[i] = img
-            rays += requests[i]["width"] * requests[i]["height"]
-            done += 1
+            for rid in finished:
+                i = rid_of[rid]
+                latency[i] = t_done - requests[i]["arrival"] * time_scale
+            admit()
+            for rid in finished:
+                i = rid_of.pop(rid)
+                a = time.perf_counter()
+                img = server.result(rid, copy=True)
+                copy_ms[i] = (time.perf_counter() - a) * 1e3
+                if i in keep:
+                    images[i] = img
+                rays += requests[i]["width"] * requests[i]["height"]
+                done += 1
+                admit()
+        elif queue:
+            time.sleep(5e-5)  # the head waits for a slot or pool space
         if not queue and nxt < n:
             wait = requests[order[nxt]]["arrival"] * time_scale - (time.perf_counter() - t0)
             if wait > 2e-4:
