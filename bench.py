@@ -529,8 +529,8 @@ def serving(rf, packed, scene, bound, dts):
     res = {"requests": len(stream), "offered_mrays_s": round(offered, 2)}
     # the same requests all at once: the server's capacity
     burst = [dict(r, arrival=0.0) for r in stream]
-    # a fresh server's first launches (code loading, first touch of its pool) are
-    # slow: 16 requests all at once warm it up before each timed replay
+    # a fresh server on a device that has been idle serves its first requests
+    # slowly: 16 requests all at once warm it up before each timed replay
     warm = [dict(r, arrival=0.0) for r in stream[:16]]
     for dt in dts:
         with Server(packed[dt], bound, pool_bytes=1 << 30, max_inflight=64) as srv:
