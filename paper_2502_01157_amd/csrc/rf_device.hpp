@@ -19,7 +19,7 @@
 namespace rf {
 
 constexpr int kWave = 64;
-constexpr int kBlock = 256;  // four wavefronts = four 8x8 screen tiles
+constexpr int kBlock = 256;  // block of the point-location kernel (the walks run one wavefront per block)
 
 __host__ __device__ constexpr int sh_count(int deg) { return (deg + 1) * (deg + 1); }
 
