@@ -329,7 +329,9 @@ __device__ inline void exit_offsets(double t, float ox, float oy, float oz, floa
 // same arithmetic, and the colour of the next visits uses the new leg's
 // basis; the crossing visit's package is emitted in its own iteration, before
 // the lane's basis turns, since nothing after the crossing changes it.
-template <int DEG, bool BF16, bool REDUCE, bool LOG, bool SURF = false>
+// QUANT = false leaves out the quantile regulariser's terms (and their 13
+// registers) for calls without them.
+template <int DEG, bool BF16, bool REDUCE, bool LOG, bool SURF = false, bool QUANT = true>
 __global__ __launch_bounds__(kWalkBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_backward(WalkArgs a)
 {
     constexpr int B = sh_count(DEG);
@@ -396,7 +398,7 @@ __global__ __launch_bounds__(kWalkBlock) __attribute__((amdgpu_waves_per_eu(3)))
     // dsigma_k -= c (t - t0_k) / sigma_k and the exit before k moves t by c.
     float qc[2] = {0.0f, 0.0f}, qD[2] = {0.0f, 0.0f}, qs[2] = {1.0f, 1.0f}, qt[2] = {0.0f, 0.0f};
     int qk[2] = {-1, -1};
-    if (state == 0 && a.grad_q) {
+    if (QUANT && state == 0 && a.grad_q) {
         const float t_a = a.q_t[2 * r], t_b = a.q_t[2 * r + 1];
         const int k_a = a.q_seg[2 * r], k_b = a.q_seg[2 * r + 1];
         if (k_a >= 0 && k_b >= 0 && t_a != t_b) {
@@ -495,7 +497,7 @@ __global__ __launch_bounds__(kWalkBlock) __attribute__((amdgpu_waves_per_eu(3)))
                 float dsig_q = 0.0f, gt_q = 0.0f;
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    if (qc[j] != 0.0f) {
+                    if (QUANT && qc[j] != 0.0f) {
                         dtau += qc[j] * (qD[j] - (n < qk[j] ? 1.0f : 0.0f)) / qs[j];
                         if (n == qk[j]) {
                             dsig_q -= qc[j] * (float)((double)qt[j] - t0) / qs[j];
@@ -741,7 +743,10 @@ static hipError_t launch_walk_t(WalkKind kind, const WalkArgs& a, hipStream_t st
         break;
     case kBackwardLogReduce:
         // rays within the log, then the rays whose walks outgrew it (recomputed)
-        hipLaunchKernelGGL((k_backward<DEG, BF16, true, true>), grid, block, 0, stream, a);
+        if (a.grad_q)
+            hipLaunchKernelGGL((k_backward<DEG, BF16, true, true>), grid, block, 0, stream, a);
+        else
+            hipLaunchKernelGGL((k_backward<DEG, BF16, true, true, false, false>), grid, block, 0, stream, a);
         hipLaunchKernelGGL((k_backward<DEG, BF16, true, false>), grid, block, 0, stream, a);
         break;
     case kBackwardLogAtomic:
