@@ -736,18 +736,23 @@ static hipError_t launch_walk_t(WalkKind kind, const WalkArgs& a, hipStream_t st
         hipLaunchKernelGGL((k_forward<DEG, BF16, false, true>), grid, block, 0, stream, a);
         break;
     case kBackwardReduce:
-        hipLaunchKernelGGL((k_backward<DEG, BF16, true, false>), grid, block, 0, stream, a);
+        if (a.grad_q)
+            hipLaunchKernelGGL((k_backward<DEG, BF16, true, false>), grid, block, 0, stream, a);
+        else
+            hipLaunchKernelGGL((k_backward<DEG, BF16, true, false, false, false>), grid, block, 0, stream, a);
         break;
     case kBackwardAtomic:
         hipLaunchKernelGGL((k_backward<DEG, BF16, false, false>), grid, block, 0, stream, a);
         break;
     case kBackwardLogReduce:
         // rays within the log, then the rays whose walks outgrew it (recomputed)
-        if (a.grad_q)
+        if (a.grad_q) {
             hipLaunchKernelGGL((k_backward<DEG, BF16, true, true>), grid, block, 0, stream, a);
-        else
+            hipLaunchKernelGGL((k_backward<DEG, BF16, true, false>), grid, block, 0, stream, a);
+        } else {
             hipLaunchKernelGGL((k_backward<DEG, BF16, true, true, false, false>), grid, block, 0, stream, a);
-        hipLaunchKernelGGL((k_backward<DEG, BF16, true, false>), grid, block, 0, stream, a);
+            hipLaunchKernelGGL((k_backward<DEG, BF16, true, false, false, false>), grid, block, 0, stream, a);
+        }
         break;
     case kBackwardLogAtomic:
         hipLaunchKernelGGL((k_backward<DEG, BF16, false, true>), grid, block, 0, stream, a);
