@@ -128,18 +128,18 @@ __device__ inline void emit_atomic(bool has, const Package& p, const float* Y, c
 // instruction when it is evicted (or at the end) replaces most atomics.
 // The slot keys live in one register across lanes 0..kSlots-1, so a lookup is
 // one ballot. Members are summed in lane order, one fused multiply-add each.
-template <int DEG>
+template <int DEG, int SLOTS>
 struct EmitLayout {
     static constexpr int B = sh_count(DEG);
     static constexpr int S = (B + 8 + 3) & ~3;  // row stride: whole float4s
     static constexpr int NOUT = 3 * B + 4;
-    static constexpr int kSlots = 32;
+    static constexpr int kSlots = SLOTS;
     static constexpr int FLOATS = kWave * S + kSlots * NOUT;  // per wavefront
 };
 
-template <int DEG>
+template <int DEG, int SLOTS>
 struct Emitter {
-    using E = EmitLayout<DEG>;
+    using E = EmitLayout<DEG, SLOTS>;
     float* rows;   // LDS, kWave x S
     float* cache;  // LDS, kSlots x NOUT
     int lane;
@@ -324,6 +324,18 @@ __device__ inline void exit_offsets(double t, float ox, float oy, float oz, floa
     }
 }
 
+// The plain reducing backward with BF16 attributes runs 4 wavefronts per SIMD,
+// which needs the wavefront's LDS within 10 KiB: 19 gradient-cache rows
+// instead of 32 (measured on the clustered 1M-site frame: the logged backward
+// 7.53 -> 7.10 ms, the recomputing one 11.25 -> 10.03 ms). With FP32
+// attributes, or with the quantile or surface terms, the registers spilled at
+// 4 wavefronts cost more than the extra wavefront hides (FP32 logged: 7.83 ->
+// 8.73 ms), so those keep 3 wavefronts and 32 rows.
+constexpr bool four_waves(bool bf16, bool reduce, bool surf, bool quant)
+{
+    return bf16 && reduce && !surf && !quant;
+}
+
 // With SURF the walks bend at the surface as in the forward: each crossing
 // (logged, or found again by the recomputing walk) turns the leg with the
 // same arithmetic, and the colour of the next visits uses the new leg's
@@ -332,14 +344,16 @@ __device__ inline void exit_offsets(double t, float ox, float oy, float oz, floa
 // QUANT = false leaves out the quantile regulariser's terms (and their 13
 // registers) for calls without them.
 template <int DEG, bool BF16, bool REDUCE, bool LOG, bool SURF = false, bool QUANT = true>
-__global__ __launch_bounds__(kWalkBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_backward(WalkArgs a)
+__global__ __launch_bounds__(kWalkBlock) __attribute__((amdgpu_waves_per_eu(four_waves(BF16, REDUCE, SURF, QUANT) ? 4 : 3)))
+void k_backward(WalkArgs a)
 {
     constexpr int B = sh_count(DEG);
-    using E = EmitLayout<DEG>;
+    constexpr int kSlots = four_waves(BF16, REDUCE, SURF, QUANT) ? 19 : 32;
+    using E = EmitLayout<DEG, kSlots>;
     static_assert(REDUCE || !SURF, "bent walks emit through the wavefront reduction");
     __shared__ __align__(16) float lds[REDUCE ? (kWalkBlock / kWave) * E::FLOATS : 1];
     const int lane = threadIdx.x & (kWave - 1);
-    Emitter<DEG> em;
+    Emitter<DEG, kSlots> em;
     if constexpr (REDUCE) em.init(lds + (threadIdx.x / kWave) * E::FLOATS, lane, a);
 
     const int64_t r = ray_index();
