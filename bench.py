@@ -5,12 +5,16 @@ Workload (default): 1M sites from 64 thin anisotropic Gaussian clusters plus
 orbit of radius 0.8, forward + backward with per-pixel N(0,1) upstream
 gradients. One step is the whole hot path on one batch:
 camera rays (8x8 tiles) -> scene pack (face planes + cell records) ->
-forward walk -> backward walk (gradients for sites, density, SH).
+forward walk -> backward walk (gradients for sites, density, SH; the backward
+recomputes each walk from the saved colour and transmittance). With
+--config shell_3m a batch is the rays of all eight cameras, one pack per step.
 
 Prints ONE JSON line. `value` is forward+backward Mrays/s with FP32 attributes;
-forward-only and BF16-attribute rates, per-kernel times, step-latency
-percentiles, the roofline of the dominant kernel and the FP64 CPU oracle's
-rate on a bounded sample of the same workload are added fields.
+forward-only and BF16-attribute rates, the training step whose backward reads
+a walk log, per-kernel times, step-latency percentiles, the HBM roofline of
+every walk kernel (rocprofv3 DRAM bytes over the HIP-event duration) with its
+vector-ALU companion, and the FP64 CPU oracle's rate on a bounded sample of
+the same workload are added fields.
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--config clustered_1m]
 """
@@ -30,7 +34,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP32 vector peak without packed math: 256 CUs x 64 FMA lanes x 2 flops x 2.4 GHz.
+# MI355X published FP32 vector peak (packed FP32), and the rate without packed
+# math (256 CUs x 64 FMA lanes x 2 flops x 2.4 GHz), which is what this build
+# can issue: packed FP32 instructions are disabled.
+FP32_PEAK_TFLOPS = 157.3
 VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
@@ -52,29 +59,37 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:12]
 
 
-def measured_traffic(kernel: str, workload: str, dtype: str):
-    """HBM bytes per launch (read + written) of `kernel` from the committed rocprofv3 PMC summary,
-    or None if that summary was taken on other kernel sources."""
+def measured_traffic(workload: str, dtype: str, label: str):
+    """HBM bytes per launch (read + written) of the launch `label` (e.g.
+    "backward (recomputing)") from the committed rocprofv3 PMC summary of
+    `workload` and `dtype`, or None if there is none for these kernel sources."""
     path = os.path.join(ROOT, "profiles", f"walk_kernels_{workload}_{dtype}_hbm_traffic.md")
-    if not os.path.exists(path):
+    if not label or not os.path.exists(path):
         return None
     text = open(path).read()
     m = re.search(r"kernel source digest: ([0-9a-f]+)", text)
     if not m or m.group(1) != kernel_source_digest():
         return None
-    # the launch the training step times: the logged forward, the log kernel of the backward
-    label = {"forward": "logged (training step)", "backward": "log kernel"}[kernel]
-    m = re.search(rf"^\| k_{kernel} \| {re.escape(label)} \| \d+ \| \d+ \| \d+ \| ([0-9.]+) \| ([0-9.]+) \|",
+    kernel, _, rest = label.partition(" ")
+    rest = rest.strip("()") or kernel
+    m = re.search(rf"^\| k_{kernel} \| {re.escape(rest)} \| \d+ \| [0-9.]+ \| [0-9.]+ \| ([0-9.]+) \| ([0-9.]+) \|",
                   text, re.M)
     if not m:
         return None
     return int(round((float(m.group(1)) + float(m.group(2))) * 1e6))
 
 
-def visit_bytes(mean_deg: float, B: int, dt: str) -> float:
-    """Algorithmic bytes of one visited cell: its row offsets (4), neighbour ids
-    (4 per face) and positions (12 per face), and its SH and density."""
-    return 4 + 16 * mean_deg + (3 * B + 1) * (2 if dt == "bf16" else 4)
+def visit_bytes(mean_deg: float, B: int, dt: str, kind: str = "forward") -> float:
+    """Bytes the method touches per visited cell, with no reuse: its row offsets
+    (4), neighbour ids (4 per face) and positions (12 per face), and its SH and
+    density. A backward adds the cell's gradient package before any reduction
+    ((3B + 1 + 3) floats, read-modify-write counted once); the backward that
+    reads the walk log reads 12 B of log and the site (12 B) instead of the faces."""
+    attr = (3 * B + 1) * (2 if dt == "bf16" else 4)
+    scan = 4 + 16 * mean_deg
+    grad = 4 * (3 * B + 4)
+    return {"forward": scan + attr, "backward_recompute": scan + attr + grad,
+            "backward": 12 + 12 + attr + grad}[kind]
 
 
 def flops_per_visit(mean_deg: float, B: int, kernel: str) -> float:
@@ -103,17 +118,16 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", type=int, default=0, help="backward reduction mode (0 wave-reduced, 1 per-lane)")
-    ap.add_argument("--recompute", action="store_true",
-                    help="backward recomputes every walk instead of reading the forward's walk log")
-    ap.add_argument("--log-capacity", type=int, default=256, help="visits per ray kept in the walk log")
+    ap.add_argument("--log-capacity", type=int, default=256,
+                    help="visits per ray kept in the walk log of the logged training step")
     ap.add_argument("--only", choices=["f32", "bf16"], default=None, help="time one attribute precision only")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving replay (512 Poisson requests)")
     ap.add_argument("--no-locate", action="store_true", help="skip the start-cell location timing")
     ap.add_argument("--no-quantile", action="store_true", help="skip the quantile regulariser timing")
     ap.add_argument("--no-effects", action="store_true", help="skip the secondary-ray and fisheye timing")
     ap.add_argument("--no-training", action="store_true", help="skip the optimizer / densification timing")
-    ap.add_argument("--no-recompute-compare", action="store_true",
-                    help="skip timing the training step with the recomputing backward")
+    ap.add_argument("--no-log-compare", action="store_true",
+                    help="skip timing the training step whose backward reads a walk log")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -135,11 +149,12 @@ def main() -> int:
     scene, rng = synth.make_scene(args.config, return_rng=True)
     cams = synth.make_cameras(args.config, rng)
     cam = cams[0]
-    R = cam.width * cam.height
+    R = sum(c.width * c.height for c in cams)
     g_np = synth.make_upstream_grads(rng, R)
-    start = int(synth.nearest_site(scene.sites, cam.position[None, :])[0])
+    starts = [int(x) for x in synth.nearest_site(scene.sites, np.stack([c.position for c in cams]))]
+    start = starts[0]
     log(f"scene {args.config}: {scene.n_sites} sites, {scene.n_edges} directed edges, "
-        f"{cam.width}x{cam.height} rays, built in {time.time() - t0:.1f}s")
+        f"{len(cams)} camera(s), {R} rays per step, built in {time.time() - t0:.1f}s")
 
     dev = torch.device("cuda:0")
 
@@ -149,33 +164,43 @@ def main() -> int:
     sites, off, idx, dens, sh = map(dv, (scene.sites, scene.off, scene.idx, scene.density, scene.sh))
     grad_rgb = dv(g_np)
     B = (scene.sh_deg + 1) ** 2
-    pose, fov, W, H = cam.pose12(), cam.fov_deg, cam.width, cam.height
     bound = cfg["bound"]
 
     scenes = {dt: rf.PackedScene(sites, off, idx, dens, sh, scene.sh_deg, dt, validate=True)
               for dt in ("f32", "bf16")}
     grads = (torch.zeros((scene.n_sites, 3), device=dev), torch.zeros(scene.n_sites, device=dev),
              torch.zeros((scene.n_sites, B, 3), device=dev))
-    rays = rf.raygen(pose, fov, W, H, bound, start, device=dev, with_pixel=False)[:4]
+    # one batch: the rays of every camera of the workload, camera after camera
+    rays = (torch.empty((R, 3), device=dev), torch.empty((R, 3), device=dev), torch.empty(R, device=dev),
+            torch.empty(R, dtype=torch.int32, device=dev))
+    cam_rows = np.concatenate([[0], np.cumsum([c.width * c.height for c in cams])])
+
+    def raygen_all():
+        for c, st, a, b in zip(cams, starts, cam_rows[:-1], cam_rows[1:]):
+            rf.raygen(c.pose12(), c.fov_deg, c.width, c.height, bound, st, device=dev, with_pixel=False,
+                      out=tuple(x[a:b] for x in rays))
+        return rays
+
+    raygen_all()
     fwd_out = (torch.empty((R, 3), device=dev), torch.empty(R, device=dev),
                torch.empty(R, dtype=torch.int32, device=dev))
-    walk_log = None if args.recompute else rf.WalkLog(R, args.log_capacity, dev)
+    walk_log = None if args.no_log_compare else rf.WalkLog(R, args.log_capacity, dev)
     ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for k in ("raygen", "pack", "forward", "backward")}
 
-    def step(dt: str, backward: bool, timed: dict = None, use_log: bool = True):
+    def step(dt: str, backward: bool, timed: dict = None, use_log: bool = False):
         def mark(k, i):
             if timed is not None:
                 ev[k][i].record()
 
         mark("raygen", 0)
-        o, d, t, s, _ = rf.raygen(pose, fov, W, H, bound, start, device=dev, with_pixel=False)
+        o, d, t, s = raygen_all()
         mark("raygen", 1)
         mark("pack", 0)
         scenes[dt].pack(sites, dens, sh)
         mark("pack", 1)
         mark("forward", 0)
-        # a training step's forward keeps the walk log for its backward
+        # the logged form's forward keeps the walk log for its backward
         log = walk_log if backward and use_log else None
         rgb, tf, steps = rf.render_forward(scenes[dt], o, d, t, s, out=fwd_out, log=log)
         mark("forward", 1)
@@ -193,7 +218,7 @@ def main() -> int:
                     continue
                 timed.setdefault(k, []).append(ev[k][0].elapsed_time(ev[k][1]))
 
-    def run(dt: str, backward: bool, use_log: bool = True):
+    def run(dt: str, backward: bool, use_log: bool = False):
         for _ in range(args.warmup):
             step(dt, backward, use_log=use_log)
         torch.cuda.synchronize()
@@ -211,21 +236,22 @@ def main() -> int:
             lat.append((time.perf_counter() - a) * 1e3)
         return total / args.steps * 1e3, {k: float(np.mean(v)) for k, v in timed.items()}, lat
 
-    # visits per frame (the work unit of the walk)
+    # visits per batch (the work unit of the walk)
     o, d, t, s = rays
     _, _, steps_fp32 = rf.render_forward(scenes["f32"], o, d, t, s)
     torch.cuda.synchronize()
     steps_np = steps_fp32.cpu().numpy()
     visits = int(np.clip(steps_np, 0, None).sum())
     # mean degree of visited cells, from a traced sample of tiles
-    sample = slice(R // 2 - 8192, R // 2 + 8192)
+    mid = min(R // 2, cam_rows[1] // 2)
+    sample = slice(max(mid - 8192, 0), min(mid + 8192, R))
     tr = rf.render_trace(scenes["f32"], o[sample].contiguous(), d[sample].contiguous(), t[sample].contiguous(),
                          s[sample].contiguous(), max_len=1024)
     cells = tr["cells"].cpu().numpy()
     cells = cells[cells >= 0]
     deg = np.diff(scene.off)
     mean_deg = float(deg[cells].mean())
-    log(f"visits/frame {visits} ({visits / R:.1f} per ray), mean visited degree {mean_deg:.2f}, "
+    log(f"visits/batch {visits} ({visits / R:.1f} per ray), mean visited degree {mean_deg:.2f}, "
         f"flagged rays {(steps_np < 0).sum()}")
 
     if args.copy_calibration:
@@ -237,22 +263,19 @@ def main() -> int:
         log("copy calibration: 1 GiB read + 1 GiB written by one device copy kernel")
         del src, dst
 
+    # forms of the step: the training step with the recomputing backward (the
+    # headline), the forward alone, and the training step whose forward keeps
+    # a walk log that its backward reads
+    forms = [("fwd_bwd", True, False), ("fwd", False, False)]
+    if walk_log is not None:
+        forms.append(("fwd_bwd_logged", True, True))
     results = {}
     for dt in (("f32", "bf16") if args.only is None else (args.only,)):
-        for bwd in (True, False):
-            ms, kern, lat = run(dt, bwd)
-            results[(dt, bwd)] = (ms, kern, lat)
-            log(f"{dt} {'fwd+bwd' if bwd else 'fwd'}: {ms:.3f} ms/step, {R / ms / 1e3:.1f} Mrays/s, "
+        for form, bwd, use_log in forms:
+            ms, kern, lat = run(dt, bwd, use_log)
+            results[(dt, form)] = (ms, kern, lat)
+            log(f"{dt} {form}: {ms:.3f} ms/step, {R / ms / 1e3:.1f} Mrays/s, "
                 f"kernels(ms) {json.dumps({k: round(v, 4) for k, v in kern.items()})}")
-
-    recompute = None
-    if walk_log is not None and not args.no_recompute_compare:
-        # the same training step with the backward recomputing every walk (no walk log)
-        ms_r, kern_r, _ = run("f32" if args.only is None else args.only, True, use_log=False)
-        recompute = {"mrays_s": round(R / ms_r / 1e3, 3), "ms_per_step": round(ms_r, 4),
-                     "backward_ms": round(kern_r["backward"], 4)}
-        log(f"fwd+bwd with the recomputing backward: {ms_r:.3f} ms/step, {R / ms_r / 1e3:.1f} Mrays/s, "
-            f"backward {kern_r['backward']:.3f} ms")
 
     # the colour error BF16-stored attributes introduce, against the FP32-attribute frame
     bf16_err = None
@@ -263,22 +286,50 @@ def main() -> int:
         diff = (c16 - c32).abs()
         scale = float(c32.abs().max())
         bf16_err = {"max_rel": round(float(diff.max()) / scale, 6), "mean_rel": round(float(diff.mean()) / scale, 8),
-                    "p99_rel": round(float(torch.quantile(diff.flatten()[:: 7].float(), 0.99)) / scale, 7)}
+                    "p99_rel": round(float(torch.quantile(diff.flatten()[:: 7][: 1 << 24].float(), 0.99)) / scale, 7)}
         log(f"bf16 colour error against the fp32-attribute frame: max {bf16_err['max_rel']:.2e}, "
             f"p99 {bf16_err['p99_rel']:.2e}, mean {bf16_err['mean_rel']:.2e} of the largest colour")
 
     main_dt = "f32" if args.only is None else args.only
-    dts = [k[0] for k in results if k[1]]
-    ms, kern, lat = results[(main_dt, True)]
+    dts = sorted({k[0] for k in results}, key=lambda x: x != "f32")
+    ms, kern, lat = results[(main_dt, "fwd_bwd")]
     value = R / (ms * 1e-3) / 1e6
-    dominant = max(("forward", "backward"), key=lambda k: kern[k])
-    fl = flops_per_visit(mean_deg, B, dominant if dominant == "forward" or not args.recompute
-                         else "backward_recompute") * visits
-    achieved = fl / (kern[dominant] * 1e-3) / 1e12
 
+    def roofline(dt: str, form: str, kernel: str) -> dict:
+        """HBM roofline of one kernel of a step form: measured DRAM bytes per launch
+        (rocprofv3, when the committed summary matches these kernel sources) over
+        the HIP-event duration; beside it the method's per-visit bytes and flops."""
+        k_ms = results[(dt, form)][1][kernel]
+        kind = {("forward", False): "forward", ("backward", False): "backward_recompute",
+                ("forward", True): "forward", ("backward", True): "backward"}[(kernel, form == "fwd_bwd_logged")]
+        label = {"fwd_bwd": {"forward": "forward", "backward": "backward (recomputing)"},
+                 "fwd": {"forward": "forward", "backward": ""},
+                 "fwd_bwd_logged": {"forward": "forward (logged)", "backward": "backward (log kernel)"}}[form][kernel]
+        traffic = measured_traffic(args.config, dt, label)
+        achieved = traffic / (k_ms * 1e-3) / 1e9 if traffic else None
+        fl = flops_per_visit(mean_deg, B, kind) * visits
+        tf = fl / (k_ms * 1e-3) / 1e12
+        vb = visits * visit_bytes(mean_deg, B, dt, kind)
+        return {"bound": "hbm", "kernel": f"k_{kernel}, {label} ({dt} attributes)", "ms": round(k_ms, 4),
+                "achieved": None if achieved is None else round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic,
+                "visit_bytes": int(vb), "visit_gbs": round(vb / (k_ms * 1e-3) / 1e9, 1),
+                "alu": {"achieved": round(tf, 3), "unit": "TFLOP/s", "peak": FP32_PEAK_TFLOPS,
+                        "frac": round(tf / FP32_PEAK_TFLOPS, 4), "peak_nonpacked": round(VALU_PEAK_TFLOPS, 2),
+                        "frac_nonpacked": round(tf / VALU_PEAK_TFLOPS, 4)}}
+
+    dominant = max(("forward", "backward"), key=lambda k: kern[k])
+    rooflines = {f"{dt}_{form}_{k}": roofline(dt, form, k) for dt in dts for form, bwd, _ in forms
+                 for k in (("forward", "backward") if bwd else ("forward",))}
+
+    workload = (f"{args.config}: {scene.n_sites} sites {synth.CONFIGS[args.config]['kind']}, SH deg {scene.sh_deg}, "
+                f"{len(cams)} x {cams[0].width}x{cams[0].height} camera{'s' if len(cams) > 1 else ''}, "
+                f"raygen+pack+forward+backward (the backward recomputes each walk from the saved colour "
+                f"and transmittance)")
     out = {
-        "metric": "Mrays/s fwd+bwd at 1M sites (FP32 attributes); fwd and BF16 rates and p50/p99 step latency "
-                  "in added fields",
+        "metric": "Mrays/s fwd+bwd at 1M sites (FP32 attributes, recomputing backward); fwd, walk-log and BF16 "
+                  "rates and p50/p99 step latency in added fields",
         "value": round(value, 3),
         "unit": "Mrays/s",
         "n_gpus": 1,
@@ -290,35 +341,30 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded clustered Voronoi scene, Delaunay CSR from Qhull)",
-        "config": {"workload": f"{args.config}: {scene.n_sites} sites {synth.CONFIGS[args.config]['kind']}, SH deg {scene.sh_deg}, "
-                               f"{W}x{H} camera, raygen+pack+forward+backward"
-                               + (" (backward recomputes the walks)" if args.recompute
-                                  else f" (forward logs up to {args.log_capacity} visits per ray for the backward)"),
-                   "rays_per_step": R, "visits_per_step": visits, "mean_visited_degree": round(mean_deg, 3),
-                   "parallelism": "single GPU"},
-        "fwd_mrays_s": {dt: round(R / results[(dt, False)][0] / 1e3, 3) for dt in dts},
-        "fwd_bwd_mrays_s": {dt: round(R / results[(dt, True)][0] / 1e3, 3) for dt in dts},
-        "fwd_bwd_recompute": recompute,
+        "config": {"workload": workload, "rays_per_step": R, "cameras": len(cams), "visits_per_step": visits,
+                   "mean_visited_degree": round(mean_deg, 3), "parallelism": "single GPU"},
+        "fwd_mrays_s": {dt: round(R / results[(dt, "fwd")][0] / 1e3, 3) for dt in dts},
+        "fwd_bwd_mrays_s": {dt: round(R / results[(dt, "fwd_bwd")][0] / 1e3, 3) for dt in dts},
+        "fwd_bwd_logged": ({dt: {"mrays_s": round(R / results[(dt, "fwd_bwd_logged")][0] / 1e3, 3),
+                                 "ms_per_step": round(results[(dt, "fwd_bwd_logged")][0], 4),
+                                 "log_capacity": args.log_capacity,
+                                 "log_bytes": int(R * (12 * args.log_capacity + 16))} for dt in dts}
+                           if walk_log is not None else None),
         "bf16_colour_error": bf16_err,
-        "bf16_speedup_fwd_bwd": (round(results[("f32", True)][0] / results[("bf16", True)][0], 4)
+        "bf16_speedup_fwd_bwd": (round(results[("f32", "fwd_bwd")][0] / results[("bf16", "fwd_bwd")][0], 4)
                                  if len(dts) == 2 else None),
-        "step_latency_ms": {f"{dt}_{'fwd_bwd' if b else 'fwd'}": {
-            "p50": round(float(np.percentile(results[(dt, b)][2], 50)), 4),
-            "p99": round(float(np.percentile(results[(dt, b)][2], 99)), 4)} for dt in dts
-            for b in (True, False)},
-        "kernel_ms": {f"{dt}_{'fwd_bwd' if b else 'fwd'}": {k: round(v, 4) for k, v in results[(dt, b)][1].items()}
-                      for dt in dts for b in (True, False)},
-        # the method's own bytes per visited cell (row offsets, neighbour ids and
-        # positions, the cell's attributes) times visits, over the plain forward's time
-        "effective_visit_gbs": {dt: round(visits * visit_bytes(mean_deg, B, dt) / (results[(dt, False)][1]["forward"]
-                                                                                 * 1e-3) / 1e9, 1) for dt in dts},
-        "roofline": {"bound": "alu", "kernel": f"{dominant} walk ({main_dt} attributes)",
-                     "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s",
-                     "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
-                     "traffic": measured_traffic(dominant, args.config, "fp32" if main_dt == "f32" else main_dt)},
+        "bf16_speedup_fwd": (round(results[("f32", "fwd")][0] / results[("bf16", "fwd")][0], 4)
+                             if len(dts) == 2 else None),
+        "step_latency_ms": {f"{dt}_{form}": {
+            "p50": round(float(np.percentile(results[(dt, form)][2], 50)), 4),
+            "p99": round(float(np.percentile(results[(dt, form)][2], 99)), 4)} for dt in dts
+            for form, _, _ in forms},
+        "kernel_ms": {f"{dt}_{form}": {k: round(v, 4) for k, v in results[(dt, form)][1].items()}
+                      for dt in dts for form, _, _ in forms},
+        "roofline": dict(rooflines[f"{main_dt}_fwd_bwd_{dominant}"]),
+        "rooflines": rooflines,
         "kernel_source_digest": kernel_source_digest(),
     }
-
     if not args.no_serving and args.config == "clustered_1m":
         out["serving"] = serving(rf, scenes, scene, bound, dts)
     if not args.no_locate:
@@ -327,9 +373,9 @@ def main() -> int:
         out["quantile"] = quantile_cost(rf, scenes["f32"], rays, grad_rgb, walk_log, dev, args.steps)
     if not args.no_training:
         out["training"] = training_cost(rf, scene, sites, off, idx, dens, sh, grads, dev, args.steps)
-    if not args.no_effects and walk_log is not None:
-        out["effects"] = effects_cost(rf, scenes["f32"], rays, grad_rgb, walk_log, bound, pose, fov, W, H, start, dev,
-                                      args.steps)
+    if not args.no_effects and walk_log is not None and len(cams) == 1:
+        out["effects"] = effects_cost(rf, scenes["f32"], rays, grad_rgb, walk_log, bound, cam.pose12(), cam.fov_deg,
+                                      cam.width, cam.height, start, dev, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, cam, bound, start, g_np, visits / R, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -16,7 +16,24 @@ from . import _lib as L
 
 DEFAULT_EPS = 1e-4
 DEFAULT_MAX_STEPS = 8192
-DEFAULT_LOG_CAPACITY = 256  # visits per ray saved by a differentiable forward (12 B each)
+# The differentiable forward keeps no walk log by default: its backward
+# recomputes each walk from the saved colour and transmittance. A caller may
+# ask for a log of up to `log_capacity` visits per ray (12 B each); it is cut
+# to what fits in LOG_MEMORY_FRACTION of the free device memory, and walks
+# longer than the log are recomputed by the backward.
+DEFAULT_LOG_CAPACITY = 0
+LOG_MEMORY_FRACTION = 0.5
+
+
+def fitting_log_capacity(n_rays: int, requested: int, device=None) -> int:
+    """The largest walk-log capacity <= ``requested`` whose buffers
+    (n_rays * (12 * capacity + 16) bytes) fit in LOG_MEMORY_FRACTION of the
+    device's free memory (0: no log)."""
+    if requested <= 0 or n_rays <= 0:
+        return 0
+    free, _total = torch.cuda.mem_get_info(device)
+    fit = int((free * LOG_MEMORY_FRACTION - 16 * n_rays) // (12 * n_rays))
+    return max(0, min(int(requested), fit))
 
 
 def _stream(device: Optional[torch.device] = None) -> ctypes.c_void_p:
@@ -146,14 +163,25 @@ def bound_desc(bound: tuple) -> L.BoundDesc:
 
 
 def raygen(pose12, fov_deg: float, width: int, height: int, bound: tuple, start: int,
-           device="cuda", with_pixel: bool = True, model: str = "pinhole"):
-    """Camera rays (pinhole or equidistant fisheye) in 8x8 tile order: (origin, dir, t_max, start_cell, pixel)."""
+           device="cuda", with_pixel: bool = True, model: str = "pinhole", out=None):
+    """Camera rays (pinhole or equidistant fisheye) in 8x8 tile order: (origin, dir, t_max, start_cell, pixel).
+
+    ``out`` = (origin [R,3], dir [R,3], t_max [R], start [R]) writes the rays into
+    existing contiguous tensors (e.g. one camera's rows of a multi-camera batch)."""
     R = int(width) * int(height)
     dev = torch.device(device)
-    o = torch.empty((R, 3), dtype=torch.float32, device=dev)
-    d = torch.empty((R, 3), dtype=torch.float32, device=dev)
-    t = torch.empty(R, dtype=torch.float32, device=dev)
-    s = torch.empty(R, dtype=torch.int32, device=dev)
+    if out is None:
+        o = torch.empty((R, 3), dtype=torch.float32, device=dev)
+        d = torch.empty((R, 3), dtype=torch.float32, device=dev)
+        t = torch.empty(R, dtype=torch.float32, device=dev)
+        s = torch.empty(R, dtype=torch.int32, device=dev)
+    else:
+        o, d, t, s = out
+        _dev(o, torch.float32, (R, 3), "origin")
+        _dev(d, torch.float32, (R, 3), "dir")
+        _dev(t, torch.float32, (R,), "t_max")
+        _dev(s, torch.int32, (R,), "start_cell")
+        dev = o.device
     px = torch.empty(R, dtype=torch.int32, device=dev) if with_pixel else None
     cam = camera_desc(pose12, fov_deg, width, height, model)
     b = bound_desc(bound)
@@ -380,9 +408,10 @@ class RadFoamRender(torch.autograd.Function):
         -> (rgb [R,3], t_final [R], steps [R], quantile_loss [R])
 
     Packs the scene (face planes from the current sites, attributes in
-    ``attr_dtype``), walks every ray, and saves a walk log of the first
-    ``log_capacity`` visits per ray (0: none; the backward then recomputes
-    every walk). With ``quantile_draws`` [R,2] it also returns the quantile
+    ``attr_dtype``) and walks every ray; the backward recomputes each walk
+    from the saved colour and final transmittance. With ``log_capacity`` > 0
+    the forward also saves a walk log of up to that many visits per ray (cut
+    to what fits in free device memory) and the backward reads it instead. With ``quantile_draws`` [R,2] it also returns the quantile
     regulariser |W^-1(u1) - W^-1(u2)| per ray (Sec. 3.4; zeros otherwise).
     With ``surface`` (a ``Surface``) the rays bend at it; the quantile
     regulariser is then not available.
@@ -398,8 +427,9 @@ class RadFoamRender(torch.autograd.Function):
         sites_c, dens_c, sh_c = sites.detach().contiguous(), density.detach().contiguous(), sh.detach().contiguous()
         scene = PackedScene(sites_c, off, idx, dens_c, sh_c, sh_degree, attr_dtype, validate=False)
         R = int(direction.shape[0])
-        want_log = log_capacity > 0 or quantile_draws is not None
-        log = WalkLog(R, max(log_capacity, 0), direction.device) if want_log else None
+        cap = fitting_log_capacity(R, log_capacity, direction.device)
+        want_log = cap > 0 or quantile_draws is not None
+        log = WalkLog(R, cap, direction.device) if want_log else None
         rgb, tf, steps = render_forward(scene, origin, direction, t_max, start, eps, max_steps, log=log,
                                         surface=surface)
         q = None

@@ -205,7 +205,7 @@ def test_bent_autograd_and_errors(setup):
     g = torch.randn_like(rgb)
     (rgb * g).sum().backward()
     p = _packed(rf, scene)
-    log = rf.WalkLog(R, rf.DEFAULT_LOG_CAPACITY, o.device)
+    log = rf.WalkLog(R, 256, o.device)
     rgb2, tf2, _ = rf.render_forward(p, o, d, t, s, log=log, surface=sf)
     assert torch.equal(rgb.detach(), rgb2)
     ref = rf.render_backward(p, o, d, t, s, rgb2, tf2, g, log=log, surface=sf)

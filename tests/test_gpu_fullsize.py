@@ -97,7 +97,7 @@ def test_full_frame_forward_backward(name, dtype):
     print(f"gradient errors (sites, density, sh): {errs}", flush=True)
     assert max(errs) <= GRAD_RTOL
     # the training step as the benchmark times it: logged forward, logged backward
-    log = rf.WalkLog(R, rf.DEFAULT_LOG_CAPACITY, od.device)
+    log = rf.WalkLog(R, 256, od.device)
     rgb_l, tf_l, _ = rf.render_forward(p, od, dd, td, sd, log=log)
     assert torch.equal(rgb_l, rgb_d) and torch.equal(tf_l, tf_d)
     grads = rf.render_backward(p, od, dd, td, sd, rgb_l, tf_l, _dv(gm), log=log)
@@ -210,7 +210,7 @@ def test_bent_full_frame_glass_sphere():
     p = rf.PackedScene(*map(_dv, (scene.sites, scene.off, scene.idx, scene.density, scene.sh)), 3, "f32")
     od, dd, td, sd = map(_dv, (o, d, t, s))
     sf = rf.Surface("glass", (0.0, 0.0, 0.0), radius, bound, ior=1.5, max_bounces=8)
-    log = rf.WalkLog(R, rf.DEFAULT_LOG_CAPACITY, od.device)
+    log = rf.WalkLog(R, 256, od.device)
     rgb, tf, steps = rf.render_forward(p, od, dd, td, sd, log=log, surface=sf)
     torch.cuda.synchronize()
     bent = (log.tail[:, 3] > 0).cpu().numpy()

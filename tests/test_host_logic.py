@@ -87,4 +87,7 @@ def test_bench_accounting():
     # bytes of a visited cell: row offsets, 4 + 12 bytes per face, 49 attributes
     assert bench.visit_bytes(17.0, 16, "f32") == 4 + 16 * 17 + 49 * 4
     assert bench.visit_bytes(17.0, 16, "bf16") == 4 + 16 * 17 + 49 * 2
+    assert bench.visit_bytes(17.0, 16, "f32", "backward_recompute") == 4 + 16 * 17 + 49 * 4 + 52 * 4
+    assert bench.visit_bytes(17.0, 16, "bf16", "backward") == 24 + 49 * 2 + 52 * 4
     assert bench.VALU_PEAK_TFLOPS == pytest.approx(78.64, rel=1e-3)
+    assert bench.FP32_PEAK_TFLOPS == 157.3
