@@ -61,9 +61,10 @@ def kernel_source_digest() -> str:
 
 def measured_traffic(workload: str, dtype: str, label: str):
     """HBM bytes per launch (read + written) of the launch `label` (e.g.
-    "backward (recomputing)") from the committed rocprofv3 PMC summary of
-    `workload` and `dtype`, or None if there is none for these kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"walk_kernels_{workload}_{dtype}_hbm_traffic.md")
+    "backward (recomputing)") with `dtype` attributes, from the committed
+    rocprofv3 PMC summary of `workload`, or None if there is none for these
+    kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"walk_kernels_{workload}_hbm_traffic.md")
     if not label or not os.path.exists(path):
         return None
     text = open(path).read()
@@ -72,8 +73,8 @@ def measured_traffic(workload: str, dtype: str, label: str):
         return None
     kernel, _, rest = label.partition(" ")
     rest = rest.strip("()") or kernel
-    m = re.search(rf"^\| k_{kernel} \| {re.escape(rest)} \| \d+ \| [0-9.]+ \| [0-9.]+ \| ([0-9.]+) \| ([0-9.]+) \|",
-                  text, re.M)
+    m = re.search(rf"^\| k_{kernel} \| {re.escape(rest)} \| {dtype} \| \d+ \| [0-9.]+ \| [0-9.]+ \| ([0-9.]+) \| "
+                  rf"([0-9.]+) \|", text, re.M)
     if not m:
         return None
     return int(round((float(m.group(1)) + float(m.group(2))) * 1e6))
@@ -128,6 +129,9 @@ def main() -> int:
     ap.add_argument("--no-training", action="store_true", help="skip the optimizer / densification timing")
     ap.add_argument("--no-log-compare", action="store_true",
                     help="skip timing the training step whose backward reads a walk log")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="time only the headline step once (no BF16, no forward-only or logged forms) before the "
+                         "added measurements (serving, location, ...); for profiling those")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -269,6 +273,9 @@ def main() -> int:
     forms = [("fwd_bwd", True, False), ("fwd", False, False)]
     if walk_log is not None:
         forms.append(("fwd_bwd_logged", True, True))
+    if args.extras_only:
+        forms = [("fwd_bwd", True, False), ("fwd", False, False)]
+        args.only = args.only or "f32"
     results = {}
     for dt in (("f32", "bf16") if args.only is None else (args.only,)):
         for form, bwd, use_log in forms:

@@ -220,8 +220,16 @@ rf_status rf_render_forward(const rf_packed_scene *scene, const rf_rays *rays, c
  * Backward walk: gradients of L = sum_r grad_rgb[r].rgb[r] + grad_t_final[r] T[r]
  * (Sec. 3.1: geometry receives gradients only through the segment widths).
  * The walk is recomputed from the inputs (rf_render_backward_logged reads
- * it from a walk log instead); rgb and t_final must be the outputs of
+ * it from a walk log instead); rgb, t_final and steps must be the outputs of
  * rf_render_forward for the same scene, rays and params.
+ *   steps         int32[n_rays]        nullable: the forward's steps
+ *   mismatches    int32[1]             nullable, device: incremented (atomically)
+ *                                      once for every ray whose recomputed walk
+ *                                      ends with a final transmittance that
+ *                                      differs from t_final (bitwise) or, when
+ *                                      steps is given, a visit count or status
+ *                                      that differs from steps; 0 after a
+ *                                      consistent call (the caller zeroes it)
  *   grad_rgb      float[n_rays][3]
  *   grad_t_final  float[n_rays]        nullable (treated as 0)
  *   grad_sites    float[n_sites][3]    ACCUMULATED (+=); caller zeroes
@@ -233,9 +241,9 @@ rf_status rf_render_forward(const rf_packed_scene *scene, const rf_rays *rays, c
  * per cell before the atomics (default), 1 = one atomic per lane and value.
  * ---------------------------------------------------------------------- */
 rf_status rf_render_backward(const rf_packed_scene *scene, const rf_rays *rays, const rf_params *params,
-                             const float *rgb, const float *t_final, const float *grad_rgb,
+                             const float *rgb, const float *t_final, const int32_t *steps, const float *grad_rgb,
                              const float *grad_t_final, float *grad_sites, float *grad_density, float *grad_sh,
-                             int32_t mode, void *stream);
+                             int32_t mode, int32_t *mismatches, void *stream);
 
 /* ------------------------------------------------------------------------
  * Start-cell location: the cell containing each point, i.e. its nearest
@@ -468,6 +476,7 @@ rf_status rf_sample_cells(const float *scores, int64_t n, const float *draws, in
                           void *workspace, size_t workspace_bytes, void *stream);
 rf_status rf_prune_mask(const float *density, const int32_t *nbr_off, const int32_t *nbr_idx, int64_t n_sites,
                         float threshold, uint8_t *mask, void *stream);
+
 
 /* Copies the packed face planes (float4 per directed edge, CSR order) into
  * planes[n_edges][4]; for tests of the packing step. */

@@ -19,6 +19,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# a sanitizer build of the same source (see build_sanitized); the tests run the
+# pins against it in a child process that preloads the ASan runtime
+_SAN_LIB_PATH = os.path.join(_HERE, "liboracle_san.so")
+if os.environ.get("ORACLE_SANITIZED") == "1":
+    _LIB_PATH = _SAN_LIB_PATH
 
 BAD_START = -1
 MAX_STEPS = -2
@@ -34,6 +39,17 @@ def build(force: bool = True) -> str:
                                "-D_GNU_SOURCE", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+def build_sanitized() -> str:
+    """Compile oracle.c with AddressSanitizer and UndefinedBehaviorSanitizer
+    (every UB report aborts) into liboracle_san.so, for the sanitizer test."""
+    tmp = _SAN_LIB_PATH + f".tmp{os.getpid()}"
+    subprocess.check_call(["gcc", "-std=c11", "-O1", "-g", "-fPIC", "-shared", "-pthread", "-D_GNU_SOURCE",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                           "-fno-omit-frame-pointer", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _SAN_LIB_PATH)
+    return _SAN_LIB_PATH
 
 
 class _Surface(ctypes.Structure):
@@ -74,7 +90,10 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        if _LIB_PATH == _SAN_LIB_PATH:
+            if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+                build_sanitized()
+        elif not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
             build()
         lib = ctypes.CDLL(_LIB_PATH)
         P = ctypes.c_void_p
@@ -93,7 +112,10 @@ def _load():
         lib.orc_trace.argtypes = [ctypes.POINTER(_Scene), P, P, P, P, ctypes.c_int64, ctypes.c_double,
                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int, P, P, P, P, P, P, P, P, P, P, P, P, P]
         lib.orc_backward.argtypes = [ctypes.POINTER(_Scene), P, P, P, P, ctypes.c_int64, ctypes.c_double,
-                                     ctypes.c_int32, P, P, ctypes.c_int, P, P, P]
+                                     ctypes.c_int32, P, P, ctypes.c_int, P, P, P, P, P, P]
+        lib.orc_walk_forced.argtypes = [ctypes.POINTER(_Scene), P, P, P, P, ctypes.c_int64, P, ctypes.c_int64, P, P,
+                                        P, ctypes.c_double, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int, P, P, P, P, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -276,9 +298,17 @@ def trace(scene: OracleScene, o, d, tmax, start, eps: float = DEFAULT_EPS,
 
 
 def backward(scene: OracleScene, o, d, tmax, start, grad_rgb, grad_t=None, eps: float = DEFAULT_EPS,
-             max_steps: int = DEFAULT_MAX_STEPS, threads: Optional[int] = None):
-    """Gradients (sites [N,3], density [N], sh [N,B,3]) of sum(grad_rgb*rgb) + sum(grad_t*T)."""
+             max_steps: int = DEFAULT_MAX_STEPS, threads: Optional[int] = None, forced=None):
+    """Gradients (sites [N,3], density [N], sh [N,B,3]) of sum(grad_rgb*rgb) + sum(grad_t*T).
+
+    ``forced`` (optional): per ray a list of (visit, choice) pairs in walk
+    order (see ``walk_forced``); each ray then walks with those choices."""
     o, d, t, s, R = _rays(o, d, tmax, start)
+    f_off = f_visit = f_choice = None
+    if forced is not None:
+        if len(forced) != R:
+            raise ValueError("forced needs one list per ray")
+        f_off, f_visit, f_choice = _pack_forced(forced)
     g = _f64(grad_rgb).reshape(R, 3)
     gt = None if grad_t is None else _f64(grad_t).reshape(R)
     n = scene.n_sites
@@ -287,8 +317,100 @@ def backward(scene: OracleScene, o, d, tmax, start, grad_rgb, grad_t=None, eps: 
     gsh = np.zeros((n, scene.B, 3))
     _check(_load().orc_backward(ctypes.byref(scene._c), _ptr(o), _ptr(d), _ptr(t), _ptr(s), R, float(eps),
                                 int(max_steps), _ptr(g), _ptr(gt), threads or default_threads(),
-                                _ptr(gs), _ptr(gd), _ptr(gsh)), "backward")
+                                _ptr(gs), _ptr(gd), _ptr(gsh), _ptr(f_off), _ptr(f_visit), _ptr(f_choice)),
+           "backward")
     return gs, gd, gsh
+
+
+# Choice codes of a decision (besides a neighbour id: leave through the face to it).
+CH_CLIP = -3  # the ray ends in this cell at t_max
+CH_STOP = -4  # the transmittance test before the visit fails
+CH_GO = -5    # the transmittance test before the visit passes
+
+
+def _pack_forced(forced):
+    f_off = np.zeros(len(forced) + 1, dtype=np.int64)
+    f_off[1:] = np.cumsum([len(f) for f in forced])
+    flat = [c for f in forced for c in f]
+    f_visit = np.ascontiguousarray(np.array([v for v, _ in flat] or [0], dtype=np.int32))
+    f_choice = np.ascontiguousarray(np.array([c for _, c in flat] or [0], dtype=np.int32))
+    return f_off, f_visit, f_choice
+
+
+def walk_forced(scene: OracleScene, o, d, tmax, start, ray_idx, forced, eps: float = DEFAULT_EPS,
+                max_steps: int = DEFAULT_MAX_STEPS, kappa_t: float = 0.0, kappa_T: float = 0.0,
+                max_len: int = 1024, nt_cap: int = 16, threads: Optional[int] = None) -> dict:
+    """Walks of rays ``ray_idx`` (jobs) with the forced choices ``forced`` (per
+    job a list of (visit, choice) in walk order; a decision is the
+    transmittance test before visit n, choice CH_STOP or CH_GO, or the exit of
+    visit n, a neighbour id or CH_CLIP). Returns per job the colour,
+    transmittance, status, cells, visit count, and the near ties after its
+    last forced decision: decisions whose exact winner is within kappa_t
+    (faces and t_max, in the decision-margin units of ``trace``) or kappa_T
+    (|ln T - ln eps|) of an alternative, as (visit, alternative choice) pairs
+    (``nt_len`` -1: more than ``nt_cap``); ``bad`` flags a forced choice that
+    was not available."""
+    o, d, t, s, R = _rays(o, d, tmax, start)
+    idx = np.ascontiguousarray(np.asarray(ray_idx, dtype=np.int32))
+    J = len(idx)
+    f_off, f_visit, f_choice = _pack_forced(forced)
+    out = dict(rgb=np.empty((J, 3)), t_final=np.empty(J), steps=np.empty(J, dtype=np.int32),
+               cells=np.full((J, max_len), -1, dtype=np.int32), len=np.empty(J, dtype=np.int32),
+               nt_visit=np.zeros((J, max(nt_cap, 1)), dtype=np.int32),
+               nt_choice=np.zeros((J, max(nt_cap, 1)), dtype=np.int32), nt_len=np.empty(J, dtype=np.int32),
+               bad=np.empty(J, dtype=np.int32))
+    _check(_load().orc_walk_forced(ctypes.byref(scene._c), _ptr(o), _ptr(d), _ptr(t), _ptr(s), R, _ptr(idx), J,
+                                   _ptr(f_off), _ptr(f_visit), _ptr(f_choice), float(eps), int(max_steps),
+                                   float(kappa_t), float(kappa_T), int(max_len), int(nt_cap),
+                                   threads or default_threads(),
+                                   *[_ptr(out[k]) for k in ("rgb", "t_final", "steps", "cells", "len", "nt_visit",
+                                                            "nt_choice", "nt_len", "bad")]), "walk_forced")
+    return out
+
+
+def alternatives(scene: OracleScene, o, d, tmax, start, ray_idx, kappa_t: float, kappa_T: float,
+                 eps: float = DEFAULT_EPS, max_steps: int = DEFAULT_MAX_STEPS, max_len: int = 1024,
+                 max_leaves: int = 32, threads: Optional[int] = None) -> dict:
+    """Every walk of rays ``ray_idx`` that takes, at each near tie (see
+    ``walk_forced``), the exact winner or one of its near alternatives: the
+    walks a computation whose face and transmittance decisions err only
+    within kappa_t / kappa_T may produce. Searched level by level (walks with
+    k forced choices, then k + 1); a ray with more than ``max_leaves`` such
+    walks, or with more near ties on one walk than can be listed, is marked
+    ``complete`` False. Returns per ray a list of leaves, each a dict (forced,
+    cells, len, rgb, t_final, steps), the exact walk first."""
+    idx = np.asarray(ray_idx, dtype=np.int64)
+    leaves = [[] for _ in idx]
+    complete = np.ones(len(idx), dtype=bool)
+    pending = [(q, []) for q in range(len(idx))]
+    while pending:
+        jobs = [q for q, _ in pending]
+        forced = [f for _, f in pending]
+        w = walk_forced(scene, o, d, tmax, start, idx[jobs], forced, eps=eps, max_steps=max_steps, kappa_t=kappa_t,
+                        kappa_T=kappa_T, max_len=max_len, nt_cap=16, threads=threads)
+        nxt = []
+        for k, (q, f) in enumerate(pending):
+            if w["bad"][k]:
+                complete[q] = False
+                continue
+            L = int(w["len"][k])
+            leaves[q].append(dict(forced=f, cells=w["cells"][k, :min(L, max_len)].copy(), len=L,
+                                  rgb=w["rgb"][k].copy(), t_final=float(w["t_final"][k]), steps=int(w["steps"][k])))
+            n_nt = int(w["nt_len"][k])
+            if n_nt < 0 or L > max_len:
+                complete[q] = False
+                continue
+            for m in range(n_nt):
+                nxt.append((q, f + [(int(w["nt_visit"][k, m]), int(w["nt_choice"][k, m]))]))
+        pending = []
+        queued = {}
+        for q, f in nxt:
+            if len(leaves[q]) + queued.get(q, 0) >= max_leaves:
+                complete[q] = False
+                continue
+            queued[q] = queued.get(q, 0) + 1
+            pending.append((q, f))
+    return dict(leaves=leaves, complete=complete)
 
 
 def quantile(scene: OracleScene, o, d, tmax, start, u, grad_loss=None, eps: float = DEFAULT_EPS,

@@ -328,6 +328,42 @@ typedef struct {
                         site gradient, which divides by the exit face's n.d) */
 } margins_t;
 
+/* Decisions of a walk that FP32 arithmetic may take either way, and walks
+ * that take a given alternative at such a decision.
+ *
+ * A decision is identified by its visit n and its kind: the transmittance
+ * test before visit n (kind 0), or the choice of the exit of visit n (kind
+ * 1) among the front faces and the end of the ray at t_max. A choice code is
+ * a neighbour id (leave through the face to it), ORC_CH_CLIP (the ray ends
+ * in this cell at t_max), ORC_CH_STOP or ORC_CH_GO (the transmittance test
+ * fails or passes). A decision is a near tie when the exact winner's margin
+ * to an alternative is below kappa_t (faces and t_max, in the units of the
+ * margin below) or kappa_T (|ln T - ln eps|). */
+#define ORC_CH_CLIP (-3)
+#define ORC_CH_STOP (-4)
+#define ORC_CH_GO (-5)
+
+typedef struct {
+    const int32_t *f_visit, *f_choice; /* forced choices, in walk order */
+    int32_t nf;
+    double kappa_t, kappa_T;
+    int32_t *nt_visit, *nt_choice; /* near ties after the last forced decision (alternatives to the exact choice) */
+    int32_t nt_cap, nt_len;        /* nt_len = -1: more than nt_cap */
+    int bad;                       /* a forced choice was not available */
+} walk_ctl;
+
+static void note_tie(walk_ctl *c, int32_t n, int32_t choice)
+{
+    if (c->nt_len < 0) return;
+    if (c->nt_len == c->nt_cap) {
+        c->nt_len = -1;
+        return;
+    }
+    c->nt_visit[c->nt_len] = n;
+    c->nt_choice[c->nt_len] = choice;
+    ++c->nt_len;
+}
+
 static void push_visit(visit_buf *b, const visit_t *v)
 {
     if (b->len == b->cap) {
@@ -397,8 +433,15 @@ static int surface_turn(const orc_surface *sf, const double p[3], const double d
 /* Walks one ray. Returns the status code written to steps[]. */
 static int32_t walk_ray(const orc_scene *s, const double o[3], const double d[3], double tmax, int32_t start,
                         double eps, int32_t max_steps, double rgb[3], double *t_final,
-                        visit_buf *rec, margins_t *mg)
+                        visit_buf *rec, margins_t *mg, walk_ctl *ctl)
 {
+    /* position of a decision in walk order: 2 n + kind */
+    int32_t fi = 0;
+    const int64_t last_forced =
+        (ctl && ctl->nf > 0)
+            ? 2 * (int64_t)ctl->f_visit[ctl->nf - 1] +
+                  ((ctl->f_choice[ctl->nf - 1] == ORC_CH_STOP || ctl->f_choice[ctl->nf - 1] == ORC_CH_GO) ? 0 : 1)
+            : -1;
     const int B = sh_count(s->sh_deg);
     double Y[16];
     rgb[0] = rgb[1] = rgb[2] = 0.0;
@@ -432,7 +475,17 @@ static int32_t walk_ray(const orc_scene *s, const double o[3], const double d[3]
     for (;;) {
         if (!cont) {
             if (mg && eps > 0.0) mg->term = fmin(mg->term, fabs(log(T) - log(eps)));
-            if (!(T > eps)) break;
+            int stop = !(T > eps);
+            if (ctl) {
+                if (fi < ctl->nf && ctl->f_visit[fi] == n &&
+                    (ctl->f_choice[fi] == ORC_CH_STOP || ctl->f_choice[fi] == ORC_CH_GO)) {
+                    stop = ctl->f_choice[fi] == ORC_CH_STOP;
+                    ++fi;
+                } else if (2 * (int64_t)n > last_forced && eps > 0.0 && fabs(log(T) - log(eps)) < ctl->kappa_T) {
+                    note_tie(ctl, n, stop ? ORC_CH_GO : ORC_CH_STOP);
+                }
+            }
+            if (stop) break;
         }
         cont = 0;
         if (n == max_steps) {
@@ -445,6 +498,7 @@ static int32_t walk_ray(const orc_scene *s, const double o[3], const double d[3]
         int32_t inext = -1;
         /* nearest front face; runner-ups are kept for the decision margins */
         double cand_t[512], cand_cos[512];
+        int32_t cand_j[512];
         int ncand = 0, win = -1;
         for (int32_t k = s->off[i]; k < s->off[i + 1]; ++k) {
             const int32_t j = s->idx[k];
@@ -462,9 +516,10 @@ static int32_t walk_ray(const orc_scene *s, const double o[3], const double d[3]
                 continue;
             }
             const double t = dot3(nv, mo) / den;
-            if (mg && ncand < 512) {
+            if ((mg || ctl) && ncand < 512) {
                 cand_t[ncand] = t;
                 cand_cos[ncand] = den / nlen;
+                cand_j[ncand] = j;
                 ++ncand;
             }
             if (t < t1) {
@@ -476,7 +531,49 @@ static int32_t walk_ray(const orc_scene *s, const double o[3], const double d[3]
             }
         }
 
-        double te = fmax(t0, fmin(t1, tmax));
+        /* near ties of this exit, and a forced choice */
+        int force_clip = 0;
+        if (ctl) {
+            const int64_t pos = 2 * (int64_t)n + 1;
+            if (fi < ctl->nf && ctl->f_visit[fi] == n && ctl->f_choice[fi] != ORC_CH_STOP &&
+                ctl->f_choice[fi] != ORC_CH_GO) {
+                const int32_t c = ctl->f_choice[fi++];
+                if (c == ORC_CH_CLIP) {
+                    force_clip = 1;
+                } else {
+                    int q = 0;
+                    while (q < ncand && cand_j[q] != c) ++q;
+                    if (q < ncand) {
+                        /* leave through the face to c; its den as the scan computed it */
+                        double nv[3];
+                        for (int a = 0; a < 3; ++a) nv[a] = s->sites[3 * (int64_t)c + a] - x[a];
+                        t1 = cand_t[q];
+                        inext = c;
+                        den1 = dot3(nv, ld);
+                        nlen1 = sqrt(dot3(nv, nv));
+                        win = q;
+                        /* the face taken instead of the end of the ray: its exit lies at t_max */
+                        if (t1 >= tmax) t1 = nextafter(tmax, -INFINITY);
+                    } else {
+                        ctl->bad = 1;
+                    }
+                }
+            } else if (pos > last_forced && inext >= 0) {
+                const double scale = scale0 + fabs(t1);
+                const double cos1 = den1 / nlen1;
+                if (t1 < tmax) {
+                    for (int q = 0; q < ncand; ++q) {
+                        if (q == win || !(cand_t[q] < tmax)) continue;
+                        if ((cand_t[q] - t1) / (scale * (1.0 / cos1 + 1.0 / cand_cos[q])) < ctl->kappa_t)
+                            note_tie(ctl, n, cand_j[q]);
+                    }
+                    if ((tmax - t1) * cos1 / scale < ctl->kappa_t) note_tie(ctl, n, ORC_CH_CLIP);
+                } else if ((t1 - tmax) * cos1 / scale < ctl->kappa_t) {
+                    note_tie(ctl, n, inext);
+                }
+            }
+        }
+        double te = force_clip ? fmax(t0, tmax) : fmax(t0, fmin(t1, tmax));
         /* the leg crosses the surface inside this cell */
         const int bounce = ts < te;
         if (mg && sf && isfinite(ts)) {
@@ -493,7 +590,7 @@ static int32_t walk_ray(const orc_scene *s, const double o[3], const double d[3]
             for (int ch = 0; ch < 3; ++ch) c[ch] += s->sh[(3 * (int64_t)B) * i + 3 * b + ch] * Y[b];
         for (int ch = 0; ch < 3; ++ch) rgb[ch] += T * alpha * c[ch];
 
-        const int clipped = !bounce && ((inext < 0) || (t1 >= tmax));
+        const int clipped = !bounce && ((inext < 0) || (t1 >= tmax) || force_clip);
         if (mg && inext >= 0 && !bounce) {
             const double scale = scale0 + fabs(t1);
             const double cos1 = den1 / nlen1;
@@ -650,6 +747,13 @@ typedef struct {
     /* quantile regulariser */
     const double *u, *grad_loss;
     double *tq, *loss;
+    /* forced choices (per ray, or per job of orc_walk_forced) and near ties */
+    const int32_t *ray_idx;
+    const int64_t *f_off;
+    const int32_t *f_visit, *f_choice;
+    double kappa_t, kappa_T;
+    int32_t nt_cap;
+    int32_t *nt_visit, *nt_choice, *nt_len, *bad;
     int status;
 } job_t;
 
@@ -681,7 +785,7 @@ static void *forward_worker(void *arg)
         const int tracing = j->cells != NULL;
         buf.len = 0;
         j->steps[r] = walk_ray(j->s, j->o + 3 * r, j->d + 3 * r, j->tmax[r], j->start[r], j->eps, j->max_steps,
-                               j->rgb + 3 * r, j->t_final + r, tracing ? &buf : NULL, tracing ? &mg : NULL);
+                               j->rgb + 3 * r, j->t_final + r, tracing ? &buf : NULL, tracing ? &mg : NULL, NULL);
         if (tracing) {
             const int64_t L = buf.len < j->max_len ? buf.len : j->max_len;
             for (int64_t n = 0; n < L; ++n) {
@@ -713,11 +817,51 @@ static void *backward_worker(void *arg)
     for (int64_t r = j->r0; r < j->r1; ++r) {
         double rgb[3], tf;
         buf.len = 0;
+        walk_ctl ctl;
+        memset(&ctl, 0, sizeof ctl);
+        if (j->f_off) {
+            ctl.f_visit = j->f_visit + j->f_off[r];
+            ctl.f_choice = j->f_choice + j->f_off[r];
+            ctl.nf = (int32_t)(j->f_off[r + 1] - j->f_off[r]);
+            ctl.nt_len = -1; /* nothing recorded */
+        }
         const int32_t st = walk_ray(j->s, j->o + 3 * r, j->d + 3 * r, j->tmax[r], j->start[r], j->eps, j->max_steps,
-                                    rgb, &tf, &buf, NULL);
+                                    rgb, &tf, &buf, NULL, j->f_off ? &ctl : NULL);
         if (st == ORC_BAD_START) continue;
         const double gT = j->grad_t ? j->grad_t[r] : 0.0;
         ray_gradient(j->s, buf.v, buf.len, tf, j->grad_rgb + 3 * r, gT, j->gsites, j->gdens, j->gsh);
+    }
+    free(buf.v);
+    return NULL;
+}
+
+/* Walks of orc_walk_forced: job q walks ray ray_idx[q] with the forced
+ * choices f_visit/f_choice[f_off[q] .. f_off[q+1]) and records its cells and
+ * the near ties after the last forced decision. */
+static void *forced_worker(void *arg)
+{
+    job_t *j = (job_t *)arg;
+    visit_buf buf = {0, 0, 0};
+    for (int64_t q = j->r0; q < j->r1; ++q) {
+        const int64_t r = j->ray_idx[q];
+        walk_ctl ctl;
+        memset(&ctl, 0, sizeof ctl);
+        ctl.f_visit = j->f_visit + j->f_off[q];
+        ctl.f_choice = j->f_choice + j->f_off[q];
+        ctl.nf = (int32_t)(j->f_off[q + 1] - j->f_off[q]);
+        ctl.kappa_t = j->kappa_t;
+        ctl.kappa_T = j->kappa_T;
+        ctl.nt_visit = j->nt_visit + q * j->nt_cap;
+        ctl.nt_choice = j->nt_choice + q * j->nt_cap;
+        ctl.nt_cap = j->nt_cap;
+        buf.len = 0;
+        j->steps[q] = walk_ray(j->s, j->o + 3 * r, j->d + 3 * r, j->tmax[r], j->start[r], j->eps, j->max_steps,
+                               j->rgb + 3 * q, j->t_final + q, &buf, NULL, &ctl);
+        const int64_t L = buf.len < j->max_len ? buf.len : j->max_len;
+        for (int64_t n = 0; n < L; ++n) j->cells[q * j->max_len + n] = buf.v[n].cell;
+        j->len[q] = (int32_t)buf.len;
+        j->nt_len[q] = ctl.nt_len;
+        j->bad[q] = ctl.bad;
     }
     free(buf.v);
     return NULL;
@@ -807,7 +951,7 @@ static void *quantile_worker(void *arg)
         int64_t k[2];
         buf.len = 0;
         const int32_t st = walk_ray(j->s, j->o + 3 * r, j->d + 3 * r, j->tmax[r], j->start[r], j->eps, j->max_steps,
-                                    rgb, &tf, &buf, NULL);
+                                    rgb, &tf, &buf, NULL, NULL);
         for (int q = 0; q < 2; ++q) {
             k[q] = st == ORC_BAD_START ? -1 : quantile_point(j->s, buf.v, buf.len, j->u[2 * r + q], &t[q]);
             if (k[q] < 0) t[q] = 0.0;
@@ -920,10 +1064,59 @@ int orc_trace(const orc_scene *s, const double *o, const double *d, const double
     return run_jobs(&j, n_rays, nthreads, forward_worker, 0);
 }
 
-/* Gradients are accumulated (+=) into the caller's buffers. */
+/* Walks of rays with forced choices (see walk_ctl): job q walks ray
+ * ray_idx[q] taking the choices f_visit/f_choice[f_off[q] .. f_off[q+1]) (in
+ * walk order) and reports its colour, transmittance, status, cells (the
+ * first max_len) and visit count, the near ties after its last forced
+ * decision (up to nt_cap; nt_len = -1 if more) and whether a forced choice was
+ * not available (bad). */
+int orc_walk_forced(const orc_scene *s, const double *o, const double *d, const double *tmax, const int32_t *start,
+                    int64_t n_rays, const int32_t *ray_idx, int64_t n_jobs, const int64_t *f_off,
+                    const int32_t *f_visit, const int32_t *f_choice, double eps, int32_t max_steps, double kappa_t,
+                    double kappa_T, int32_t max_len, int32_t nt_cap, int nthreads, double *rgb, double *t_final,
+                    int32_t *steps, int32_t *cells, int32_t *len, int32_t *nt_visit, int32_t *nt_choice,
+                    int32_t *nt_len, int32_t *bad)
+{
+    if (check_inputs(s, d, n_rays) != ORC_OK || max_steps < 1 || max_len < 1 || nt_cap < 0 || n_jobs < 0)
+        return ORC_EINVAL;
+    for (int64_t q = 0; q < n_jobs; ++q)
+        if (ray_idx[q] < 0 || ray_idx[q] >= n_rays || f_off[q + 1] < f_off[q]) return ORC_EINVAL;
+    job_t j;
+    memset(&j, 0, sizeof j);
+    j.s = s;
+    j.o = o;
+    j.d = d;
+    j.tmax = tmax;
+    j.start = start;
+    j.eps = eps;
+    j.max_steps = max_steps;
+    j.ray_idx = ray_idx;
+    j.f_off = f_off;
+    j.f_visit = f_visit;
+    j.f_choice = f_choice;
+    j.kappa_t = kappa_t;
+    j.kappa_T = kappa_T;
+    j.max_len = max_len;
+    j.nt_cap = nt_cap;
+    j.rgb = rgb;
+    j.t_final = t_final;
+    j.steps = steps;
+    j.cells = cells;
+    j.len = len;
+    j.nt_visit = nt_visit;
+    j.nt_choice = nt_choice;
+    j.nt_len = nt_len;
+    j.bad = bad;
+    return run_jobs(&j, n_jobs, nthreads, forced_worker, 0);
+}
+
+/* Gradients are accumulated (+=) into the caller's buffers. With f_off
+ * (nullable) ray r takes the forced choices f_visit/f_choice[f_off[r] ..
+ * f_off[r+1]) (see orc_walk_forced). */
 int orc_backward(const orc_scene *s, const double *o, const double *d, const double *tmax, const int32_t *start,
                  int64_t n_rays, double eps, int32_t max_steps, const double *grad_rgb, const double *grad_t,
-                 int nthreads, double *grad_sites, double *grad_density, double *grad_sh)
+                 int nthreads, double *grad_sites, double *grad_density, double *grad_sh, const int64_t *f_off,
+                 const int32_t *f_visit, const int32_t *f_choice)
 {
     if (check_inputs(s, d, n_rays) != ORC_OK || max_steps < 1) return ORC_EINVAL;
     job_t j;
@@ -940,6 +1133,9 @@ int orc_backward(const orc_scene *s, const double *o, const double *d, const dou
     j.gsites = grad_sites;
     j.gdens = grad_density;
     j.gsh = grad_sh;
+    j.f_off = f_off;
+    j.f_visit = f_visit;
+    j.f_choice = f_choice;
     return run_jobs(&j, n_rays, nthreads, backward_worker, 1);
 }
 

@@ -127,7 +127,7 @@ def lib() -> ctypes.CDLL:
         L.rf_render_trace.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Rays),
                                       ctypes.POINTER(Params), ctypes.c_int32, P, P, P, P, P, P]
         L.rf_render_backward.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Rays),
-                                         ctypes.POINTER(Params), P, P, P, P, P, P, P, ctypes.c_int32, P]
+                                         ctypes.POINTER(Params), P, P, P, P, P, P, P, P, ctypes.c_int32, P, P]
         L.rf_render_forward_logged.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Rays),
                                                ctypes.POINTER(Params), P, P, P, ctypes.POINTER(WalkLog), P]
         L.rf_render_backward_logged.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Rays),

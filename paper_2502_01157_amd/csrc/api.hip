@@ -284,8 +284,9 @@ rf_status rf_render_trace(const rf_packed_scene* scene, const rf_rays* rays, con
 }
 
 rf_status rf_render_backward(const rf_packed_scene* scene, const rf_rays* rays, const rf_params* params,
-                             const float* rgb, const float* t_final, const float* grad_rgb, const float* grad_t_final,
-                             float* grad_sites, float* grad_density, float* grad_sh, int32_t mode, void* stream)
+                             const float* rgb, const float* t_final, const int32_t* steps, const float* grad_rgb,
+                             const float* grad_t_final, float* grad_sites, float* grad_density, float* grad_sh,
+                             int32_t mode, int32_t* mismatches, void* stream)
 {
     rf_status st;
     if ((st = check_packed(scene)) != RF_OK || (st = check_rays(rays)) != RF_OK || (st = check_params(params)) != RF_OK)
@@ -299,6 +300,8 @@ rf_status rf_render_backward(const rf_packed_scene* scene, const rf_rays* rays, 
     a.t_final_in = t_final;
     a.grad_rgb = grad_rgb;
     a.grad_t = grad_t_final;
+    a.steps_in = steps;
+    a.mismatch = mismatches;
     a.g_sites = grad_sites;
     a.g_density = grad_density;
     a.g_sh = grad_sh;

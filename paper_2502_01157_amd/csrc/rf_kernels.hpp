@@ -52,6 +52,8 @@ struct WalkArgs {
     const float* t_final_in;
     const float* grad_rgb;
     const float* grad_t;
+    const int32_t* steps_in;  // the forward's steps (nullable), checked against the recomputed walk
+    int32_t* mismatch;        // counts rays whose recomputed walk disagrees with the saved outputs (nullable)
     float* g_sites;
     float* g_density;
     float* g_sh;

@@ -69,15 +69,17 @@ struct RayResult {
 // through m = x_i + n/2 with normal n (the stored n = x_j - x_i), so that
 // t = n.(m - o) / n.d is formed from differences of nearby points instead of
 // the FP32 offset c - n.o, whose cancellation costs ~eps32 (|o| + t)/cos.
-__device__ inline double exit_distance(float4 p, const float* site, float ox, float oy, float oz, float dx, float dy,
-                                       float dz)
+// The ray is taken in double: a caller's FP32 ray widened exactly, or a
+// secondary leg kept in double (see Leg).
+__device__ inline double exit_distance(float4 p, const float* site, double ox, double oy, double oz, double dx,
+                                       double dy, double dz)
 {
     const double nx = p.x, ny = p.y, nz = p.z;
     const double mx = fma(0.5, nx, (double)site[0]) - (double)ox;
     const double my = fma(0.5, ny, (double)site[1]) - (double)oy;
     const double mz = fma(0.5, nz, (double)site[2]) - (double)oz;
     const double num = fma(nz, mz, fma(ny, my, nx * mx));
-    const double den = fma(nz, (double)dz, fma(ny, (double)dy, nx * (double)dx));
+    const double den = fma(nz, dz, fma(ny, dy, nx * dx));
     return num / den;
 }
 
@@ -107,9 +109,12 @@ __device__ inline void segment(double t0, const float* Y, Visit<DEG>& v)
     colour<DEG>(v.at, Y, v.c);
 }
 
+// `hi` (nullable): the ray in double, {o, d, t_max}, for the exit distance and
+// the clipping of a secondary leg; the face decision always uses the FP32 ray.
 template <int DEG, bool BF16>
 __device__ inline void visit_cell(const SceneView& s, uint2 ref, double t0, float tmax, float ox, float oy, float oz,
-                                  float dx, float dy, float dz, const float* Y, Visit<DEG>& v)
+                                  float dx, float dy, float dz, const float* Y, Visit<DEG>& v,
+                                  const double* hi = nullptr)
 {
     const int cell = ref_cell(ref), beg = ref_beg(ref);
     v.h = nearest_front_face(s.planes, beg, ref_deg(ref), ox, oy, oz, dx, dy, dz);
@@ -122,8 +127,13 @@ __device__ inline void visit_cell(const SceneView& s, uint2 ref, double t0, floa
     }
     load_record<DEG, BF16>(s.rec, cell, v.at);
     v.t1 = INFINITY;
-    if (v.h.k >= 0) v.t1 = exit_distance(wp, v.at.site, ox, oy, oz, dx, dy, dz);
-    const double tm = (double)tmax;
+    if (v.h.k >= 0) {
+        if (hi)
+            v.t1 = exit_distance(wp, v.at.site, hi[0], hi[1], hi[2], hi[3], hi[4], hi[5]);
+        else
+            v.t1 = exit_distance(wp, v.at.site, ox, oy, oz, dx, dy, dz);
+    }
+    const double tm = hi ? hi[6] : (double)tmax;
     v.clipped = (v.h.k < 0) || (v.t1 >= tm);
     v.te = fmax(t0, fmin(v.t1, tm));
     segment<DEG>(t0, Y, v);
@@ -135,11 +145,11 @@ __device__ inline void visit_cell(const SceneView& s, uint2 ref, double t0, floa
 // precision even for a nearly grazing exit face, where an FP32 dot product
 // would lose a relative ~2^-24/cos to cancellation (and that face's site
 // gradient is the largest of the ray's).
-__device__ inline double face_den(const float* xi, const float* xj, float dx, float dy, float dz)
+__device__ inline double face_den(const float* xi, const float* xj, double dx, double dy, double dz)
 {
     const double nx = (double)xj[0] - (double)xi[0], ny = (double)xj[1] - (double)xi[1],
                  nz = (double)xj[2] - (double)xi[2];
-    return fma(nz, (double)dz, fma(ny, (double)dy, nx * (double)dx));
+    return fma(nz, dz, fma(ny, dy, nx * dx));
 }
 
 // ---------------------------------------------------------------------------
@@ -174,6 +184,7 @@ struct StageLayout {
     static constexpr int kBytes = kRecOff + kRecs * kRecStride;
     static_assert(kBytes <= kBudget, "stage region over budget");
 };
+
 
 // Called with every lane of the wavefront active. Lanes with `want` stage the
 // row and record of their cell `ref`; on return face_slot / rec_slot give the
@@ -219,7 +230,8 @@ __device__ inline void stage_cells(const SceneView& s, bool want, uint2 ref, lds
 template <int DEG, bool BF16>
 __device__ inline void visit_cell_staged(const SceneView& s, uint2 ref, int face_slot, int rec_slot,
                                          lds_u8* region, double t0, float tmax, float ox, float oy, float oz,
-                                         float dx, float dy, float dz, const float* Y, Visit<DEG>& v)
+                                         float dx, float dy, float dz, const float* Y, Visit<DEG>& v,
+                                         const double* hi = nullptr)
 {
     using SL = StageLayout<DEG, BF16>;
     using R = Rec<DEG, BF16>;
@@ -239,8 +251,13 @@ __device__ inline void visit_cell_staged(const SceneView& s, uint2 ref, int face
     else
         load_record<DEG, BF16>(s.rec, cell, v.at);
     v.t1 = INFINITY;
-    if (v.h.k >= 0) v.t1 = exit_distance(wp, v.at.site, ox, oy, oz, dx, dy, dz);
-    const double tm = (double)tmax;
+    if (v.h.k >= 0) {
+        if (hi)
+            v.t1 = exit_distance(wp, v.at.site, hi[0], hi[1], hi[2], hi[3], hi[4], hi[5]);
+        else
+            v.t1 = exit_distance(wp, v.at.site, ox, oy, oz, dx, dy, dz);
+    }
+    const double tm = hi ? hi[6] : (double)tmax;
     v.clipped = (v.h.k < 0) || (v.t1 >= tm);
     v.te = fmax(t0, fmin(v.t1, tm));
     segment<DEG>(t0, Y, v);
@@ -271,22 +288,29 @@ constexpr uint32_t kLogCell = kLogCross - 1u;
 // reflected or refracted direction, measuring t from the crossing again, up
 // to the scene bound. The leg arithmetic is in double and shared by the
 // forward and the backward, so both build the same legs bit for bit.
+// A leg after a crossing is kept in double (origin, unit direction, t_max):
+// its exit distances, clipping and next crossing are computed from that, and
+// only the face decisions and the SH basis use its FP32 rounding, so the
+// legs are those of the exact reflection and refraction laws up to double
+// rounding (a face decision near a tie may still go either way, as for any
+// FP32 ray).
 // ---------------------------------------------------------------------------
 struct Leg {
     double ts;    // distance along the leg to its next crossing, +inf if none
     int inside;   // the leg starts inside the sphere
     int bounces;  // crossings so far
+    double hi[7]; // the leg in double: origin, direction, t_max
 };
 
 // Next crossing of the leg: the far root of |o + t d - c| = r from inside,
 // the near positive root from outside (a leg leaving the surface outwards
 // has none).
-__device__ inline double surface_hit(const SurfaceArgs& sf, float ox, float oy, float oz, float dx, float dy,
-                                     float dz, int inside, int bounces)
+__device__ inline double surface_hit(const SurfaceArgs& sf, const double* o, const double* d, int inside,
+                                     int bounces)
 {
     if (bounces >= sf.max_bounces) return INFINITY;
-    const double cx = (double)ox - sf.centre[0], cy = (double)oy - sf.centre[1], cz = (double)oz - sf.centre[2];
-    const double b = fma(cz, (double)dz, fma(cy, (double)dy, cx * (double)dx));
+    const double cx = o[0] - sf.centre[0], cy = o[1] - sf.centre[1], cz = o[2] - sf.centre[2];
+    const double b = fma(cz, d[2], fma(cy, d[1], cx * d[0]));
     const double r = sf.radius;
     const double c = fma(cz, cz, fma(cy, cy, cx * cx)) - r * r;
     const double disc = b * b - c;
@@ -296,13 +320,20 @@ __device__ inline double surface_hit(const SurfaceArgs& sf, float ox, float oy, 
 }
 
 __device__ inline void leg_start(const SurfaceArgs& sf, float ox, float oy, float oz, float dx, float dy, float dz,
-                                 Leg& L)
+                                 float tmax, Leg& L)
 {
-    const double cx = (double)ox - sf.centre[0], cy = (double)oy - sf.centre[1], cz = (double)oz - sf.centre[2];
+    L.hi[0] = ox;
+    L.hi[1] = oy;
+    L.hi[2] = oz;
+    L.hi[3] = dx;
+    L.hi[4] = dy;
+    L.hi[5] = dz;
+    L.hi[6] = tmax;
+    const double cx = L.hi[0] - sf.centre[0], cy = L.hi[1] - sf.centre[1], cz = L.hi[2] - sf.centre[2];
     const double r = sf.radius;
     L.inside = fma(cz, cz, fma(cy, cy, cx * cx)) < r * r;
     L.bounces = 0;
-    L.ts = surface_hit(sf, ox, oy, oz, dx, dy, dz, L.inside, 0);
+    L.ts = surface_hit(sf, L.hi, L.hi + 3, L.inside, 0);
 }
 
 // Distance from o along d to the bound (box or sphere about the origin).
@@ -327,14 +358,15 @@ __device__ inline double bound_exit(int kind, const float* b, const double o[3],
 // Snell's law with n1/n2 = 1/ior entering and ior leaving (total internal
 // reflection when the refracted cosine is imaginary). Updates the leg's
 // origin, direction, t_max and crossing state.
+// The new leg is kept in L.hi; ox..dz and tmax receive its FP32 rounding.
 __device__ inline void surface_turn(const SurfaceArgs& sf, Leg& L, float& ox, float& oy, float& oz, float& dx,
                                     float& dy, float& dz, float& tmax)
 {
-    const double d[3] = {dx, dy, dz};
+    const double d[3] = {L.hi[3], L.hi[4], L.hi[5]};
     double p[3], N[3];
-    p[0] = fma(L.ts, d[0], (double)ox);
-    p[1] = fma(L.ts, d[1], (double)oy);
-    p[2] = fma(L.ts, d[2], (double)oz);
+    p[0] = fma(L.ts, d[0], L.hi[0]);
+    p[1] = fma(L.ts, d[1], L.hi[1]);
+    p[2] = fma(L.ts, d[2], L.hi[2]);
 #pragma unroll
     for (int k = 0; k < 3; ++k) N[k] = p[k] - (double)sf.centre[k];
     const double inv = 1.0 / sqrt(fma(N[2], N[2], fma(N[1], N[1], N[0] * N[0])));
@@ -362,16 +394,21 @@ __device__ inline void surface_turn(const SurfaceArgs& sf, Leg& L, float& ox, fl
         for (int q = 0; q < 3; ++q) dn[q] = fma(-2.0 * dN, N[q], d[q]);
     }
     const double il = 1.0 / sqrt(fma(dn[2], dn[2], fma(dn[1], dn[1], dn[0] * dn[0])));
-    ox = (float)p[0];
-    oy = (float)p[1];
-    oz = (float)p[2];
-    dx = (float)(dn[0] * il);
-    dy = (float)(dn[1] * il);
-    dz = (float)(dn[2] * il);
-    const double o2[3] = {ox, oy, oz}, d2[3] = {dx, dy, dz};
-    tmax = (float)bound_exit(sf.bound_kind, sf.bound, o2, d2);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        L.hi[q] = p[q];
+        L.hi[3 + q] = dn[q] * il;
+    }
+    L.hi[6] = bound_exit(sf.bound_kind, sf.bound, L.hi, L.hi + 3);
+    ox = (float)L.hi[0];
+    oy = (float)L.hi[1];
+    oz = (float)L.hi[2];
+    dx = (float)L.hi[3];
+    dy = (float)L.hi[4];
+    dz = (float)L.hi[5];
+    tmax = (float)L.hi[6];
     ++L.bounces;
-    L.ts = surface_hit(sf, ox, oy, oz, dx, dy, dz, L.inside, L.bounces);
+    L.ts = surface_hit(sf, L.hi, L.hi + 3, L.inside, L.bounces);
 }
 
 // Algorithm 1 for one ray: start in `start`, take the nearest front face of
@@ -472,10 +509,11 @@ __device__ inline void walk_forward_staged(const SceneView& s, bool live, float 
     double t0 = 0.0;
     float T = 1.0f;
     int n = 0;
-    Leg leg = {INFINITY, 0, 0};
+    Leg leg = {};  // no crossing yet, no bounces (the tail reports leg.bounces)
+    leg.ts = INFINITY;
     bool cont = false;  // the visit continues a cell after a crossing
     if constexpr (SURF) {
-        if (live) leg_start(*sf, ox, oy, oz, dx, dy, dz, leg);
+        if (live) leg_start(*sf, ox, oy, oz, dx, dy, dz, tmax, leg);
     }
     while (__ballot(live)) {
         if (live) {
@@ -493,9 +531,19 @@ __device__ inline void walk_forward_staged(const SceneView& s, bool live, float 
             if constexpr (LOG) {
                 if (n == lg->cap) tail = ref;
             }
+            if constexpr (SURF) {
+                // the leg's FP32 rounding for the face scan, taken afresh from
+                // the double leg (so that only the double leg stays live)
+                ox = (float)leg.hi[0];
+                oy = (float)leg.hi[1];
+                oz = (float)leg.hi[2];
+                dx = (float)leg.hi[3];
+                dy = (float)leg.hi[4];
+                dz = (float)leg.hi[5];
+            }
             Visit<DEG> v;
             visit_cell_staged<DEG, BF16>(s, ref, face_slot, rec_slot, region, t0, tmax, ox, oy, oz, dx, dy, dz, Y,
-                                         v);
+                                         v, SURF ? leg.hi : nullptr);
             bool cross = false;
             if constexpr (SURF) {
                 if (leg.ts < v.te) {

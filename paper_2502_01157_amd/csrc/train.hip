@@ -275,6 +275,8 @@ int64_t sample_workspace_doubles(int64_t n)
     return n + (n + kScanTile - 1) / kScanTile;
 }
 
+
+
 hipError_t launch_sample(const float* score, int64_t n, const float* draws, int64_t n_draws, int32_t* out,
                          double* workspace, hipStream_t stream)
 {

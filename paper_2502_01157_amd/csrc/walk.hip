@@ -313,7 +313,7 @@ struct Emitter {
 
 // Offsets of the exit point p = o + t d from the two sites of the face, formed
 // in double so that p - x does not lose the digits of |o| + t.
-__device__ inline void exit_offsets(double t, float ox, float oy, float oz, float dx, float dy, float dz,
+__device__ inline void exit_offsets(double t, double ox, double oy, double oz, double dx, double dy, double dz,
                                     const float* xa, const float* xb, float* pa, float* pb)
 {
     const double o[3] = {ox, oy, oz}, d[3] = {dx, dy, dz};
@@ -342,8 +342,11 @@ constexpr bool four_waves(bool bf16, bool reduce, bool surf, bool quant)
 // basis; the crossing visit's package is emitted in its own iteration, before
 // the lane's basis turns, since nothing after the crossing changes it.
 // QUANT = false leaves out the quantile regulariser's terms (and their 13
-// registers) for calls without them.
-template <int DEG, bool BF16, bool REDUCE, bool LOG, bool SURF = false, bool QUANT = true>
+// registers) for calls without them. CHECK = true (a recomputing walk with a
+// mismatch counter) compares each recomputed walk's final transmittance and
+// status with the forward's; it is a separate instantiation because its
+// registers cost the four-wavefront BF16 kernel 12 bytes more of spills.
+template <int DEG, bool BF16, bool REDUCE, bool LOG, bool SURF = false, bool QUANT = true, bool CHECK = false>
 __global__ __launch_bounds__(kWalkBlock) __attribute__((amdgpu_waves_per_eu(four_waves(BF16, REDUCE, SURF, QUANT) ? 4 : 3)))
 void k_backward(WalkArgs a)
 {
@@ -398,11 +401,12 @@ void k_backward(WalkArgs a)
     }
     float Y[B];
     sh_basis<DEG>(dx, dy, dz, Y);
-    Leg leg = {INFINITY, 0, 0};
+    Leg leg = {};  // no crossing yet, no bounces (the tail reports leg.bounces)
+    leg.ts = INFINITY;
     bool cont = false;    // the next visit continues a cell after a crossing
     bool turned = false;  // this visit ended at the surface: the leg has turned, Y has not yet
     if constexpr (SURF) {
-        if (state == 0) leg_start(a.surf, ox, oy, oz, dx, dy, dz, leg);
+        if (state == 0) leg_start(a.surf, ox, oy, oz, dx, dy, dz, tmax, leg);
     }
 
     // quantile regulariser, if requested: with D = u T_f / (1 - u + u T_f)
@@ -448,15 +452,23 @@ void k_backward(WalkArgs a)
     Package entry = {0, {0, 0, 0}, 0, {0, 0, 0}};
     bool entry_valid = false;
 
+    int status = 0;  // the recomputed walk's status, as the forward reports it in steps
     while (__ballot(state != 3)) {
         bool has = false;
         Package out = prev;
+        bool stop = false;
         if (state == 0) {
-            bool stop;
-            if constexpr (LOG)
+            if constexpr (LOG) {
                 stop = (n == n_total);
-            else
-                stop = (!cont && !(T > a.eps)) || (n == a.max_steps);
+            } else if (!cont && !(T > a.eps)) {
+                stop = true;
+                if constexpr (CHECK) status = n;
+            } else if (n == a.max_steps) {
+                stop = true;
+                if constexpr (CHECK) status = -2;  // max_steps cells visited with T > eps, as the forward flags it
+            }
+        }
+        if (state == 0) {
             if (!stop) {
                 Visit<DEG> v;
                 int cell;
@@ -488,7 +500,15 @@ void k_backward(WalkArgs a)
                     segment<DEG>(t0, Y, v);
                 } else {
                     cell = ref_cell(ref);
-                    visit_cell<DEG, BF16>(a.s, ref, t0, tmax, ox, oy, oz, dx, dy, dz, Y, v);
+                    if constexpr (SURF) {
+                        ox = (float)leg.hi[0];
+                        oy = (float)leg.hi[1];
+                        oz = (float)leg.hi[2];
+                        dx = (float)leg.hi[3];
+                        dy = (float)leg.hi[4];
+                        dz = (float)leg.hi[5];
+                    }
+                    visit_cell<DEG, BF16>(a.s, ref, t0, tmax, ox, oy, oz, dx, dy, dz, Y, v, SURF ? leg.hi : nullptr);
                     if constexpr (SURF) {
                         if (leg.ts < v.te) {
                             cross = true;
@@ -525,9 +545,16 @@ void k_backward(WalkArgs a)
                     if (p_moves) {
                         // exit point relative to both sites, in double: p - x = (o - x) + t d
                         const float gt = p_sdt - sdt + gt_q;
-                        const float s = (float)((double)gt / face_den(p_site, at.site, dx, dy, dz));
                         float pa[3], pb[3];
-                        exit_offsets(p_t1, ox, oy, oz, dx, dy, dz, p_site, at.site, pa, pb);
+                        float s;
+                        if constexpr (SURF) {
+                            s = (float)((double)gt / face_den(p_site, at.site, leg.hi[3], leg.hi[4], leg.hi[5]));
+                            exit_offsets(p_t1, leg.hi[0], leg.hi[1], leg.hi[2], leg.hi[3], leg.hi[4], leg.hi[5],
+                                         p_site, at.site, pa, pb);
+                        } else {
+                            s = (float)((double)gt / face_den(p_site, at.site, dx, dy, dz));
+                            exit_offsets(p_t1, ox, oy, oz, dx, dy, dz, p_site, at.site, pa, pb);
+                        }
                         prev.dx[0] = fmaf(s, pa[0], prev.dx[0]);
                         prev.dx[1] = fmaf(s, pa[1], prev.dx[1]);
                         prev.dx[2] = fmaf(s, pa[2], prev.dx[2]);
@@ -557,6 +584,7 @@ void k_backward(WalkArgs a)
                 ++n;
                 if (v.clipped) {
                     stop = true;
+                    if constexpr (CHECK) status = n;
                 } else if (cross) {
                     if constexpr (SURF) {
                         // a new leg from the crossing, in the same cell; the
@@ -574,6 +602,12 @@ void k_backward(WalkArgs a)
                 }
             }
             if (stop) {
+                if constexpr (CHECK && !LOG) {
+                    // consistency of the recomputation: the same final
+                    // transmittance (bit for bit) and visit count as the forward's
+                    if (__float_as_uint(T) != __float_as_uint(Tfin) || (a.steps_in && a.steps_in[r] != status))
+                        atomicAdd(a.mismatch, 1);
+                }
                 if (have_prev && p_moves) {
                     // the last exit moved with its face but no segment follows it
                     float xj[3], pa[3], pb[3];
@@ -581,8 +615,15 @@ void k_backward(WalkArgs a)
                     // cannot address outside the scene)
                     entry.cell = min(ref_cell(ref), (int)(a.s.n_sites - 1));
                     load_site<DEG, BF16>(a.s.rec, entry.cell, xj);
-                    const float s = (float)((double)p_sdt / face_den(p_site, xj, dx, dy, dz));
-                    exit_offsets(p_t1, ox, oy, oz, dx, dy, dz, p_site, xj, pa, pb);
+                    float s;
+                    if constexpr (SURF) {
+                        s = (float)((double)p_sdt / face_den(p_site, xj, leg.hi[3], leg.hi[4], leg.hi[5]));
+                        exit_offsets(p_t1, leg.hi[0], leg.hi[1], leg.hi[2], leg.hi[3], leg.hi[4], leg.hi[5], p_site,
+                                     xj, pa, pb);
+                    } else {
+                        s = (float)((double)p_sdt / face_den(p_site, xj, dx, dy, dz));
+                        exit_offsets(p_t1, ox, oy, oz, dx, dy, dz, p_site, xj, pa, pb);
+                    }
                     prev.dx[0] = fmaf(s, pa[0], prev.dx[0]);
                     prev.dx[1] = fmaf(s, pa[1], prev.dx[1]);
                     prev.dx[2] = fmaf(s, pa[2], prev.dx[2]);
@@ -752,11 +793,16 @@ static hipError_t launch_walk_t(WalkKind kind, const WalkArgs& a, hipStream_t st
     case kBackwardReduce:
         if (a.grad_q)
             hipLaunchKernelGGL((k_backward<DEG, BF16, true, false>), grid, block, 0, stream, a);
+        else if (a.mismatch)
+            hipLaunchKernelGGL((k_backward<DEG, BF16, true, false, false, false, true>), grid, block, 0, stream, a);
         else
             hipLaunchKernelGGL((k_backward<DEG, BF16, true, false, false, false>), grid, block, 0, stream, a);
         break;
     case kBackwardAtomic:
-        hipLaunchKernelGGL((k_backward<DEG, BF16, false, false>), grid, block, 0, stream, a);
+        if (a.mismatch)
+            hipLaunchKernelGGL((k_backward<DEG, BF16, false, false, false, true, true>), grid, block, 0, stream, a);
+        else
+            hipLaunchKernelGGL((k_backward<DEG, BF16, false, false>), grid, block, 0, stream, a);
         break;
     case kBackwardLogReduce:
         // rays within the log, then the rays whose walks outgrew it (recomputed)

@@ -338,13 +338,18 @@ def render_trace(scene: PackedScene, origin, direction, t_max, start, eps: float
 def render_backward(scene: PackedScene, origin, direction, t_max, start, rgb, t_final, grad_rgb,
                     grad_t_final=None, eps: float = DEFAULT_EPS, max_steps: int = DEFAULT_MAX_STEPS,
                     mode: int = 0, grads=None, log: Optional[WalkLog] = None,
-                    quantiles: Optional["Quantiles"] = None, grad_loss=None, surface: Optional[Surface] = None):
+                    quantiles: Optional["Quantiles"] = None, grad_loss=None, surface: Optional[Surface] = None,
+                    steps=None, mismatches=None):
     """Gradients (sites [N,3], density [N], sh [N,B,3]); accumulated into ``grads`` if given.
 
     With ``log`` (filled by ``render_forward`` on the same scene, rays and
     parameters) the visits are read from the log instead of recomputed; with
     ``quantiles`` (from ``quantile_forward`` on that log) and ``grad_loss`` [R]
-    the quantile regulariser's gradient is included."""
+    the quantile regulariser's gradient is included. The recomputing form
+    (no log, no surface, no quantiles) checks each recomputed walk against the
+    forward's outputs when ``mismatches`` (int32 [1], zeroed by the caller) is
+    given: it counts the rays whose final transmittance, or visit count in
+    ``steps`` (the forward's, optional), differs."""
     R = int(direction.shape[0])
     dev = direction.device
     n, B = scene.n_sites, sh_count(scene.sh_degree)
@@ -387,10 +392,14 @@ def render_backward(scene: PackedScene, origin, direction, t_max, start, rgb, t_
                                                     gs.data_ptr(), gd.data_ptr(), gsh.data_ptr(), int(mode),
                                                     _stream(dev)))
     elif log is None:
+        if steps is not None:
+            _dev(steps, torch.int32, (R,), "steps")
+        if mismatches is not None:
+            _dev(mismatches, torch.int32, (1,), "mismatches")
         L.check(L.lib().rf_render_backward(ctypes.byref(scene.desc), ctypes.byref(rays), ctypes.byref(p),
-                                           rgb.data_ptr(), t_final.data_ptr(), grad_rgb.data_ptr(),
+                                           rgb.data_ptr(), t_final.data_ptr(), _ptr(steps), grad_rgb.data_ptr(),
                                            _ptr(grad_t_final), gs.data_ptr(), gd.data_ptr(), gsh.data_ptr(),
-                                           int(mode), _stream(dev)))
+                                           int(mode), _ptr(mismatches), _stream(dev)))
     else:
         log.check(R)
         L.check(L.lib().rf_render_backward_logged(ctypes.byref(scene.desc), ctypes.byref(rays), ctypes.byref(p),

@@ -1,16 +1,14 @@
 """Ray-based effects on the GPU (Fig. 3) against the FP64 oracle: secondary
 rays at a mirror or glass sphere, and the equidistant fisheye camera.
 
-The library defines each leg after a crossing as a ray with FP32 origin and
-direction (the crossing point and the new direction, computed in double,
-rounded), like the caller's rays; the oracle is run with the same rounding
-(fp32_legs), so every leg is the same FP32 ray on both sides and the plain
-walk's tolerances apply. (Against exact FP64 legs the GPU's later exit
-distances would carry an error of ~2^-24 t / cos of the exit face, which
-near-grazing faces amplify past the colour tolerance on a few rays of a full
-frame.) Rays are compared where the face decisions clear KAPPA_T and the
-surface decisions (grazing crossings, near-critical refraction, a crossing
-next to a face) clear 1e-4.
+The oracle's legs are exact (the reflection and refraction laws in double).
+The library keeps each leg after a crossing in double for its exit
+distances, clipping and next crossing, and takes only its face decisions in
+FP32 on the leg's rounding, as for any ray: so the plain walk's tolerances
+apply, with the face decisions' margin (KAPPA_T, whose error scale includes
+the rounding of the leg's origin and direction) and the surface decisions
+(a crossing next to an exit, a grazing crossing, near-critical refraction)
+clearing KAPPA_SURF.
 """
 
 import numpy as np
@@ -19,7 +17,8 @@ import pytest
 import oracle
 import synth
 
-from parity import COLOUR_RTOL, GRAD_RTOL, KAPPA_G, KAPPA_T, KAPPA_TERM, KAPPA_X, colour_err, grad_err
+from parity import (COLOUR_RTOL, KAPPA_G, KAPPA_T, KAPPA_TERM, KAPPA_X, check_gradients, colour_err, colour_ratio,
+                    grad_err)
 
 pytestmark = pytest.mark.gpu
 
@@ -27,7 +26,7 @@ pytestmark = pytest.mark.gpu
 CENTRE = tuple(float(np.float32(c)) for c in (0.05, -0.1, 0.0))
 RADIUS = float(np.float32(0.35))
 BOX = ("box", -1.0, 1.0)
-KAPPA_SURF = 1e-4
+KAPPA_SURF = 1e-6
 EPS = 1e-4
 
 
@@ -64,7 +63,7 @@ def setup():
 def _surfaces(rf, kind, ior=1.5, max_bounces=8):
     ior = float(np.float32(ior))
     return (rf.Surface(kind, CENTRE, RADIUS, BOX, ior=ior, max_bounces=max_bounces),
-            oracle.Surface(kind, CENTRE, RADIUS, BOX, ior=ior, max_bounces=max_bounces, fp32_legs=True))
+            oracle.Surface(kind, CENTRE, RADIUS, BOX, ior=ior, max_bounces=max_bounces))
 
 
 def _packed(rf, scene, dtype="f32", density=None):
@@ -112,7 +111,7 @@ def test_bent_forward_matches_oracle(setup, kind, dtype):
     # the logged and the plain forward give the same outputs bit for bit
     assert torch.equal(rgb, rgb2) and torch.equal(tf, tf2) and torch.equal(steps, steps2)
     rgb, tf, steps = rgb.cpu().numpy(), tf.cpu().numpy(), steps.cpu().numpy()
-    assert colour_err(rgb[ok], tr["rgb"][ok]) <= COLOUR_RTOL
+    assert colour_ratio(rgb[ok], tr["rgb"][ok], np.abs(tr["rgb"]).mean()).max() <= 1.0
     assert np.abs(tf[ok] - tr["t_final"][ok]).max() <= 1e-4
     np.testing.assert_array_equal(steps[ok], tr["steps"][ok])
     # visited cells and crossings, from the walk log
@@ -184,8 +183,7 @@ def test_bent_backward_matches_oracle(setup, kind, cap):
     rgb, tf, _ = rf.render_forward(p, o, d, t, s, eps=EPS, log=log, surface=sf)
     got = rf.render_backward(p, o, d, t, s, rgb, tf, _dv(g), _dv(gT), eps=EPS, log=log, surface=sf)
     torch.cuda.synchronize()
-    errs = [grad_err(x.cpu().numpy(), y) for x, y in zip(got, ref)]
-    assert max(errs) <= GRAD_RTOL, errs
+    check_gradients(got, ref)
 
 
 def test_bent_autograd_and_errors(setup):

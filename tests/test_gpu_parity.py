@@ -11,8 +11,9 @@ import pytest
 import oracle
 import synth
 
-from parity import (COLOUR_RTOL, GRAD_RTOL, T_ATOL, T_EXIT_ATOL, camera_rays, colour_err, compare_sequences,
-                    decidable, grad_err, gradient_decidable, inside_rays)
+from parity import (COLOUR_RTOL, GRAD_RTOL, T_ATOL, T_EXIT_ATOL, camera_rays, check_gradients, colour_err,
+                    colour_ratio, compare_sequences, decidable, grad_err, gradient_decidable, inside_rays,
+                    resolve_near_ties)
 
 pytestmark = pytest.mark.gpu
 
@@ -52,21 +53,39 @@ def gpu_trace(rf, p, rays, eps, max_steps=8192, max_len=1024):
     return out
 
 
-def check_forward(rf, scene, rays, eps, dtype="f32", max_undecidable=0.03):
+def check_forward(rf, scene, rays, eps, dtype="f32", max_unresolved=0.002, max_steps=8192):
+    """Every ray: exact cells on decidable rays, the GPU's walk among the
+    oracle's alternatives on near-tie rays, and colour, transmittance and
+    visit count against the matching walk."""
     p, _ = packed(rf, scene, dtype)
     osc = oracle.OracleScene.from_scene(scene)
     if dtype == "bf16":
         dens = oracle.bf16_to_f32(oracle.bf16_round(scene.density))
         sh = oracle.bf16_to_f32(oracle.bf16_round(scene.sh))
         osc = oracle.OracleScene.from_scene(scene, density=dens, sh=sh)
-    ref = oracle.trace(osc, *rays, eps=eps, max_len=1024)
-    g = gpu_trace(rf, p, rays, eps)
+    ref = oracle.trace(osc, *rays, eps=eps, max_len=1024, max_steps=max_steps)
+    g = gpu_trace(rf, p, rays, eps, max_steps=max_steps)
     dec = decidable(ref, eps)
-    assert dec.mean() >= 1 - max_undecidable, f"only {dec.mean():.4f} of rays decidable"
     assert compare_sequences(g["cells"], g["len"], ref, dec) == 0
     np.testing.assert_array_equal(g["steps"][dec], ref["steps"][dec])
-    assert colour_err(g["rgb"], ref["rgb"]) <= COLOUR_RTOL
-    assert np.abs(g["t_final"] - ref["t_final"]).max() <= T_ATOL
+    mean_abs = float(np.abs(ref["rgb"]).mean())
+    assert colour_ratio(g["rgb"][dec], ref["rgb"][dec], mean_abs).max(initial=0) <= 1.0
+    assert np.abs(g["t_final"][dec] - ref["t_final"][dec]).max(initial=0) <= T_ATOL
+    und = np.nonzero(~dec)[0]
+    if len(und):
+        res = resolve_near_ties(osc, rays, und, g["cells"][und], g["len"][und], eps, max_steps=max_steps)
+        unresolved = 0
+        for q, r in enumerate(und):
+            m = res["match"][q]
+            if m is None:
+                # no alternative matched: only allowed where the alternatives were not all listed
+                assert not res["complete"][q], f"ray {r}: the GPU's walk is none of the oracle's alternatives"
+                unresolved += 1
+                continue
+            assert colour_ratio(g["rgb"][r], m["rgb"], mean_abs)[0] <= 1.0, r
+            assert abs(g["t_final"][r] - m["t_final"]) <= T_ATOL, r
+            assert g["steps"][r] == m["steps"], r
+        assert unresolved <= max_unresolved * len(dec), (unresolved, len(dec))
     # exit distances of decidable rays
     for r in np.nonzero(dec)[0][:2000]:
         L = ref["len"][r]
@@ -223,7 +242,7 @@ def test_edge_cases(rf, clustered):
     dec = decidable(ref, 1e-4)
     np.testing.assert_array_equal(g["steps"][dec], ref["steps"][dec])
     assert np.any(g["steps"] == -2)
-    assert colour_err(g["rgb"], ref["rgb"]) <= COLOUR_RTOL
+    assert colour_ratio(g["rgb"][dec], ref["rgb"][dec], np.abs(ref["rgb"]).mean()).max() <= 1.0
     # zero density everywhere: fully transparent
     p0 = rf.PackedScene(*to_dev(scene.sites, scene.off, scene.idx, np.zeros_like(scene.density), scene.sh), 3)
     rgb, tf, _ = rf.render_forward(p0, *to_dev(o[8:], d[8:], t[8:], s[8:]))
@@ -259,11 +278,13 @@ def check_backward(rf, scene, rays, eps, mode=0, dtype="f32", with_gt=True, seed
     rgb, tf, steps = rf.render_forward(p, o, d, t, s, eps=eps, log=log)
     gg, = to_dev(g)
     gt_dev = to_dev(gT)[0] if with_gt else None
-    gs, gd, gsh = rf.render_backward(p, o, d, t, s, rgb, tf, gg, gt_dev, eps=eps, mode=mode, log=log)
+    mism = torch.zeros(1, dtype=torch.int32, device=o.device) if log is None else None
+    gs, gd, gsh = rf.render_backward(p, o, d, t, s, rgb, tf, gg, gt_dev, eps=eps, mode=mode, log=log,
+                                     steps=steps if log is None else None, mismatches=mism)
     torch.cuda.synchronize()
-    errs = [grad_err(x.cpu().numpy(), y) for x, y in zip((gs, gd, gsh), ref_g)]
-    assert max(errs) <= GRAD_RTOL, errs
-    return errs
+    if mism is not None:
+        assert int(mism.item()) == 0
+    return check_gradients((gs, gd, gsh), ref_g)
 
 
 @pytest.mark.parametrize("mode", [0, 1])
@@ -285,6 +306,32 @@ def test_backward_interior_rays_eps0_and_dense_termination(rf, clustered):
     dense = _Deg(scene, 3)
     dense.density = scene.density * 40.0          # most rays end by the transmittance test
     check_backward(rf, dense, rays, eps=1e-2, seed=2)
+
+
+def test_backward_consistency_check_counts_disagreeing_rays(rf, clustered):
+    """The recomputing backward compares each recomputed walk with the
+    forward's outputs: none differ for the forward's own outputs; a final
+    transmittance or a visit count changed on the host is counted per ray."""
+    import torch
+
+    scene, cam, _ = clustered
+    p, _ = packed(rf, scene)
+    o, d, t, s = to_dev(*camera_rays(scene, cam)[:4])
+    R = int(t.shape[0])
+    rgb, tf, steps = rf.render_forward(p, o, d, t, s)
+    g = torch.randn_like(rgb)
+    mism = torch.zeros(1, dtype=torch.int32, device=o.device)
+    rf.render_backward(p, o, d, t, s, rgb, tf, g, steps=steps, mismatches=mism)
+    torch.cuda.synchronize()
+    assert int(mism.item()) == 0
+    tf_bad = tf.clone()
+    tf_bad[:100] = torch.nextafter(tf_bad[:100], torch.full_like(tf_bad[:100], 2.0))
+    steps_bad = steps.clone()
+    steps_bad[R - 50:] += 1
+    mism.zero_()
+    rf.render_backward(p, o, d, t, s, rgb, tf_bad, g, steps=steps_bad, mismatches=mism)
+    torch.cuda.synchronize()
+    assert int(mism.item()) == 150
 
 
 def test_backward_modes_agree(rf, clustered):
@@ -412,6 +459,36 @@ def test_autograd_function(rf, clustered):
         assert grad_err(x.cpu().numpy(), y.cpu().numpy()) < 1e-5
 
 
+@pytest.mark.parametrize("log_capacity", [0, 256])
+def test_autograd_matches_oracle(rf, clustered, log_capacity):
+    """rf.render(...).backward() (the torch.autograd.Function, with the
+    recomputing backward and with a walk log) against the oracle's gradient of
+    the same loss sum(g . rgb) + sum(g_T T), for sites, density and SH."""
+    import torch
+
+    scene, cam, _ = clustered
+    rays = camera_rays(scene, cam)[:4]
+    osc = oracle.OracleScene.from_scene(scene)
+    ref = oracle.trace(osc, *rays, eps=1e-4, max_len=1)
+    keep = gradient_decidable(ref, 1e-4)
+    rng = np.random.default_rng(17)
+    g = np.where(keep[:, None], rng.standard_normal((len(keep), 3)), 0.0).astype(np.float32)
+    gT = np.where(keep, rng.standard_normal(len(keep)), 0.0).astype(np.float32)
+    sites, off, idx, dens, sh = to_dev(scene.sites, scene.off, scene.idx, scene.density, scene.sh)
+    for x in (sites, dens, sh):
+        x.requires_grad_(True)
+    o, d, t, s = to_dev(*rays)
+    rgb, tf, steps = rf.render(sites, dens, sh, off, idx, o, d, t, s, 3, log_capacity=log_capacity)
+    gg, gtt = to_dev(g, gT)
+    ((rgb * gg).sum() + (tf * gtt).sum()).backward()
+    torch.cuda.synchronize()
+    ref_g = oracle.backward(osc, *rays, g, gT, eps=1e-4)
+    check_gradients((sites.grad, dens.grad, sh.grad), ref_g)
+    dec = decidable(ref, 1e-4)
+    c = rgb.detach().cpu().numpy()
+    assert colour_ratio(c[dec], ref["rgb"][dec], np.abs(ref["rgb"]).mean()).max() <= 1.0
+
+
 # ---------------------------------------------------------------------------
 # a7: bf16-stored attributes
 # ---------------------------------------------------------------------------
@@ -424,3 +501,64 @@ def test_bf16_forward_and_backward(rf, clustered):
     # total error against the fp32-attribute oracle stays at bf16 rounding level
     full = oracle.forward(oracle.OracleScene.from_scene(scene), *rays, eps=1e-4)
     assert colour_err(g["rgb"], full[0]) < 1e-2
+
+
+def test_gpu_finite_differences(rf, clustered):
+    """Central finite differences of the GPU forward against the GPU backward
+    (FP32 renders, the loss summed in double on the host): the largest density
+    and SH gradients, and the largest site gradients (a small site step that
+    changes no face decision on the traced rays)."""
+    import torch
+
+    scene, cam, _ = clustered
+    rays = camera_rays(scene, cam)[:4]
+    o, d, t, s = to_dev(*rays)
+    g = np.random.default_rng(23).standard_normal((len(rays[2]), 3)).astype(np.float32)
+    gg, = to_dev(g)
+    sites0, dens0, sh0 = (a.astype(np.float32).copy() for a in (scene.sites, scene.density, scene.sh))
+    off, idx = to_dev(scene.off, scene.idx)
+
+    def loss(sites, dens, sh):
+        p = rf.PackedScene(*to_dev(sites, scene.off, scene.idx, dens, sh), 3)
+        rgb, _, _ = rf.render_forward(p, o, d, t, s)
+        torch.cuda.synchronize()
+        return float((rgb.cpu().numpy().astype(np.float64) * g).sum())
+
+    p = rf.PackedScene(*to_dev(sites0, scene.off, scene.idx, dens0, sh0), 3)
+    rgb, tf, steps = rf.render_forward(p, o, d, t, s)
+    gs, gd, gsh = (x.cpu().numpy() for x in rf.render_backward(p, o, d, t, s, rgb, tf, gg))
+    for i in np.argsort(-np.abs(gd))[:3]:
+        h = 1e-2 * dens0[i]
+        dp, dm = dens0.copy(), dens0.copy()
+        dp[i] += h
+        dm[i] -= h
+        fd = (loss(sites0, dp, sh0) - loss(sites0, dm, sh0)) / (float(dp[i]) - float(dm[i]))
+        assert abs(fd - gd[i]) <= 1e-2 * abs(gd[i]), (i, fd, gd[i])
+    flat = np.argsort(-np.abs(gsh.ravel()))[:3]
+    for f in flat:
+        h = 1e-2
+        sp, sm = sh0.copy(), sh0.copy()
+        sp.ravel()[f] += h
+        sm.ravel()[f] -= h
+        fd = (loss(sites0, dens0, sp) - loss(sites0, dens0, sm)) / (float(sp.ravel()[f]) - float(sm.ravel()[f]))
+        assert abs(fd - gsh.ravel()[f]) <= 1e-3 * abs(gsh.ravel()[f]), (f, fd, gsh.ravel()[f])
+    ref = oracle.trace(oracle.OracleScene.from_scene(scene), *rays, eps=1e-4, max_len=1024)
+    checked = 0
+    for f in np.argsort(-np.abs(gs.ravel()))[:8]:
+        i, c = divmod(int(f), 3)
+        h = 2e-5
+        sp, sm = sites0.copy(), sites0.copy()
+        sp[i, c] += h
+        sm[i, c] -= h
+        # the step must leave every traced ray's cells unchanged (no face decision flips)
+        same = True
+        for sx in (sp, sm):
+            tr = oracle.trace(oracle.OracleScene(sx, scene.off, scene.idx, dens0, sh0, 3), *rays, eps=1e-4,
+                              max_len=1024)
+            same &= np.array_equal(tr["cells"], ref["cells"]) and np.array_equal(tr["len"], ref["len"])
+        if not same:
+            continue
+        fd = (loss(sp, dens0, sh0) - loss(sm, dens0, sh0)) / (float(sp[i, c]) - float(sm[i, c]))
+        assert abs(fd - gs[i, c]) <= 5e-2 * abs(gs[i, c]), (i, c, fd, gs[i, c])
+        checked += 1
+    assert checked >= 3
