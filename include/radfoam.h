@@ -477,6 +477,35 @@ rf_status rf_sample_cells(const float *scores, int64_t n, const float *draws, in
 rf_status rf_prune_mask(const float *density, const int32_t *nbr_off, const int32_t *nbr_idx, int64_t n_sites,
                         float threshold, uint8_t *mask, void *stream);
 
+/* Densification applied (Sec. 3.3): a new site inside the cell of each
+ * drawn candidate. new_sites[k] = x_p + frac r_p u_k with p = parents[k],
+ * r_p half the distance from x_p to its nearest Delaunay neighbour (the
+ * largest ball about x_p inside its Voronoi cell) and u_k = offsets[k] a
+ * point of the unit ball (the caller's draws), so the new site lies strictly
+ * inside the parent's cell for 0 <= frac < 1. Formed in double, rounded to
+ * FP32. A parent outside [0, n_sites) gives NaN coordinates.
+ *   sites     float[n_sites][3], nbr_off/nbr_idx the scene's CSR (device)
+ *   parents   int32[n_new], offsets float[n_new][3], new_sites float[n_new][3] out
+ * The caller appends the new sites (and their parents' attributes, see
+ * rf_gather_rows) and rebuilds the Delaunay graph. */
+rf_status rf_insert_sites(const float *sites, const int32_t *nbr_off, const int32_t *nbr_idx, int64_t n_sites,
+                          const int32_t *parents, const float *offsets, int64_t n_new, float frac, float *new_sites,
+                          void *stream);
+
+/* out[k][:] = in[rows[k]][:] for rows of `width` floats (device arrays): the
+ * parents' attributes for new sites, or the kept rows after pruning. A row
+ * index outside [0, n_rows_in) gives a row of NaN. */
+rf_status rf_gather_rows(const float *in, int64_t n_rows_in, int32_t width, const int32_t *rows, int64_t n_rows_out,
+                         float *out, void *stream);
+
+/* Pruning applied (Sec. 3.3): the indices i with keep[i] != 0, in increasing
+ * order, into kept[0 .. *n_kept) (kept holds n entries; n_kept is a device
+ * int64 written by the call). workspace: rf_keep_workspace(n) bytes, device,
+ * 8-byte aligned. */
+rf_status rf_keep_workspace(int64_t n, size_t *bytes);
+rf_status rf_keep_index(const uint8_t *keep, int64_t n, int32_t *kept, int64_t *n_kept, void *workspace,
+                        size_t workspace_bytes, void *stream);
+
 
 /* Copies the packed face planes (float4 per directed edge, CSR order) into
  * planes[n_edges][4]; for tests of the packing step. */

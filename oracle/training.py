@@ -17,7 +17,20 @@ of what the GPU library's training kernels compute.
   neighbours), and candidates drawn from the multinomial distribution
   proportional to it by inverting its cumulative sum at given uniform draws;
 * pruning: a cell goes when its density and every neighbour's density are
-  below a threshold.
+  below a threshold;
+* insertion of the drawn candidates: each new site lies inside its parent's
+  cell, at x_p + f r_p u with r_p the radius of the largest ball about x_p
+  inside the cell (half the distance to the nearest Delaunay neighbour), u a
+  caller-supplied point of the unit ball and f < 1; the new site starts with
+  its parent's density and colour and zero optimizer moments, so that the
+  piecewise-constant field, and every render, is unchanged by the insertion;
+* removal of pruned sites: the kept sites in their order, attributes and
+  moments with them;
+* the growth schedule: the number of sites grows linearly from the initial
+  count to the maximum up to half the run;
+* the rebuild schedule: after a densification the Delaunay graph is rebuilt
+  after every optimizer step, then the steps between rebuilds grow by one
+  per rebuild up to 100 (the paper's ratio of 1:1 rising to 1:100).
 """
 
 from __future__ import annotations
@@ -132,4 +145,80 @@ def prune_mask(density, off, idx, threshold: float) -> np.ndarray:
     for i in range(n):
         nb = idx[off[i]:off[i + 1]]
         out[i] = s[i] < threshold and bool(np.all(s[nb] < threshold))
+    return out
+
+
+def inscribed_radius(sites, off, idx) -> np.ndarray:
+    """Radius of the largest ball about each site inside its Voronoi cell: the
+    cell is bounded by the bisector planes, the nearest at half the distance to
+    the nearest Delaunay neighbour (inf for a site without neighbours)."""
+    x = np.asarray(sites, dtype=np.float64)
+    r = np.full(len(x), np.inf)
+    for i in range(len(x)):
+        nb = idx[off[i]:off[i + 1]]
+        if len(nb):
+            r[i] = 0.5 * np.linalg.norm(x[nb] - x[i], axis=1).min()
+    return r
+
+
+INSERT_FRACTION = 0.5
+
+
+def insert_sites(sites, off, idx, parents, u, frac: float = INSERT_FRACTION) -> np.ndarray:
+    """New sites x_p + frac r_p u for each parent p (r_p the inscribed radius)
+    and offset u (|u| <= 1): strictly inside the parent's cell when frac < 1."""
+    x = np.asarray(sites, dtype=np.float64)
+    p = np.asarray(parents, dtype=np.int64)
+    r = inscribed_radius(x, off, idx)[p]
+    return x[p] + frac * r[:, None] * np.asarray(u, dtype=np.float64)
+
+
+def densify(params: dict, moments: list, parents, new_sites):
+    """Appends the new sites with their parents' density and SH; their optimizer
+    moments start at zero. params: "sites" [N,3], "density" [N], "sh" [N,B,3];
+    moments: dicts of the same shapes. Returns (params, moments)."""
+    p = np.asarray(parents, dtype=np.int64)
+    out = {"sites": np.concatenate([params["sites"], np.asarray(new_sites, dtype=np.float64)]),
+           "density": np.concatenate([params["density"], np.asarray(params["density"])[p]]),
+           "sh": np.concatenate([params["sh"], np.asarray(params["sh"])[p]])}
+    mom = [{k: np.concatenate([mm[k], np.zeros((len(p),) + np.shape(mm[k])[1:])]) for k in mm} for mm in moments]
+    return out, mom
+
+
+def remove_sites(params: dict, moments: list, keep):
+    """Keeps the sites where keep is True, in their order, with attributes and moments."""
+    k = np.asarray(keep, dtype=bool)
+    return ({name: np.asarray(a)[k] for name, a in params.items()},
+            [{name: np.asarray(a)[k] for name, a in mm.items()} for mm in moments])
+
+
+def grow_target(it: int, total: int, n0: int, n_max: int, start: int = 0) -> int:
+    """Number of sites wanted after iteration it: n0 until start, then linear
+    growth reaching n_max at half the run."""
+    half = total // 2
+    if it <= start or half <= start:
+        return n0 if it <= start else n_max
+    f = min(1.0, (it - start) / (half - start))
+    return int(round(n0 + (n_max - n0) * f))
+
+
+def rebuild_steps(total: int, densify_at, max_interval: int = 100) -> list:
+    """Iterations (0-based, before the step) at which the Delaunay graph is
+    rebuilt: right after each densification, then after 1, 2, 3, ... optimizer
+    steps, the interval growing by one per rebuild up to max_interval."""
+    d = sorted(set(int(i) for i in densify_at))
+    out = []
+    it, k = 0, 0
+    nxt = 0
+    while it < total:
+        if d and it >= d[0]:
+            while d and it >= d[0]:
+                d.pop(0)
+            k = 0
+            nxt = it
+        if it == nxt:
+            out.append(it)
+            k = min(k + 1, max_interval)
+            nxt = it + k
+        it += 1
     return out

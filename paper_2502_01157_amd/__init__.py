@@ -23,6 +23,9 @@ from .ops import (  # noqa: E402,F401
     WalkLog,
     adam_step,
     densify_scores,
+    gather_rows,
+    insert_sites,
+    keep_index,
     locate,
     prune_mask,
     quantile_forward,

@@ -643,6 +643,52 @@ rf_status rf_sample_cells(const float* scores, int64_t n, const float* draws, in
                       "candidate sampling");
 }
 
+rf_status rf_insert_sites(const float* sites, const int32_t* nbr_off, const int32_t* nbr_idx, int64_t n_sites,
+                          const int32_t* parents, const float* offsets, int64_t n_new, float frac, float* new_sites,
+                          void* stream)
+{
+    if (n_sites < 1 || n_new < 0) return fail(RF_ERR_INVALID_ARG, "need n_sites >= 1, n_new >= 0");
+    if (!(frac >= 0.0f && frac < 1.0f)) return fail(RF_ERR_INVALID_ARG, "frac must lie in [0, 1)");
+    if (n_new == 0) return ok();
+    if (!sites || !nbr_off || !nbr_idx || !parents || !offsets || !new_sites)
+        return fail(RF_ERR_INVALID_ARG, "an array is NULL");
+    return hip_status(rf::launch_insert_sites(sites, nbr_off, nbr_idx, n_sites, parents, offsets, n_new, frac,
+                                              new_sites, static_cast<hipStream_t>(stream)),
+                      "site insertion");
+}
+
+rf_status rf_gather_rows(const float* in, int64_t n_rows_in, int32_t width, const int32_t* rows, int64_t n_rows_out,
+                         float* out, void* stream)
+{
+    if (n_rows_in < 0 || n_rows_out < 0 || width < 1) return fail(RF_ERR_INVALID_ARG, "bad sizes");
+    if (n_rows_out == 0) return ok();
+    if (!in || !rows || !out) return fail(RF_ERR_INVALID_ARG, "an array is NULL");
+    return hip_status(rf::launch_gather_rows(in, n_rows_in, width, rows, n_rows_out, out,
+                                             static_cast<hipStream_t>(stream)),
+                      "row gather");
+}
+
+rf_status rf_keep_workspace(int64_t n, size_t* bytes)
+{
+    if (n < 0 || !bytes) return fail(RF_ERR_INVALID_ARG, "n < 0 or bytes is NULL");
+    *bytes = (size_t)rf::keep_workspace_count(n) * sizeof(int64_t);
+    return ok();
+}
+
+rf_status rf_keep_index(const uint8_t* keep, int64_t n, int32_t* kept, int64_t* n_kept, void* workspace,
+                        size_t workspace_bytes, void* stream)
+{
+    if (n < 0 || n > INT32_MAX) return fail(RF_ERR_INVALID_ARG, "need 0 <= n <= 2^31 - 1");
+    if (!n_kept) return fail(RF_ERR_INVALID_ARG, "n_kept is NULL");
+    if (n > 0 && (!keep || !kept || !workspace)) return fail(RF_ERR_INVALID_ARG, "an array is NULL");
+    if (workspace_bytes < (size_t)rf::keep_workspace_count(n) * sizeof(int64_t) ||
+        (reinterpret_cast<uintptr_t>(workspace) & 7) || (reinterpret_cast<uintptr_t>(n_kept) & 7))
+        return fail(RF_ERR_INVALID_ARG, "workspace too small (see rf_keep_workspace) or not 8-byte aligned");
+    return hip_status(rf::launch_keep_index(keep, n, kept, n_kept, static_cast<int64_t*>(workspace),
+                                            static_cast<hipStream_t>(stream)),
+                      "keep index");
+}
+
 rf_status rf_prune_mask(const float* density, const int32_t* nbr_off, const int32_t* nbr_idx, int64_t n_sites,
                         float threshold, uint8_t* mask, void* stream)
 {

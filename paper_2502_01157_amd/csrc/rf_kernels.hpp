@@ -179,6 +179,14 @@ hipError_t launch_densify_score(const float* sites, const int32_t* off, const in
                                 const float* grad_sites, float* score, hipStream_t stream);
 hipError_t launch_prune_mask(const float* density, const int32_t* off, const int32_t* idx, int64_t n,
                              float threshold, uint8_t* mask, hipStream_t stream);
+hipError_t launch_insert_sites(const float* sites, const int32_t* off, const int32_t* idx, int64_t n_sites,
+                               const int32_t* parents, const float* u, int64_t n_new, float frac, float* out,
+                               hipStream_t stream);
+hipError_t launch_gather_rows(const float* in, int64_t n_in, int width, const int32_t* rows, int64_t n_out,
+                              float* out, hipStream_t stream);
+int64_t keep_workspace_count(int64_t n);  // int64 values of the keep-index workspace
+hipError_t launch_keep_index(const uint8_t* keep, int64_t n, int32_t* kept, int64_t* n_kept, int64_t* workspace,
+                             hipStream_t stream);
 int64_t sample_workspace_doubles(int64_t n);
 hipError_t launch_sample(const float* score, int64_t n, const float* draws, int64_t n_draws, int32_t* out,
                          double* workspace, hipStream_t stream);

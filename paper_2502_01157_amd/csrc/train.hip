@@ -180,6 +180,180 @@ hipError_t launch_prune_mask(const float* density, const int32_t* off, const int
 }
 
 // ---------------------------------------------------------------------------
+// Inserting and removing sites (densification and pruning applied).
+// ---------------------------------------------------------------------------
+// A new site inside its parent's cell: x_p + frac r_p u, with r_p the radius
+// of the largest ball about x_p inside the cell, half the distance to the
+// nearest Delaunay neighbour (the nearest bisector plane). Formed in double,
+// rounded once to FP32. A parent out of range gives NaN coordinates.
+__global__ __launch_bounds__(kTrainBlock) void k_insert_sites(const float* __restrict__ sites,
+                                                              const int32_t* __restrict__ off,
+                                                              const int32_t* __restrict__ idx, int64_t n_sites,
+                                                              const int32_t* __restrict__ parents,
+                                                              const float* __restrict__ u, int64_t n_new, float frac,
+                                                              float* __restrict__ out)
+{
+    const int64_t k = (int64_t)blockIdx.x * kTrainBlock + threadIdx.x;
+    if (k >= n_new) return;
+    const int p = parents[k];
+    if (p < 0 || p >= n_sites) {
+        out[3 * k] = out[3 * k + 1] = out[3 * k + 2] = __int_as_float(0x7fc00000);
+        return;
+    }
+    const double x[3] = {sites[3 * (int64_t)p], sites[3 * (int64_t)p + 1], sites[3 * (int64_t)p + 2]};
+    double best = INFINITY;
+    for (int e = off[p]; e < off[p + 1]; ++e) {
+        const int j = idx[e];
+        if (j < 0 || j >= n_sites || j == p) continue;
+        const double dx = sites[3 * (int64_t)j] - x[0], dy = sites[3 * (int64_t)j + 1] - x[1],
+                     dz = sites[3 * (int64_t)j + 2] - x[2];
+        best = fmin(best, fma(dz, dz, fma(dy, dy, dx * dx)));
+    }
+    const double s = isfinite(best) ? (double)frac * 0.5 * sqrt(best) : 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[3 * k + c] = (float)fma(s, (double)u[3 * k + c], x[c]);
+}
+
+// out[k][:] = in[rows[k]][:] for rows of `width` floats; a row index out of
+// range gives a row of NaN.
+__global__ __launch_bounds__(kTrainBlock) void k_gather_rows(const float* __restrict__ in, int64_t n_in, int width,
+                                                             const int32_t* __restrict__ rows, int64_t n_out,
+                                                             float* __restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * kTrainBlock + threadIdx.x;
+    if (e >= n_out * width) return;
+    const int64_t k = e / width;
+    const int c = (int)(e - k * width);
+    const int r = rows[k];
+    out[e] = (r >= 0 && r < n_in) ? in[(int64_t)r * width + c] : __int_as_float(0x7fc00000);
+}
+
+// The kept indices of a mask, in order: per tile of kKeepTile flags a count,
+// an exclusive scan of the counts (one block), then every kept index written
+// at its tile's offset plus its rank in the tile.
+constexpr int kKeepPer = 4;
+constexpr int kKeepTile = kTrainBlock * kKeepPer;
+
+__device__ inline int block_exclusive_scan(int v, int* wave_sum, int& total)
+{
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    int incl = v;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int o = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += o;
+    }
+    if (lane == kWave - 1) wave_sum[w] = incl;
+    __syncthreads();
+    int before = incl - v;
+    total = 0;
+    for (int q = 0; q < kTrainBlock / kWave; ++q) {
+        if (q < w) before += wave_sum[q];
+        total += wave_sum[q];
+    }
+    return before;
+}
+
+__global__ __launch_bounds__(kTrainBlock) void k_keep_count(const uint8_t* __restrict__ keep, int64_t n,
+                                                            int64_t* __restrict__ counts)
+{
+    __shared__ int wave_sum[kTrainBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kKeepTile + (int64_t)threadIdx.x * kKeepPer;
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < kKeepPer; ++q) c += (base + q < n && keep[base + q]) ? 1 : 0;
+    int total;
+    (void)block_exclusive_scan(c, wave_sum, total);
+    if (threadIdx.x == 0) counts[blockIdx.x] = total;
+}
+
+// Exclusive scan of the tile counts in place (one block); the sum into *n_kept.
+__global__ __launch_bounds__(kTrainBlock) void k_keep_offsets(int64_t* counts, int64_t n_tiles, int64_t* n_kept)
+{
+    __shared__ int64_t wave_sum[kTrainBlock / kWave];
+    const int64_t per = (n_tiles + kTrainBlock - 1) / kTrainBlock;
+    const int64_t beg = (int64_t)threadIdx.x * per;
+    const int64_t end = beg + per < n_tiles ? beg + per : n_tiles;
+    int64_t run = 0;
+    for (int64_t b = beg; b < end; ++b) run += counts[b];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    int64_t incl = run;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int64_t o = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += o;
+    }
+    if (lane == kWave - 1) wave_sum[w] = incl;
+    __syncthreads();
+    int64_t acc = incl - run;
+    for (int q = 0; q < w; ++q) acc += wave_sum[q];
+    for (int64_t b = beg; b < end; ++b) {
+        const int64_t t = counts[b];
+        counts[b] = acc;
+        acc += t;
+    }
+    if (threadIdx.x == kTrainBlock - 1) *n_kept = acc;
+}
+
+__global__ __launch_bounds__(kTrainBlock) void k_keep_scatter(const uint8_t* __restrict__ keep, int64_t n,
+                                                              const int64_t* __restrict__ offsets,
+                                                              int32_t* __restrict__ kept)
+{
+    __shared__ int wave_sum[kTrainBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kKeepTile + (int64_t)threadIdx.x * kKeepPer;
+    bool f[kKeepPer];
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < kKeepPer; ++q) {
+        f[q] = base + q < n && keep[base + q];
+        c += f[q] ? 1 : 0;
+    }
+    int total;
+    int64_t pos = offsets[blockIdx.x] + block_exclusive_scan(c, wave_sum, total);
+#pragma unroll
+    for (int q = 0; q < kKeepPer; ++q)
+        if (f[q]) kept[pos++] = (int32_t)(base + q);
+}
+
+hipError_t launch_insert_sites(const float* sites, const int32_t* off, const int32_t* idx, int64_t n_sites,
+                               const int32_t* parents, const float* u, int64_t n_new, float frac, float* out,
+                               hipStream_t stream)
+{
+    const int64_t blocks = (n_new + kTrainBlock - 1) / kTrainBlock;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_insert_sites, dim3((unsigned)blocks), dim3(kTrainBlock), 0, stream, sites, off, idx, n_sites,
+                       parents, u, n_new, frac, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const float* in, int64_t n_in, int width, const int32_t* rows, int64_t n_out,
+                              float* out, hipStream_t stream)
+{
+    const int64_t blocks = (n_out * width + kTrainBlock - 1) / kTrainBlock;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)blocks), dim3(kTrainBlock), 0, stream, in, n_in, width, rows,
+                       n_out, out);
+    return hipGetLastError();
+}
+
+int64_t keep_workspace_count(int64_t n) { return (n + kKeepTile - 1) / kKeepTile; }
+
+hipError_t launch_keep_index(const uint8_t* keep, int64_t n, int32_t* kept, int64_t* n_kept, int64_t* workspace,
+                             hipStream_t stream)
+{
+    const int64_t tiles = keep_workspace_count(n);
+    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+    if (tiles > 0)
+        hipLaunchKernelGGL(k_keep_count, dim3((unsigned)tiles), dim3(kTrainBlock), 0, stream, keep, n, workspace);
+    // (with no tiles this only writes *n_kept = 0)
+    hipLaunchKernelGGL(k_keep_offsets, dim3(1), dim3(kTrainBlock), 0, stream, workspace, tiles, n_kept);
+    if (tiles > 0)
+        hipLaunchKernelGGL(k_keep_scatter, dim3((unsigned)tiles), dim3(kTrainBlock), 0, stream, keep, n, workspace,
+                           kept);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Multinomial sampling by inverting the cumulative score (double).
 // ---------------------------------------------------------------------------
 constexpr int kScanPer = 4;                          // values per thread

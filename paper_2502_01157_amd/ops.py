@@ -564,3 +564,47 @@ def prune_mask(density, off, idx, threshold: float) -> torch.Tensor:
     L.check(L.lib().rf_prune_mask(density.data_ptr(), off.data_ptr(), _ptr(idx) if idx.numel() else None, n,
                                   float(threshold), out.data_ptr(), _stream(density.device)))
     return out.bool()
+
+
+def insert_sites(sites, off, idx, parents, offsets, frac: float = 0.5) -> torch.Tensor:
+    """New sites inside their parents' cells: x_p + frac r_p u (r_p half the
+    distance to p's nearest Delaunay neighbour, u = offsets[k] in the unit ball)."""
+    n, k = int(sites.shape[0]), int(parents.shape[0])
+    _dev(sites, torch.float32, (n, 3), "sites")
+    _dev(off, torch.int32, (n + 1,), "off")
+    _dev(idx, torch.int32, (int(idx.shape[0]),), "idx")
+    _dev(parents, torch.int32, (k,), "parents")
+    _dev(offsets, torch.float32, (k, 3), "offsets")
+    out = torch.empty((k, 3), dtype=torch.float32, device=sites.device)
+    L.check(L.lib().rf_insert_sites(sites.data_ptr(), off.data_ptr(), _ptr(idx) if idx.numel() else None, n,
+                                    _ptr(parents) if k else None, _ptr(offsets) if k else None, k, float(frac),
+                                    _ptr(out) if k else None, _stream(sites.device)))
+    return out
+
+
+def gather_rows(x, rows) -> torch.Tensor:
+    """x[rows] for a float32 tensor x [n, ...] and int32 rows [k] (``rf_gather_rows``)."""
+    n, k = int(x.shape[0]), int(rows.shape[0])
+    if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous():
+        raise TypeError("x must be a contiguous float32 CUDA tensor")
+    _dev(rows, torch.int32, (k,), "rows")
+    width = int(x[0].numel()) if n else int(torch.Size(x.shape[1:]).numel())
+    out = torch.empty((k,) + tuple(x.shape[1:]), dtype=torch.float32, device=x.device)
+    L.check(L.lib().rf_gather_rows(_ptr(x) if x.numel() else None, n, max(width, 1), _ptr(rows) if k else None, k,
+                                   _ptr(out) if out.numel() else None, _stream(x.device)))
+    return out
+
+
+def keep_index(keep) -> torch.Tensor:
+    """Indices where ``keep`` (bool or uint8 [n]) is set, in order (int32); synchronises for the count."""
+    n = int(keep.shape[0])
+    k8 = keep.to(torch.uint8) if keep.dtype == torch.bool else keep
+    _dev(k8, torch.uint8, (n,), "keep")
+    nbytes = ctypes.c_size_t()
+    L.check(L.lib().rf_keep_workspace(n, ctypes.byref(nbytes)))
+    ws = torch.empty(max(int(nbytes.value) // 8, 1), dtype=torch.int64, device=keep.device)
+    kept = torch.empty(max(n, 1), dtype=torch.int32, device=keep.device)
+    count = torch.empty(1, dtype=torch.int64, device=keep.device)
+    L.check(L.lib().rf_keep_index(_ptr(k8) if n else None, n, kept.data_ptr(), count.data_ptr(), ws.data_ptr(),
+                                  ws.numel() * 8, _stream(keep.device)))
+    return kept[: int(count.item())]

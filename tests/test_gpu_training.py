@@ -198,3 +198,101 @@ def test_fit_reduces_the_loss():
         rf.adam_step(rf.train_schedule(it, total), state, pos, x, sh, gs, gd, gsh)
     assert losses[-1] < 0.5 * losses[0], losses[::10]
     assert all(np.isfinite(losses))
+
+
+# ---------------------------------------------------------------------------
+# densification and pruning applied, and a run with a changing adjacency
+# ---------------------------------------------------------------------------
+
+def _unit_ball(rng, n):
+    u = rng.standard_normal((n, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    return (u * rng.uniform(0, 1, (n, 1)) ** (1 / 3)).astype(np.float32)
+
+
+def test_insert_gather_keep_match_oracle(scene):
+    import torch
+
+    import paper_2502_01157_amd as rf
+
+    rng = np.random.default_rng(90)
+    n = scene.n_sites
+    parents = rng.integers(0, n, 5001).astype(np.int32)
+    parents[:2] = [-1, n]  # out of range: NaN coordinates
+    u = _unit_ball(rng, len(parents))
+    sites, off, idx = map(_dv, (scene.sites, scene.off, scene.idx))
+    got = rf.insert_sites(sites, off, idx, _dv(parents), _dv(u), 0.5).cpu().numpy()
+    assert np.isnan(got[:2]).all()
+    ref = otr.insert_sites(scene.sites.astype(np.float64), scene.off, scene.idx, parents[2:], u[2:], frac=0.5)
+    # formed in double and rounded once: within one FP32 rounding of the oracle's value
+    np.testing.assert_allclose(got[2:], ref, rtol=2 ** -23, atol=0)
+    # every new site lies in its parent's cell (nearest site by brute force)
+    nn = synth.nearest_site(scene.sites, got[2:])
+    np.testing.assert_array_equal(nn, parents[2:])
+    # rows gathered bit for bit; indices out of range give NaN rows
+    sh = _dv(scene.sh)
+    rows = rng.integers(0, n, 777).astype(np.int32)
+    np.testing.assert_array_equal(rf.gather_rows(sh, _dv(rows)).cpu().numpy(), scene.sh[rows])
+    bad = rf.gather_rows(sites, _dv(np.array([3, -2, n], dtype=np.int32))).cpu().numpy()
+    np.testing.assert_array_equal(bad[0], scene.sites[3])
+    assert np.isnan(bad[1:]).all()
+    # kept indices in order, for ragged sizes and edge cases
+    for size, p in ((0, 0.5), (1, 1.0), (1023, 0.3), (1024, 0.0), (1025, 1.0), (100003, 0.7)):
+        keep = rng.uniform(0, 1, size) < p
+        got = rf.keep_index(_dv(keep)).cpu().numpy() if size else rf.keep_index(
+            torch.zeros(0, dtype=torch.bool, device="cuda")).cpu().numpy()
+        np.testing.assert_array_equal(got, np.nonzero(keep)[0])
+
+
+def test_training_with_changing_adjacency():
+    """A short run of the training loop on synthetic targets: renders of a
+    3,000-site scene from 8,192 interior rays, fitted from 800 random sites
+    with flat density and zero colour, densified at three steps (pruned,
+    sites inserted by the score, graph rebuilt) up to 2,000 sites. The loss
+    falls, the number of sites follows the growth schedule, the rebuilds
+    follow the schedule, and every rebuilt graph is the Delaunay graph of the
+    sites on the device at that moment (a fresh Qhull build)."""
+    import torch
+
+    import paper_2502_01157_amd as rf
+    from paper_2502_01157_amd.training import TrainConfig, Trainer
+    from parity import inside_rays
+
+    tgt = synth.small_scene("clustered", 3000, seed=91, sh_deg=3)
+    rng = np.random.default_rng(92)
+    o, d, t, s = inside_rays(tgt, rng, 8192, -0.9, 0.9)
+    od, dd, td, sd = map(_dv, (o, d, t, s))
+    target_scene = rf.PackedScene(*map(_dv, (tgt.sites, tgt.off, tgt.idx, tgt.density, tgt.sh)), 3)
+    target, _, _ = rf.render_forward(target_scene, od, dd, td, sd)
+
+    checked = []
+
+    class CheckedTrainer(Trainer):
+        def rebuild(self):
+            super().rebuild()
+            cpu_sites = self.sites.cpu().numpy()
+            off, idx = synth.build_adjacency(cpu_sites)
+            np.testing.assert_array_equal(self.off.cpu().numpy(), off)
+            np.testing.assert_array_equal(self.idx.cpu().numpy(), idx)
+            checked.append(len(cpu_sites))
+
+    init = rng.uniform(-0.95, 0.95, (800, 3)).astype(np.float32)
+    cfg = TrainConfig(total=90, n_max=2000, densify_every=15, prune_threshold=1e-3, seed=93)
+    tr = CheckedTrainer(_dv(init), torch.zeros(800, device="cuda"), torch.zeros((800, 16, 3), device="cuda"), 3,
+                        cfg)
+    hist = tr.run((od, dd, td), target)
+    losses = [h.loss for h in hist]
+    print(f"losses {losses[0]:.5f} -> {losses[-1]:.5f}; sites {[h.n_sites for h in hist if h.densified]}; "
+          f"rebuilds {tr.rebuilds}; graphs checked {len(checked)}", flush=True)
+    assert all(np.isfinite(losses))
+    assert losses[-1] < 0.5 * losses[0]
+    assert tr.densify_at == [15, 30, 45]
+    sizes = {h.it: h.n_sites for h in hist}
+    assert sizes[45] == 2000 and sizes[89] == 2000
+    assert 800 < sizes[15] < sizes[30] < 2000
+    assert tr.rebuilds == otr.rebuild_steps(90, [16, 31, 46])
+    assert len(checked) >= len(tr.rebuilds)
+    # positions are frozen for the last tenth of the run, so the start cells
+    # located at the last rebuild are the nearest sites of the ray origins
+    same = tr.starts.cpu().numpy() == synth.nearest_site(tr.sites.cpu().numpy(), o)
+    assert tr.rebuilds[-1] >= 81 and same.mean() > 0.999

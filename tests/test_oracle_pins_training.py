@@ -134,3 +134,117 @@ def test_prune_mask_by_hand():
     np.testing.assert_array_equal(tr.prune_mask(dens, off, idx, 0.01), [True, False, False, False, True, True])
     np.testing.assert_array_equal(tr.prune_mask(dens, off, idx, 0.6), [True] * 6)
     np.testing.assert_array_equal(tr.prune_mask(dens, off, idx, 0.0), [False] * 6)
+
+
+# ---------------------------------------------------------------------------
+# inserting and removing sites, growth and rebuild schedules
+# ---------------------------------------------------------------------------
+
+def _small_scene(n, seed, sh_deg=1):
+    import synth
+
+    return synth.small_scene("clustered", n, seed=seed, sh_deg=sh_deg)
+
+
+def _unit_ball(rng, n):
+    u = rng.standard_normal((n, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    return u * rng.uniform(0, 1, (n, 1)) ** (1 / 3)
+
+
+def test_inserted_sites_lie_inside_their_parents_cells():
+    sc = _small_scene(600, 41)
+    rng = np.random.default_rng(42)
+    parents = rng.integers(0, sc.n_sites, 400)
+    x = sc.sites.astype(np.float64)
+    # the inscribed radius is half the distance to the nearest site at all (brute force)
+    d = np.linalg.norm(x[:, None, :] - x[None, :, :], axis=-1)
+    np.fill_diagonal(d, np.inf)
+    np.testing.assert_allclose(tr.inscribed_radius(x, sc.off, sc.idx), 0.5 * d.min(axis=1), rtol=1e-15)
+    for frac in (0.5, 0.999):
+        new = tr.insert_sites(x, sc.off, sc.idx, parents, _unit_ball(rng, 400), frac=frac)
+        nn = np.argmin(np.linalg.norm(new[:, None, :] - x[None, :, :], axis=-1), axis=1)
+        np.testing.assert_array_equal(nn, parents)
+    # towards the nearest neighbour the cell ends exactly at the inscribed radius
+    p = parents[:50]
+    j = np.argmin(d[p], axis=1)
+    u = (x[j] - x[p]) / np.linalg.norm(x[j] - x[p], axis=1, keepdims=True)
+    out = tr.insert_sites(x, sc.off, sc.idx, p, u, frac=1.001)
+    closer = np.linalg.norm(out - x[j], axis=1) < np.linalg.norm(out - x[p], axis=1)
+    assert closer.all()
+
+
+def _render(sites, density, sh, sh_deg, o, d, t):
+    import oracle
+    import synth
+
+    s32 = np.asarray(sites, dtype=np.float32)
+    off, idx = synth.build_adjacency(s32)
+    osc = oracle.OracleScene(s32, off, idx, density, sh, sh_deg)
+    start = synth.nearest_site(s32, o).astype(np.int32)
+    return oracle.forward(osc, o, d, t, start, eps=0.0)
+
+
+def _rays(rng, n):
+    o = rng.uniform(-0.8, 0.8, (n, 3))
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return o, d, np.full(n, 0.9)
+
+
+def test_densify_and_prune_change_the_render_as_the_geometry_says():
+    """The field is piecewise constant. A child with its parent's density and
+    colour, placed at a distance f r_p from its parent, moves only bisectors
+    near the parent by O(f r_p): the mean change of the renders is linear in f
+    (with a wrong copy of the attributes the child's half of the parent's cell
+    would change them at any f). Removing an empty cell whose neighbours are all empty
+    hands its volume to those neighbours (a point's second-nearest site is a
+    Delaunay neighbour of its nearest): no render changes (transmittance test
+    off)."""
+    sc = _small_scene(800, 43)
+    rng = np.random.default_rng(44)
+    o, d, t = _rays(rng, 300)
+    x = sc.sites.astype(np.float32).astype(np.float64)
+    dens = sc.density.astype(np.float64)
+    sh = sc.sh.astype(np.float64)
+    ref_rgb, ref_t, _ = _render(x, dens, sh, 1, o, d, t)
+    parents = rng.integers(0, sc.n_sites, 200)
+    u = _unit_ball(rng, 200)
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    moments = [{"sites": np.ones_like(x), "density": np.ones_like(dens), "sh": np.ones_like(sh)}]
+    change = []
+    for frac in (1e-3, 1e-4):
+        new = tr.insert_sites(x, sc.off, sc.idx, parents, u, frac=frac)
+        params, mom = tr.densify({"sites": x, "density": dens, "sh": sh}, moments, parents, new)
+        assert params["sites"].shape == (1000, 3) and np.all(mom[0]["density"][800:] == 0)
+        assert np.all(mom[0]["sh"][:800] == 1)
+        np.testing.assert_array_equal(params["sh"][800:], sh[parents])
+        np.testing.assert_array_equal(params["density"][800:], dens[parents])
+        rgb, T, steps = _render(params["sites"], params["density"], params["sh"], 1, o, d, t)
+        change.append(np.abs(rgb - ref_rgb).mean())
+    # the mean change over the rays is linear in f
+    assert 7.0 < change[0] / change[1] < 14.0, change
+    assert change[1] < 1e-4 * np.abs(ref_rgb).mean()
+    # empty cells with empty neighbours: removing them changes nothing
+    dens2 = dens.copy()
+    dens2[rng.uniform(0, 1, len(dens2)) < 0.95] = 0.0
+    ref2 = _render(x, dens2, sh, 1, o, d, t)
+    keep = ~tr.prune_mask(dens2, sc.off, sc.idx, 1e-30)
+    assert 20 < (~keep).sum() < 790
+    p2, m2 = tr.remove_sites({"sites": x, "density": dens2, "sh": sh}, moments, keep)
+    got2 = _render(p2["sites"], p2["density"], p2["sh"], 1, o, d, t)
+    np.testing.assert_allclose(got2[0], ref2[0], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(got2[1], ref2[1], rtol=1e-12)
+    np.testing.assert_array_equal(p2["sites"], x[keep])
+    # a cell with density is never removed
+    assert np.all(keep[dens2 > 0])
+
+
+def test_growth_and_rebuild_schedules_by_hand():
+    assert [tr.grow_target(i, 100, 10, 110, 10) for i in (0, 10, 30, 50, 99)] == [10, 10, 60, 110, 110]
+    # rebuilt after the step of a densification, then after 1, 2, 3, ... steps
+    assert tr.rebuild_steps(30, [0]) == [0, 1, 3, 6, 10, 15, 21, 28]
+    assert tr.rebuild_steps(30, [0, 12]) == [0, 1, 3, 6, 10, 12, 13, 15, 18, 22, 27]
+    long = tr.rebuild_steps(20000, [0])
+    gaps = np.diff(long)
+    assert gaps.max() == 100 and gaps[0] == 1 and np.all(np.diff(gaps) >= 0)
