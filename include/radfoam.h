@@ -506,6 +506,19 @@ rf_status rf_keep_workspace(int64_t n, size_t *bytes);
 rf_status rf_keep_index(const uint8_t *keep, int64_t n, int32_t *kept, int64_t *n_kept, void *workspace,
                         size_t workspace_bytes, void *stream);
 
+/* rf_sample_cells for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same cells bit for bit, with the
+ * scan's workspace in a fixed scratch array inside the library instead of
+ * the caller's buffer. The call allocates nothing. Limit: n <= 4,194,304
+ * cells (RF_ERR_UNSUPPORTED beyond; the scratch is 33.6 MB, held by every
+ * GPU the library runs on until the process ends). Calls on one GPU share
+ * that GPU's scratch: calls that overlap on one GPU (different streams, or
+ * host threads) race and must be serialised by the caller. The scratch
+ * keeps the last call's contents; nothing in it needs clearing. scores,
+ * draws and cells as in rf_sample_cells (device pointers). */
+rf_status rf_sample_cells_noalloc(const float *scores, int64_t n, const float *draws, int64_t n_draws,
+                                  int32_t *cells, void *stream);
 
 /* Copies the packed face planes (float4 per directed edge, CSR order) into
  * planes[n_edges][4]; for tests of the packing step. */

@@ -146,6 +146,7 @@ def lib() -> ctypes.CDLL:
         L.rf_densify_scores.argtypes = [P, P, P, ctypes.c_int64, P, P, P]
         L.rf_sample_workspace.argtypes = [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
         L.rf_sample_cells.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P, ctypes.c_size_t, P]
+        L.rf_sample_cells_noalloc.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P]
         L.rf_insert_sites.argtypes = [P, P, P, ctypes.c_int64, P, P, ctypes.c_int64, ctypes.c_float, P, P]
         L.rf_gather_rows.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, ctypes.c_int64, P, P]
         L.rf_keep_workspace.argtypes = [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
@@ -164,7 +165,7 @@ def lib() -> ctypes.CDLL:
                      "rf_render_backward_logged", "rf_quantile_forward", "rf_render_backward_quantile",
                      "rf_locate", "rf_render_forward_surface", "rf_render_backward_surface",
                      "rf_train_schedule", "rf_adam_step", "rf_densify_scores", "rf_sample_workspace",
-                     "rf_sample_cells", "rf_prune_mask", "rf_insert_sites",
+                     "rf_sample_cells", "rf_sample_cells_noalloc", "rf_prune_mask", "rf_insert_sites",
                      "rf_gather_rows", "rf_keep_workspace", "rf_keep_index",
                      "rf_packed_planes", "rf_packed_attributes"):
             getattr(L, name).restype = st

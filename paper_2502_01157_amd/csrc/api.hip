@@ -689,6 +689,22 @@ rf_status rf_keep_index(const uint8_t* keep, int64_t n, int32_t* kept, int64_t* 
                       "keep index");
 }
 
+rf_status rf_sample_cells_noalloc(const float* scores, int64_t n, const float* draws, int64_t n_draws,
+                                  int32_t* cells, void* stream)
+{
+    if (n < 1 || n_draws < 0) return fail(RF_ERR_INVALID_ARG, "need n >= 1, n_draws >= 0");
+    if (n > rf::sample_noalloc_max_cells())
+        return fail(RF_ERR_UNSUPPORTED, "n = %lld exceeds the allocation-free sampler's limit of %lld cells",
+                    (long long)n, (long long)rf::sample_noalloc_max_cells());
+    if (n_draws == 0) return ok();
+    if (!scores || !draws || !cells) return fail(RF_ERR_INVALID_ARG, "an array is NULL");
+    double* ws = nullptr;
+    const hipError_t e = rf::sample_scratch(&ws);
+    if (e != hipSuccess) return hip_status(e, "scratch address of the allocation-free sampler");
+    return hip_status(rf::launch_sample(scores, n, draws, n_draws, cells, ws, static_cast<hipStream_t>(stream)),
+                      "candidate sampling (allocation-free)");
+}
+
 rf_status rf_prune_mask(const float* density, const int32_t* nbr_off, const int32_t* nbr_idx, int64_t n_sites,
                         float threshold, uint8_t* mask, void* stream)
 {

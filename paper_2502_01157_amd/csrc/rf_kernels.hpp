@@ -188,6 +188,9 @@ int64_t keep_workspace_count(int64_t n);  // int64 values of the keep-index work
 hipError_t launch_keep_index(const uint8_t* keep, int64_t n, int32_t* kept, int64_t* n_kept, int64_t* workspace,
                              hipStream_t stream);
 int64_t sample_workspace_doubles(int64_t n);
+int64_t sample_noalloc_max_cells();
+// the per-device address of the allocation-free sampler's scratch (current device)
+hipError_t sample_scratch(double** out);
 hipError_t launch_sample(const float* score, int64_t n, const float* draws, int64_t n_draws, int32_t* out,
                          double* workspace, hipStream_t stream);
 hipError_t launch_unpack(int sh_degree, bool bf16, const SceneView& s, float* planes_out, float* density_out,

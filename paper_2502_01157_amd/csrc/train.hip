@@ -11,6 +11,8 @@
 // (per block of 1024, then the block totals in one block, then the offsets) and inverts
 // the cumulative sum at each draw by binary search.
 
+#include <mutex>
+
 #include "rf_device.hpp"
 #include "rf_kernels.hpp"
 
@@ -449,7 +451,41 @@ int64_t sample_workspace_doubles(int64_t n)
     return n + (n + kScanTile - 1) / kScanTile;
 }
 
+// Scratch of the allocation-free sampler (rf_sample_cells_noalloc): the
+// cumulative scores and tile offsets of up to kNoAllocMaxCells cells. Every
+// GPU the library runs on holds its own copy until the process ends; calls on
+// one GPU share it, so calls that overlap on one GPU race. Nothing needs
+// clearing: each call writes every value it reads before reading it.
+constexpr int64_t kNoAllocMaxCells = int64_t(1) << 22;
+constexpr int64_t kNoAllocScratchDoubles = kNoAllocMaxCells + (kNoAllocMaxCells + kScanTile - 1) / kScanTile;
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
 
+// The device address of `scratch` on each device, looked up once per device
+// with that device current (in host code the array's name is not a device
+// address).
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxScratchDevices] = {};
+
+int64_t sample_noalloc_max_cells() { return kNoAllocMaxCells; }
+
+hipError_t sample_scratch(double** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_sample(const float* score, int64_t n, const float* draws, int64_t n_draws, int32_t* out,
                          double* workspace, hipStream_t stream)
