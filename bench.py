@@ -356,7 +356,7 @@ def main() -> int:
                                  "ms_per_step": round(results[(dt, "fwd_bwd_logged")][0], 4),
                                  "log_capacity": args.log_capacity,
                                  "log_bytes": int(R * (12 * args.log_capacity + 16))} for dt in dts}
-                           if walk_log is not None else None),
+                           if (main_dt, "fwd_bwd_logged") in results else None),
         "bf16_colour_error": bf16_err,
         "bf16_speedup_fwd_bwd": (round(results[("f32", "fwd_bwd")][0] / results[("bf16", "fwd_bwd")][0], 4)
                                  if len(dts) == 2 else None),
@@ -565,8 +565,10 @@ def serving(rf, packed, scene, bound, dts):
     """Continuous-batching replay of 512 render requests (exponential inter-arrivals,
     mean 5 ms; sizes uniform over 256^2, 512^2, 1024^2, 1920x1080; poses inside
     [-0.8, 0.8]^3) against the resident 1M-site scene, forward only; then the same
-    requests all arriving at once, whose throughput is the server's capacity. Each
-    server is warmed up with 16 of the requests before it is timed."""
+    requests all arriving at once, whose throughput is the server's capacity. Both
+    forms of the server (batched launches; one persistent kernel). The replay is
+    timed on a fresh server, and again on a server warmed up with 16 of the
+    requests; the capacity run follows a warm-up too."""
     import numpy as np
 
     import synth
@@ -586,23 +588,35 @@ def serving(rf, packed, scene, bound, dts):
     # slowly: 16 requests all at once warm it up before each timed replay
     warm = [dict(r, arrival=0.0) for r in stream[:16]]
     for dt in dts:
-        with Server(packed[dt], bound, pool_bytes=1 << 30, max_inflight=64) as srv:
-            replay(srv, warm, timeout_s=120)
-            st0 = srv.stats()
-            out = replay(srv, stream, timeout_s=120)
-            st = srv.stats()
-        with Server(packed[dt], bound, pool_bytes=1 << 30, max_inflight=64) as srv:
-            replay(srv, warm, timeout_s=120)
-            cap = replay(srv, burst, timeout_s=120)
-        res[dt] = {"p50_ms": round(out["p50_ms"], 3), "p99_ms": round(out["p99_ms"], 3),
-                   "mean_ms": round(out["mean_ms"], 3), "mrays_s": round(out["mrays_per_s"], 2),
-                   "launches": int(st["launches"] - st0["launches"]),
-                   "busy_rejections": int(st["rejected_busy"] - st0["rejected_busy"]),
-                   "copy_out_ms_mean": round(float(np.nanmean(out["copy_ms"])), 3),
-                   "burst_mrays_s": round(cap["mrays_per_s"], 2)}
-        log(f"serving {dt}: p50 {out['p50_ms']:.2f} ms, p99 {out['p99_ms']:.2f} ms, "
-            f"{out['mrays_per_s']:.1f} Mrays/s sustained (offered {offered:.1f}), {res[dt]['launches']} launches; "
-            f"all {len(burst)} requests at once: {cap['mrays_per_s']:.1f} Mrays/s")
+        res[dt] = {}
+        for mode in ("launches", "persistent"):
+            def server():
+                return Server(packed[dt], bound, pool_bytes=1 << 30, max_inflight=64, mode=mode)
+
+            # a fresh server, no warm-up: the first requests arrive on a just-created server
+            with server() as srv:
+                cold = replay(srv, stream, timeout_s=120)
+            with server() as srv:
+                replay(srv, warm, timeout_s=120)
+                st0 = srv.stats()
+                out = replay(srv, stream, timeout_s=120)
+                st = srv.stats()
+            with server() as srv:
+                replay(srv, warm, timeout_s=120)
+                cap = replay(srv, burst, timeout_s=120)
+            res[dt][mode] = {"p50_ms": round(out["p50_ms"], 3), "p99_ms": round(out["p99_ms"], 3),
+                             "mean_ms": round(out["mean_ms"], 3), "mrays_s": round(out["mrays_per_s"], 2),
+                             "cold_p50_ms": round(cold["p50_ms"], 3), "cold_p99_ms": round(cold["p99_ms"], 3),
+                             "cold_max_ms": round(float(np.nanmax(cold["latency_s"])) * 1e3, 3),
+                             "launches": int(st["launches"] - st0["launches"]),
+                             "busy_rejections": int(st["rejected_busy"] - st0["rejected_busy"]),
+                             "copy_out_ms_mean": round(float(np.nanmean(out["copy_ms"])), 3),
+                             "burst_mrays_s": round(cap["mrays_per_s"], 2)}
+            log(f"serving {dt} {mode}: p50 {out['p50_ms']:.2f} ms, p99 {out['p99_ms']:.2f} ms "
+                f"(fresh server: p50 {cold['p50_ms']:.2f}, p99 {cold['p99_ms']:.2f} ms), "
+                f"{out['mrays_per_s']:.1f} Mrays/s sustained (offered {offered:.1f}), "
+                f"{res[dt][mode]['launches']} launches; all {len(burst)} requests at once: "
+                f"{cap['mrays_per_s']:.1f} Mrays/s")
     return res
 
 

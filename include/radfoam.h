@@ -567,6 +567,28 @@ typedef struct {
 
 rf_status rf_server_create(const rf_packed_scene *scene, const rf_params *params, const rf_bound *bound,
                            size_t pool_bytes, int32_t max_inflight, rf_server **out);
+/* rf_server_create with a choice of form (mode):
+ *   RF_SERVE_LAUNCHES    a host scheduler thread batches the pending tiles of
+ *                        all admitted requests into ordinary kernel launches
+ *                        (rf_server_create);
+ *   RF_SERVE_PERSISTENT  one persistent kernel (the paper's low-overhead
+ *                        renderer, Sec. 3.4) serves requests as they arrive:
+ *                        a dispatcher wavefront reads request records from a
+ *                        ring in coherent host memory and opens their slots,
+ *                        worker wavefronts claim tiles of the oldest open
+ *                        request and signal each completed request through
+ *                        host memory. Every wait in the kernel is bounded: it
+ *                        leaves 2 ms after its last request once everything
+ *                        admitted is done, or after 1 s without a request,
+ *                        and the scheduler relaunches it when requests wait.
+ * Results are bitwise the same in both forms (the same ray generation and
+ * walk). rf_server_destroy waits for admitted requests (at most 60 s) and,
+ * in the persistent form, for the kernel to leave (at most 30 s; on a
+ * timeout it returns RF_ERR_HIP and keeps the server's memory). */
+#define RF_SERVE_LAUNCHES 0
+#define RF_SERVE_PERSISTENT 1
+rf_status rf_server_create_mode(const rf_packed_scene *scene, const rf_params *params, const rf_bound *bound,
+                                size_t pool_bytes, int32_t max_inflight, int32_t mode, rf_server **server);
 rf_status rf_server_submit(rf_server *server, const rf_camera *camera, int32_t start_cell, uint64_t *req_id);
 rf_status rf_server_poll(rf_server *server, uint64_t *done_ids, int32_t cap, int32_t *n_done);
 rf_status rf_server_result(rf_server *server, uint64_t req_id, float *rgba, size_t bytes);

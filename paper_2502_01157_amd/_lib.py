@@ -178,7 +178,11 @@ def lib() -> ctypes.CDLL:
         L.rf_server_result.argtypes = [P, ctypes.c_uint64, P, ctypes.c_size_t]
         L.rf_server_stats_get.argtypes = [P, ctypes.POINTER(ServerStats)]
         L.rf_server_destroy.argtypes = [P]
-        for name in ("rf_server_create", "rf_server_submit", "rf_server_poll", "rf_server_result",
+        L.rf_server_create_mode.argtypes = [ctypes.POINTER(PackedSceneDesc), ctypes.POINTER(Params),
+                                            ctypes.POINTER(BoundDesc), ctypes.c_size_t, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]
+        for name in ("rf_server_create", "rf_server_create_mode", "rf_server_submit", "rf_server_poll",
+                     "rf_server_result",
                      "rf_server_stats_get", "rf_server_destroy"):
             getattr(L, name).restype = st
         _lib = L

@@ -24,86 +24,22 @@
 
 #include "rf_device.hpp"
 #include "rf_kernels.hpp"
+#include "rf_locate.hpp"
 
 namespace rf {
-
-__device__ inline double dist2(const float* x, double px, double py, double pz)
-{
-    const double dx = px - (double)x[0], dy = py - (double)x[1], dz = pz - (double)x[2];
-    return fma(dz, dz, fma(dy, dy, dx * dx));
-}
 
 template <int DEG, bool BF16>
 __global__ __launch_bounds__(kBlock) void k_locate(LocateArgs a)
 {
     const int64_t q = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (q >= a.n_points) return;
-    const SceneView& s = a.s;
     const float px = a.points[3 * q], py = a.points[3 * q + 1], pz = a.points[3 * q + 2];
     int seed = 0;
-    if (a.seed) {
+    if (a.seed)
         seed = a.seed[q];
-    } else if (a.grid) {
-        int ix[3];
-        const float pp[3] = {px, py, pz};
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            // clamped in float, so that NaN and far-away points convert safely
-            const float f = (pp[k] - a.grid_lo[k]) * a.grid_inv[k];
-            ix[k] = f >= (float)(a.grid_n - 1) ? a.grid_n - 1 : (f >= 1.0f ? (int)f : 0);
-        }
-        seed = a.grid[((int64_t)ix[2] * a.grid_n + ix[1]) * a.grid_n + ix[0]];
-    }
-    if (seed < 0 || (int64_t)seed >= s.n_sites) {
-        a.cells[q] = -1;
-        return;
-    }
-    uint2 ref = s.row[seed];
-    int steps = 0;
-    // phase 1: FP32 steps across bisector planes
-    for (; steps < a.max_steps; ++steps) {
-        const int beg = ref_beg(ref), deg = ref_deg(ref);
-        float best = 0.0f;
-        int bk = -1;
-        for (int k = 0; k < deg; ++k) {
-            const float4 pl = s.planes[beg + k];
-            const float gain = fmaf(pl.z, pz, fmaf(pl.y, py, pl.x * px)) - pl.w;
-            if (gain > best) {
-                best = gain;
-                bk = k;
-            }
-        }
-        if (bk < 0) break;
-        ref = s.adj[beg + bk];
-    }
-    // phase 2: FP64 squared distances to the sites
-    int cur = ref_cell(ref);
-    float xc[3];
-    load_site<DEG, BF16>(s.rec, cur, xc);
-    double dcur = dist2(xc, px, py, pz);
-    for (; steps < a.max_steps; ++steps) {
-        const int beg = ref_beg(ref), deg = ref_deg(ref);
-        int bj = cur;
-        double bd = dcur;
-        uint2 bref = ref;
-        for (int k = 0; k < deg; ++k) {
-            const uint2 nb = s.adj[beg + k];
-            const int j = ref_cell(nb);
-            float xj[3];
-            load_site<DEG, BF16>(s.rec, j, xj);
-            const double dj = dist2(xj, px, py, pz);
-            if (dj < bd || (dj == bd && j < bj)) {
-                bd = dj;
-                bj = j;
-                bref = nb;
-            }
-        }
-        if (bj == cur) break;
-        cur = bj;
-        dcur = bd;
-        ref = bref;
-    }
-    a.cells[q] = steps < a.max_steps ? cur : -2;
+    else if (a.grid)
+        seed = grid_seed(a.grid, a.grid_n, a.grid_lo, a.grid_inv, px, py, pz);
+    a.cells[q] = locate_point<DEG, BF16>(a.s, px, py, pz, seed, a.max_steps);
 }
 
 template <int DEG, bool BF16>

@@ -36,7 +36,9 @@
 #include "radfoam.h"
 #include "rf_device.hpp"
 #include "rf_kernels.hpp"
+#include "rf_locate.hpp"
 #include "rf_walk.hpp"
+#include "serve_protocol.hpp"
 
 namespace rf {
 
@@ -115,6 +117,253 @@ static hipError_t launch_batch(int deg, bool bf16, const BatchArgs& a, hipStream
     return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------------------
+// Persistent form: one launch serves requests as they arrive.
+//
+// Block 0 is the dispatcher wavefront; every other block is one worker
+// wavefront. The protocol (request ring in coherent host memory, slot
+// records and claim/done words in device memory) is in serve_protocol.hpp.
+// Workers take the oldest open request (its 64 slots are inspected by the 64
+// lanes at once), claim kClaimTiles tiles of it, and render each tile exactly
+// as k_serve_tiles does. Every wait is bounded: the dispatcher leaves when the
+// host asks, or once no request has arrived for `idle_ticks` and every
+// admitted request is done, or after `hard_ticks` without a new request; a
+// worker leaves when the dispatcher has left and no request is open, or after
+// `hard_ticks` without a tile; both also leave after kIdleIterCap idle polls
+// whatever the clock says. The host relaunches the kernel when requests wait
+// and no launch is running.
+// ---------------------------------------------------------------------------
+constexpr int kClaimTiles = 4;
+constexpr uint32_t kIdleIterCap = 1u << 22;  // ~4 s of idle polls at ~1 us each
+
+struct DevEnv {
+    __device__ static uint64_t dev_load_acquire(const uint64_t* p)
+    {
+        return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ static void dev_store_relaxed(uint64_t* p, uint64_t v)
+    {
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ static void dev_store_release(uint64_t* p, uint64_t v)
+    {
+        __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ static void dev_fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+    __device__ static uint64_t dev_fetch_add_acq_rel(uint64_t* p, uint64_t v)
+    {
+        return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ static void sys_store_release(uint64_t* p, uint64_t v)
+    {
+        __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    __device__ static uint32_t word_load(const uint32_t* p)
+    {
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ static void copy_record(sp::Req* dst, const sp::Req* src)
+    {
+        const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
+        uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+        for (int k = 0; k < sp::kReqWords; ++k) d[k] = word_load(s + k);
+    }
+};
+using Proto = sp::Protocol<DevEnv>;
+
+struct PersistArgs {
+    SceneView s;
+    float eps;
+    int32_t max_steps;
+    int32_t bound_kind;
+    float bound[6];
+    sp::HostCtl* host;  // coherent host memory (device-visible pointer)
+    sp::DevCtl* dev;
+    float* pool;        // pinned host output pool
+    const int32_t* grid;  // seed grid of located cells (requests without a start cell)
+    int32_t grid_n;
+    float grid_lo[3], grid_inv[3];
+    int64_t consumed0;  // records consumed before this launch
+    uint64_t idle_ticks, hard_ticks;  // wall-clock ticks
+};
+
+template <int DEG, bool BF16>
+__device__ void persistent_dispatcher(const PersistArgs& a, int lane)
+{
+    int64_t consumed = a.consumed0;
+    uint64_t last = wall_clock64();
+    uint32_t idle_iters = 0;
+    while (idle_iters < kIdleIterCap) {
+        const int64_t n_req = __hip_atomic_load(&a.host->n_requests, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+        // the host never has more than kSlots records unconsumed; anything else is not a count it wrote
+        if (n_req < consumed || n_req - consumed > sp::kReqRing) break;
+        if (consumed < n_req) {
+            // the record, one word per lane, from the host ring
+            const uint32_t* src = reinterpret_cast<const uint32_t*>(&a.host->ring[consumed % sp::kReqRing]);
+            uint32_t w = 0;
+            if (lane < sp::kReqWords) w = __hip_atomic_load(src + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            const int slot = __shfl((int)w, (int)(offsetof(sp::Req, slot) / 4));
+            const uint32_t gen = (uint32_t)__shfl((int)w, (int)(offsetof(sp::Req, gen) / 4));
+            int start = __shfl((int)w, (int)(offsetof(sp::Req, start) / 4));
+            if (start < 0) {
+                // the camera's cell, located from the seed grid
+                const float px = __int_as_float(__shfl((int)w, (int)(offsetof(sp::Req, pos) / 4)));
+                const float py = __int_as_float(__shfl((int)w, (int)(offsetof(sp::Req, pos) / 4) + 1));
+                const float pz = __int_as_float(__shfl((int)w, (int)(offsetof(sp::Req, pos) / 4) + 2));
+                if (lane == 0)
+                    start = locate_point<DEG, BF16>(a.s, px, py, pz,
+                                                    grid_seed(a.grid, a.grid_n, a.grid_lo, a.grid_inv, px, py, pz),
+                                                    1 << 20);
+                start = __shfl(start, 0);
+                if (lane == (int)(offsetof(sp::Req, start) / 4)) w = (uint32_t)start;
+            }
+            if (slot >= 0 && slot < sp::kSlots && gen != 0) {
+                uint32_t* dst = reinterpret_cast<uint32_t*>(&a.dev->slots[slot]);
+                if (lane < sp::kReqWords) __hip_atomic_store(dst + lane, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // every lane's words of the record before the slot opens
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __builtin_amdgcn_wave_barrier();
+                if (lane == 0) Proto::activate(a.dev, slot, gen);
+            }
+            ++consumed;
+            if (lane == 0)
+                __hip_atomic_store(&a.host->consumed, consumed, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            last = wall_clock64();
+            idle_iters = 0;
+            continue;
+        }
+        if (__hip_atomic_load(&a.host->shutdown, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+        const uint64_t quiet = wall_clock64() - last;
+        if (quiet > a.idle_ticks) {
+            const bool idle = Proto::slot_idle(a.dev, lane);  // lane = slot (kSlots == kWave)
+            if (__ballot(!idle) == 0) break;                 // everything admitted is done
+            if (quiet > a.hard_ticks) break;                 // no request for long: the host relaunches
+        }
+        ++idle_iters;
+        __builtin_amdgcn_s_sleep(16);
+    }
+    if (lane == 0) __hip_atomic_store(&a.dev->stop, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int DEG, bool BF16>
+__device__ void persistent_worker(const PersistArgs& a, int lane)
+{
+    uint64_t last = wall_clock64();
+    uint32_t idle_iters = 0;
+    while (idle_iters < kIdleIterCap) {
+        uint64_t seq = ~0ull;
+        const bool op = Proto::open(a.dev, lane, &seq);  // lane = slot
+        if (!op) seq = ~0ull;
+        const uint64_t open_lanes = __ballot(op);
+        if (open_lanes == 0) {
+            if (__hip_atomic_load(&a.dev->stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) break;
+            if (wall_clock64() - last > a.hard_ticks) break;
+            ++idle_iters;
+            __builtin_amdgcn_s_sleep(32);
+            continue;
+        }
+        // the oldest open request
+        uint64_t m = seq;
+#pragma unroll
+        for (int off = kWave / 2; off >= 1; off >>= 1) {
+            const uint64_t o = __shfl_xor(m, off);
+            m = o < m ? o : m;
+        }
+        const int slot = __builtin_ctzll(__ballot(op && seq == m));
+        int cnt = 0, first = 0;
+        sp::Req rec;
+        if (lane == 0) cnt = Proto::claim(a.dev, slot, kClaimTiles, &first, &rec);
+        cnt = __shfl(cnt, 0);
+        if (cnt == 0) {
+            ++idle_iters;
+            continue;
+        }
+        first = __shfl(first, 0);
+        // the record, from lane 0 to every lane
+        uint32_t* rw = reinterpret_cast<uint32_t*>(&rec);
+        for (int k = 0; k < sp::kReqWords; ++k) rw[k] = (uint32_t)__shfl((int)rw[k], 0);
+        const int W = rec.width, H = rec.height;
+        const int tiles_x = (W + 7) / 8;
+        float* out_base = a.pool + sp::req_out_offset(rec);
+        for (int j = 0; j < cnt; ++j) {
+            const int local = first + j;
+            const int px = (local % tiles_x) * 8 + (lane & 7);
+            const int py = (local / tiles_x) * 8 + (lane >> 3);
+            if (px < W && py < H) {
+                float d[3], tmax;
+                camera_ray(rec.rot, rec.pos, rec.model, rec.focal, W, H, px, py, a.bound_kind, a.bound, d, &tmax);
+                RayResult res;
+                walk_forward<DEG, BF16, false>(a.s, rec.pos[0], rec.pos[1], rec.pos[2], d[0], d[1], d[2], tmax,
+                                               rec.start, a.eps, a.max_steps, nullptr, nullptr, 0, res);
+                float4* out = reinterpret_cast<float4*>(out_base) + ((int64_t)py * W + px);
+                *out = make_float4(res.C[0], res.C[1], res.C[2], res.T);
+            }
+            // this tile's pixels visible to the host before it counts as done
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) (void)Proto::tile_done(a.dev, a.host, rec);
+        }
+        last = wall_clock64();
+        idle_iters = 0;
+    }
+}
+
+template <int DEG, bool BF16>
+__global__ __launch_bounds__(kWave) void k_serve_persistent(PersistArgs a)
+{
+    const int lane = threadIdx.x;
+    if (blockIdx.x == 0)
+        persistent_dispatcher<DEG, BF16>(a, lane);
+    else
+        persistent_worker<DEG, BF16>(a, lane);
+}
+
+static const void* persistent_kernel(int deg, bool bf16)
+{
+    switch (deg * 2 + (bf16 ? 1 : 0)) {
+    case 0: return reinterpret_cast<const void*>(&k_serve_persistent<0, false>);
+    case 1: return reinterpret_cast<const void*>(&k_serve_persistent<0, true>);
+    case 2: return reinterpret_cast<const void*>(&k_serve_persistent<1, false>);
+    case 3: return reinterpret_cast<const void*>(&k_serve_persistent<1, true>);
+    case 4: return reinterpret_cast<const void*>(&k_serve_persistent<2, false>);
+    case 5: return reinterpret_cast<const void*>(&k_serve_persistent<2, true>);
+    case 6: return reinterpret_cast<const void*>(&k_serve_persistent<3, false>);
+    case 7: return reinterpret_cast<const void*>(&k_serve_persistent<3, true>);
+    }
+    return nullptr;
+}
+
+static hipError_t launch_persistent(int deg, bool bf16, const PersistArgs& a, int blocks, hipStream_t stream)
+{
+    const void* f = persistent_kernel(deg, bf16);
+    if (!f || blocks < 2) return hipErrorInvalidValue;
+    PersistArgs args = a;
+    void* params[] = {&args};
+    return hipLaunchKernel(f, dim3((unsigned)blocks), dim3(kWave), params, 0, stream);
+}
+
+__global__ void k_clear_stop(sp::DevCtl* d) { __hip_atomic_store(&d->stop, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+static hipError_t launch_clear_stop(sp::DevCtl* d, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_clear_stop, dim3(1), dim3(1), 0, stream, d);
+    return hipGetLastError();
+}
+
+// Blocks of the persistent grid: as many one-wavefront blocks as the device
+// holds at once (so the dispatcher and every worker are resident together).
+static hipError_t persistent_blocks(int deg, bool bf16, int device, int* blocks)
+{
+    const void* f = persistent_kernel(deg, bf16);
+    if (!f) return hipErrorInvalidValue;
+    int per_cu = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kWave, 0);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return e;
+    *blocks = std::max(2, std::min(per_cu * cus, 8192));
+    return hipSuccess;
+}
+
 }  // namespace rf
 
 // ---------------------------------------------------------------------------
@@ -137,6 +386,16 @@ struct rf_server {
     uint32_t* host_desc[rf::kLaunchesInFlight] = {nullptr, nullptr};
     hipEvent_t done_ev[rf::kLaunchesInFlight] = {nullptr, nullptr};
     int max_inflight = 0;
+    // persistent form (mode RF_SERVE_PERSISTENT)
+    int mode = RF_SERVE_LAUNCHES;
+    rf::sp::HostCtl* hctl = nullptr;  // coherent pinned host memory
+    rf::sp::DevCtl* dctl = nullptr;
+    hipEvent_t pk_ev = nullptr;       // completion of the running persistent launch
+    bool pk_running = false;
+    int pk_blocks = 0;
+    int64_t written = 0;              // records written into the host ring
+    uint64_t idle_ticks = 0, hard_ticks = 0;
+    std::chrono::steady_clock::time_point stop_deadline;  // destroy stops waiting for admitted requests then
 
     enum State { FREE = 0, QUEUED, DONE };
     struct Slot {
@@ -330,6 +589,81 @@ bool launch_next(rf_server* s)
     return true;
 }
 
+// Persistent form: marks the requests whose completion word shows their
+// sequence number done, and relaunches the kernel when requests wait and no
+// launch is running. Called with the lock held.
+void persistent_step(rf_server* s)
+{
+    for (int k = 0; k < s->max_inflight; ++k) {
+        rf_server::Slot& sl = s->slots[k];
+        if (sl.state != rf_server::QUEUED) continue;
+        if (__atomic_load_n(&s->hctl->done_seq[k], __ATOMIC_ACQUIRE) == sl.seq) {
+            sl.state = rf_server::DONE;
+            sl.retired = sl.n_tiles;
+            s->stats.completed++;
+            s->stats.rays_done += (int64_t)sl.width * sl.height;
+        }
+    }
+    if (s->pk_running) {
+        const hipError_t q = hipEventQuery(s->pk_ev);
+        if (q == hipErrorNotReady) return;
+        s->pk_running = false;
+        if (q != hipSuccess && s->worker_status == RF_OK) {
+            s->worker_status = RF_ERR_HIP;
+            snprintf(s->worker_err, sizeof s->worker_err, "persistent launch failed: %s", hipGetErrorString(q));
+            return;
+        }
+    }
+    const int64_t consumed = __atomic_load_n(&s->hctl->consumed, __ATOMIC_ACQUIRE);
+    if (consumed >= s->written || s->worker_status != RF_OK) return;
+    rf::PersistArgs a;
+    memset(&a, 0, sizeof a);
+    a.s = scene_view(s);
+    a.eps = s->params.eps;
+    a.max_steps = s->params.max_steps;
+    a.bound_kind = s->bound.kind;
+    for (int k = 0; k < 6; ++k) a.bound[k] = s->bound.p[k];
+    a.host = s->hctl;
+    a.dev = s->dctl;
+    a.pool = s->pool;
+    a.grid = s->dev_grid;
+    a.grid_n = rf::kSeedGrid;
+    for (int k = 0; k < 3; ++k) {
+        a.grid_lo[k] = s->grid_lo[k];
+        a.grid_inv[k] = s->grid_inv[k];
+    }
+    a.consumed0 = consumed;
+    a.idle_ticks = s->idle_ticks;
+    a.hard_ticks = s->hard_ticks;
+    // the previous launch's stop flag is cleared by a small kernel (no memset node), then the launch
+    hipError_t e = rf::launch_clear_stop(s->dctl, s->stream);
+    if (e == hipSuccess)
+        e = rf::launch_persistent(s->scene.sh_degree, s->scene.attr_dtype == RF_BF16, a, s->pk_blocks, s->stream);
+    if (e == hipSuccess) e = hipEventRecord(s->pk_ev, s->stream);
+    if (e != hipSuccess) {
+        s->worker_status = RF_ERR_HIP;
+        snprintf(s->worker_err, sizeof s->worker_err, "persistent launch: %s", hipGetErrorString(e));
+        return;
+    }
+    s->pk_running = true;
+    s->stats.launches++;
+}
+
+void scheduler_persistent(rf_server* s)
+{
+    (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lock(s->mu);
+    for (;;) {
+        persistent_step(s);
+        bool queued = false;
+        for (int k = 0; k < s->max_inflight; ++k) queued |= s->slots[k].state == rf_server::QUEUED;
+        if (s->stop && (!queued || s->worker_status != RF_OK || std::chrono::steady_clock::now() > s->stop_deadline))
+            break;
+        // completions are polled every 20 us while requests are queued
+        s->cv.wait_for(lock, std::chrono::microseconds(queued ? 20 : 2000));
+    }
+}
+
 void scheduler(rf_server* s)
 {
     (void)hipSetDevice(s->device);
@@ -389,6 +723,9 @@ hipError_t build_seed_grid(rf_server* s)
 
 void release(rf_server* s)
 {
+    if (s->pk_ev) (void)hipEventDestroy(s->pk_ev);
+    if (s->dctl) (void)hipFree(s->dctl);
+    if (s->hctl) (void)hipHostFree(s->hctl);
     for (int b = 0; b < rf::kLaunchesInFlight; ++b) {
         if (s->done_ev[b]) (void)hipEventDestroy(s->done_ev[b]);
         if (s->dev_desc[b]) (void)hipFree(s->dev_desc[b]);
@@ -408,6 +745,14 @@ extern "C" {
 rf_status rf_server_create(const rf_packed_scene* scene, const rf_params* params, const rf_bound* bound,
                            size_t pool_bytes, int32_t max_inflight, rf_server** out)
 {
+    return rf_server_create_mode(scene, params, bound, pool_bytes, max_inflight, RF_SERVE_LAUNCHES, out);
+}
+
+rf_status rf_server_create_mode(const rf_packed_scene* scene, const rf_params* params, const rf_bound* bound,
+                                size_t pool_bytes, int32_t max_inflight, int32_t mode, rf_server** out)
+{
+    if (mode != RF_SERVE_LAUNCHES && mode != RF_SERVE_PERSISTENT)
+        return sfail(RF_ERR_INVALID_ARG, "mode must be RF_SERVE_LAUNCHES or RF_SERVE_PERSISTENT");
     if (!scene || !params || !bound || !out) return sfail(RF_ERR_INVALID_ARG, "NULL argument");
     *out = nullptr;
     if (!scene->base || scene->sh_degree < 0 || scene->sh_degree > 3 || scene->n_sites < 1)
@@ -424,6 +769,7 @@ rf_status rf_server_create(const rf_packed_scene* scene, const rf_params* params
     s->params = *params;
     s->bound = *bound;
     s->max_inflight = max_inflight;
+    s->mode = mode;
     s->slots.resize(max_inflight);
     s->pool_floats = pool_bytes / 16 * 4;
     s->free_ranges[0] = (int64_t)s->pool_floats;
@@ -441,13 +787,30 @@ rf_status rf_server_create(const rf_packed_scene* scene, const rf_params* params
         if (e == hipSuccess) e = hipEventCreateWithFlags(&s->done_ev[b], hipEventDisableTiming);
     }
     if (e == hipSuccess) e = build_seed_grid(s);
+    if (e == hipSuccess && mode == RF_SERVE_PERSISTENT) {
+        e = hipHostMalloc((void**)&s->hctl, sizeof(rf::sp::HostCtl), hipHostMallocCoherent);
+        if (e == hipSuccess) {
+            memset(s->hctl, 0, sizeof(rf::sp::HostCtl));
+            e = hipMalloc((void**)&s->dctl, sizeof(rf::sp::DevCtl));
+        }
+        if (e == hipSuccess) e = hipMemset(s->dctl, 0, sizeof(rf::sp::DevCtl));
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->pk_ev, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = rf::persistent_blocks(s->scene.sh_degree, s->scene.attr_dtype == RF_BF16, s->device, &s->pk_blocks);
+        int khz = 0;
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device);
+        if (e == hipSuccess && khz <= 0) e = hipErrorInvalidValue;
+        // leave 2 ms after the last request once everything is done; 1 s without requests at most
+        s->idle_ticks = (uint64_t)khz * 2;
+        s->hard_ticks = (uint64_t)khz * 1000;
+    }
     if (e != hipSuccess) {
         release(s);
         delete s;
         return sfail(e == hipErrorOutOfMemory ? RF_ERR_OOM : RF_ERR_HIP, "server allocation: %s", hipGetErrorString(e));
     }
     try {
-        s->worker = std::thread(scheduler, s);
+        s->worker = std::thread(mode == RF_SERVE_PERSISTENT ? scheduler_persistent : scheduler, s);
     } catch (...) {
         release(s);
         delete s;
@@ -501,7 +864,32 @@ rf_status rf_server_submit(rf_server* s, const rf_camera* cam, int32_t start_cel
     r.height = cam->height;
     r.start = start_cell;
     r.out_offset = off;
-    s->fifo.push_back(slot);
+    if (s->mode == RF_SERVE_PERSISTENT) {
+        rf::sp::Req q;
+        memset(&q, 0, sizeof q);
+        memcpy(q.rot, r.rot, sizeof q.rot);
+        memcpy(q.pos, r.pos, sizeof q.pos);
+        q.model = r.model;
+        q.focal = r.focal;
+        q.width = r.width;
+        q.height = r.height;
+        q.start = r.start;
+        q.slot = slot;
+        q.out_offset_lo = (int32_t)(uint32_t)((uint64_t)off & 0xffffffffu);
+        q.out_offset_hi = (int32_t)(uint32_t)((uint64_t)off >> 32);
+        q.seq_lo = (uint32_t)sl.seq;
+        q.seq_hi = (uint32_t)(sl.seq >> 32);
+        q.gen = (uint32_t)(1 + (sl.seq - 1) % 0xfffffffeull);  // nonzero, differs between a slot's requests
+        q.n_tiles = (int32_t)n_tiles;
+        // the record, then its count (the dispatcher reads the record after acquiring the count)
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&s->hctl->ring[s->written % rf::sp::kReqRing]);
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(&q);
+        for (int k = 0; k < rf::sp::kReqWords; ++k) __atomic_store_n(dst + k, src[k], __ATOMIC_RELAXED);
+        ++s->written;
+        __atomic_store_n(&s->hctl->n_requests, s->written, __ATOMIC_RELEASE);
+    } else {
+        s->fifo.push_back(slot);
+    }
     s->stats.submitted++;
     s->stats.inflight++;
     s->stats.pool_used_bytes += pixels * 16;
@@ -559,9 +947,24 @@ rf_status rf_server_destroy(rf_server* s)
     {
         std::lock_guard<std::mutex> lock(s->mu);
         s->stop = true;
+        s->stop_deadline = std::chrono::steady_clock::now() + std::chrono::seconds(60);
         s->cv.notify_one();
     }
     if (s->worker.joinable()) s->worker.join();  // finishes admitted requests, then returns
+    if (s->mode == RF_SERVE_PERSISTENT) {
+        // ask the running launch to leave, and wait for it a bounded time (it
+        // leaves by itself within about a second of idling in any case)
+        __atomic_store_n(&s->hctl->shutdown, 1, __ATOMIC_RELEASE);
+        const auto until = std::chrono::steady_clock::now() + std::chrono::seconds(30);
+        while (s->pk_running && hipEventQuery(s->pk_ev) == hipErrorNotReady) {
+            if (std::chrono::steady_clock::now() > until) {
+                // the launch still runs: keep its memory (leak it) rather than free it under the kernel
+                sfail(RF_ERR_HIP, "persistent server kernel did not stop within 30 s");
+                return RF_ERR_HIP;
+            }
+            std::this_thread::sleep_for(std::chrono::milliseconds(1));
+        }
+    }
     const hipError_t e = hipStreamSynchronize(s->stream);
     rf_status st = s->worker_status;
     if (st != RF_OK)

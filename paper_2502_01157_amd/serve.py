@@ -23,14 +23,20 @@ from .ops import PackedScene, bound_desc, camera_desc
 class Server:
     """A running server. Use as a context manager or call ``close()``."""
 
+    MODES = {"launches": 0, "persistent": 1}
+
     def __init__(self, scene: PackedScene, bound: tuple, pool_bytes: int = 1 << 30, max_inflight: int = 32,
-                 eps: float = 1e-4, max_steps: int = 8192):
+                 eps: float = 1e-4, max_steps: int = 8192, mode: str = "launches"):
+        """``mode="persistent"``: one persistent kernel serves requests as they
+        arrive (``RF_SERVE_PERSISTENT``); ``"launches"``: batched launches."""
         self.scene = scene  # keeps the packed workspace alive
         self._h = ctypes.c_void_p()
         p = L.Params(float(eps), int(max_steps))
         b = bound_desc(bound)
-        L.check(L.lib().rf_server_create(ctypes.byref(scene.desc), ctypes.byref(p), ctypes.byref(b),
-                                         int(pool_bytes), int(max_inflight), ctypes.byref(self._h)))
+        L.check(L.lib().rf_server_create_mode(ctypes.byref(scene.desc), ctypes.byref(p), ctypes.byref(b),
+                                              int(pool_bytes), int(max_inflight), self.MODES[mode],
+                                              ctypes.byref(self._h)))
+        self.mode = mode
         self.max_inflight = int(max_inflight)
         self._ids = (ctypes.c_uint64 * self.max_inflight)()
         self.sizes: Dict[int, tuple] = {}

@@ -70,6 +70,39 @@ def test_mix_equals_alone_bitwise(setup):
             np.testing.assert_array_equal(one["images"][0], alone[i])
 
 
+def test_persistent_server_mix_equals_alone_bitwise(setup):
+    """The persistent form (one kernel serving requests as they arrive):
+    bitwise the batch path's images in a burst, with staggered arrivals, with
+    requests whose camera cell the dispatcher locates itself, and after the
+    kernel has idled out and been relaunched."""
+    import time
+
+    rf, scene, packed, reqs, alone = setup
+    from paper_2502_01157_amd.serve import Server, replay
+
+    burst = [dict(r, arrival=0.0) for r in reqs]
+    with Server(packed, scene.bound, pool_bytes=8 << 20, max_inflight=16, mode="persistent") as srv:
+        print("persistent server: burst", flush=True)
+        out = replay(srv, burst, keep=range(len(reqs)), timeout_s=20)
+        st = srv.stats()
+        for i in range(len(reqs)):
+            np.testing.assert_array_equal(out["images"][i], alone[i], err_msg=f"request {i}")
+        assert st["completed"] == len(reqs) and st["inflight"] == 0 and st["pool_used_bytes"] == 0
+        print("persistent server: staggered, located start cells", flush=True)
+        located = [dict(r, start_cell=-1) for r in reqs]
+        out = replay(srv, located, keep=range(len(reqs)), timeout_s=20)
+        for i in range(len(reqs)):
+            np.testing.assert_array_equal(out["images"][i], alone[i], err_msg=f"located request {i}")
+        # idle long enough for the kernel to leave, then serve again (a relaunch)
+        time.sleep(0.05)
+        n0 = srv.stats()["launches"]
+        print("persistent server: after idling", flush=True)
+        out = replay(srv, burst[:6], keep=range(6), timeout_s=20)
+        for i in range(6):
+            np.testing.assert_array_equal(out["images"][i], alone[i])
+        assert srv.stats()["launches"] > n0
+
+
 def test_served_images_match_oracle(setup):
     rf, scene, packed, reqs, alone = setup
     osc = oracle.OracleScene.from_scene(scene)
