@@ -543,24 +543,34 @@ def test_gpu_finite_differences(rf, clustered):
         fd = (loss(sites0, dens0, sp) - loss(sites0, dens0, sm)) / (float(sp.ravel()[f]) - float(sm.ravel()[f]))
         assert abs(fd - gsh.ravel()[f]) <= 1e-3 * abs(gsh.ravel()[f]), (f, fd, gsh.ravel()[f])
     ref = oracle.trace(oracle.OracleScene.from_scene(scene), *rays, eps=1e-4, max_len=1024)
+    gpu_cells = rf.render_trace(p, o, d, t, s, max_len=1024)["cells"].cpu().numpy()
     checked = 0
-    for f in np.argsort(-np.abs(gs.ravel()))[:8]:
+    for f in np.argsort(-np.abs(gs.ravel()))[:40]:
+        if checked >= 4:
+            break
         i, c = divmod(int(f), 3)
-        h = 2e-5
-        sp, sm = sites0.copy(), sites0.copy()
-        sp[i, c] += h
-        sm[i, c] -= h
-        # rays whose cells the step changes (a face decision flips: the loss is
+        h = 4e-5
+        steps_ = []
+        for hh in (h, h / 2):
+            sp, sm = sites0.copy(), sites0.copy()
+            sp[i, c] += hh
+            sm[i, c] -= hh
+            steps_.append((sp, sm))
+        # rays whose cells a step changes (a face decision flips: the loss is
         # not differentiable there) get no upstream gradient on either side
         keep = np.ones(len(rays[2]), dtype=bool)
-        for sx in (sp, sm):
+        for sx in (x for pair in steps_ for x in pair):
             tr = oracle.trace(oracle.OracleScene(sx, scene.off, scene.idx, dens0, sh0, 3), *rays, eps=1e-4,
                               max_len=1024)
             keep &= np.all(tr["cells"] == ref["cells"], axis=1) & (tr["len"] == ref["len"])
+            # the GPU's own FP32 decisions too: a flip there, at a tie the
+            # oracle resolves the other way, is a jump of the GPU's loss
+            pk = rf.PackedScene(*to_dev(sx, scene.off, scene.idx, dens0, sh0), 3)
+            keep &= np.all(rf.render_trace(pk, o, d, t, s, max_len=1024)["cells"].cpu().numpy() == gpu_cells, axis=1)
         gk = np.where(keep[:, None], g, 0.0).astype(np.float32)
         gks, = to_dev(gk)
         gsk = rf.render_backward(p, o, d, t, s, rgb, tf, gks)[0].cpu().numpy()
-        if abs(gsk[i, c]) < 1e-3 * abs(gs[i, c]):
+        if abs(gsk[i, c]) < 1e-2 * abs(gs[i, c]):
             continue
 
         def lk(sites):
@@ -569,7 +579,12 @@ def test_gpu_finite_differences(rf, clustered):
             torch.cuda.synchronize()
             return float((rk.cpu().numpy().astype(np.float64) * gk).sum())
 
-        fd = (lk(sp) - lk(sm)) / (float(sp[i, c]) - float(sm[i, c]))
-        assert abs(fd - gsk[i, c]) <= 5e-2 * abs(gsk[i, c]), (i, c, fd, gsk[i, c], int((~keep).sum()))
+        fds = [(lk(sp) - lk(sm)) / (float(sp[i, c]) - float(sm[i, c])) for sp, sm in steps_]
+        # a site whose exits are nearly grazing is not smooth at this step: the
+        # two differences disagree, and it is not a test of the gradient
+        if abs(fds[0] - fds[1]) > 2e-2 * abs(fds[1]):
+            continue
+        fd = (4.0 * fds[1] - fds[0]) / 3.0  # Richardson: the h^2 term cancels
+        assert abs(fd - gsk[i, c]) <= 2e-2 * abs(gsk[i, c]), (i, c, fds, gsk[i, c], int((~keep).sum()))
         checked += 1
     assert checked >= 3
