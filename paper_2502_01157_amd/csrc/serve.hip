@@ -124,22 +124,34 @@ static hipError_t launch_batch(int deg, bool bf16, const BatchArgs& a, hipStream
 // wavefront. The protocol (request ring in coherent host memory, slot
 // records and claim/done words in device memory) is in serve_protocol.hpp.
 // Workers take the oldest open request (its 64 slots are inspected by the 64
-// lanes at once), claim kClaimTiles tiles of it, and render each tile exactly
-// as k_serve_tiles does. Every wait is bounded: the dispatcher leaves when the
-// host asks, or once no request has arrived for `idle_ticks` and every
-// admitted request is done, or after `hard_ticks` without a new request; a
-// worker leaves when the dispatcher has left and no request is open, or after
-// `hard_ticks` without a tile; both also leave after kIdleIterCap idle polls
-// whatever the clock says. The host relaunches the kernel when requests wait
-// and no launch is running.
+// lanes at once), claim up to kClaimTiles tiles of it (fewer when its tiles
+// left are fewer than that per worker), render each tile exactly as
+// k_serve_tiles does, and report the claim done once. An idle worker polls
+// one word (the count of openings) and naps between polls, longer once it
+// has been idle for a while. Every wait is bounded: the dispatcher leaves
+// when the host asks, or once no request has arrived for `idle_ticks` and
+// every admitted request is done, or after `hard_ticks` without a new
+// request; a worker leaves when the dispatcher has left and no request is
+// open, or after `hard_ticks` without a tile; both also leave after
+// kIdleIterCap units of idle polling whatever the clock says. The host
+// relaunches the kernel when requests wait and no launch is running.
 // ---------------------------------------------------------------------------
 constexpr int kClaimTiles = 4;
-constexpr uint32_t kIdleIterCap = 1u << 22;  // ~4 s of idle polls at ~1 us each
+constexpr uint32_t kIdleIterCap = 1u << 22;  // idle polling in units of ~1 us: ~4 s
 
 struct DevEnv {
     __device__ static uint64_t dev_load_acquire(const uint64_t* p)
     {
         return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ static uint64_t dev_load_relaxed(const uint64_t* p)
+    {
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ static void dev_fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+    __device__ static void word_store_relaxed(uint32_t* p, uint32_t v)
+    {
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __device__ static void dev_store_relaxed(uint64_t* p, uint64_t v)
     {
@@ -161,12 +173,6 @@ struct DevEnv {
     __device__ static uint32_t word_load(const uint32_t* p)
     {
         return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __device__ static void copy_record(sp::Req* dst, const sp::Req* src)
-    {
-        const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
-        uint32_t* d = reinterpret_cast<uint32_t*>(dst);
-        for (int k = 0; k < sp::kReqWords; ++k) d[k] = word_load(s + k);
     }
 };
 using Proto = sp::Protocol<DevEnv>;
@@ -194,10 +200,13 @@ __device__ void persistent_dispatcher(const PersistArgs& a, int lane)
     uint64_t last = wall_clock64();
     uint32_t idle_iters = 0;
     while (idle_iters < kIdleIterCap) {
-        const int64_t n_req = __hip_atomic_load(&a.host->n_requests, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+        // polled relaxed (an acquire at system scope would invalidate this
+        // XCD's L2 on every poll); acquired once a record is there
+        const int64_t n_req = __hip_atomic_load(&a.host->n_requests, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         // the host never has more than kSlots records unconsumed; anything else is not a count it wrote
         if (n_req < consumed || n_req - consumed > sp::kReqRing) break;
         if (consumed < n_req) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
             // the record, one word per lane, from the host ring
             const uint32_t* src = reinterpret_cast<const uint32_t*>(&a.host->ring[consumed % sp::kReqRing]);
             uint32_t w = 0;
@@ -218,8 +227,14 @@ __device__ void persistent_dispatcher(const PersistArgs& a, int lane)
                 if (lane == (int)(offsetof(sp::Req, start) / 4)) w = (uint32_t)start;
             }
             if (slot >= 0 && slot < sp::kSlots && gen != 0) {
+                // the record under its generation word's sequence lock (every
+                // lane runs the lock's stores and fences; they store one value)
                 uint32_t* dst = reinterpret_cast<uint32_t*>(&a.dev->slots[slot]);
-                if (lane < sp::kReqWords) __hip_atomic_store(dst + lane, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                constexpr int kGenWord = (int)(offsetof(sp::Req, gen) / 4);
+                Proto::begin_record(a.dev, slot);
+                if (lane < sp::kReqWords && lane != kGenWord)
+                    __hip_atomic_store(dst + lane, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                Proto::end_record(a.dev, slot, gen);
                 // every lane's words of the record before the slot opens
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 __builtin_amdgcn_wave_barrier();
@@ -232,7 +247,7 @@ __device__ void persistent_dispatcher(const PersistArgs& a, int lane)
             idle_iters = 0;
             continue;
         }
-        if (__hip_atomic_load(&a.host->shutdown, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+        if (__hip_atomic_load(&a.host->shutdown, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
         const uint64_t quiet = wall_clock64() - last;
         if (quiet > a.idle_ticks) {
             const bool idle = Proto::slot_idle(a.dev, lane);  // lane = slot (kSlots == kWave)
@@ -249,67 +264,107 @@ template <int DEG, bool BF16>
 __device__ void persistent_worker(const PersistArgs& a, int lane)
 {
     uint64_t last = wall_clock64();
-    uint32_t idle_iters = 0;
-    while (idle_iters < kIdleIterCap) {
+    uint32_t idle_units = 0;  // idle polls, in units of ~1 us
+    uint32_t naps = 0;        // consecutive polls that found nothing new
+    uint64_t seen = ~0ull;    // openings counted before the last scan that found nothing open
+    while (idle_units < kIdleIterCap) {
+        // the count's low 32 bits (an idle nap does not span 2^32 openings)
+        const uint64_t o = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)Proto::opened(a.dev));
+        if (o == seen) {
+            // nothing opened since a scan found every slot closed or fully claimed
+            if (__hip_atomic_load(&a.dev->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            if (wall_clock64() - last > a.hard_ticks) break;
+            // short naps first, then ~50 us between polls: a few thousand idle
+            // wavefronts polling at once would crowd the memory channel of
+            // these words, which the working wavefronts need too
+            if (naps < 64) {
+                __builtin_amdgcn_s_sleep(127);
+                idle_units += 4;
+            } else {
+                for (int r = 0; r < 16; ++r) __builtin_amdgcn_s_sleep(127);
+                idle_units += 64;
+            }
+            ++naps;
+            continue;
+        }
+        DevEnv::dev_fence_acquire();
         uint64_t seq = ~0ull;
-        const bool op = Proto::open(a.dev, lane, &seq);  // lane = slot
+        int64_t left = 0;
+        const bool op = Proto::open(a.dev, lane, &seq, &left);  // lane = slot
         if (!op) seq = ~0ull;
         const uint64_t open_lanes = __ballot(op);
         if (open_lanes == 0) {
-            if (__hip_atomic_load(&a.dev->stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) break;
-            if (wall_clock64() - last > a.hard_ticks) break;
-            ++idle_iters;
-            __builtin_amdgcn_s_sleep(32);
+            seen = o;
+            ++idle_units;
             continue;
         }
+        seen = ~0ull;
+        naps = 0;
         // the oldest open request
         uint64_t m = seq;
 #pragma unroll
         for (int off = kWave / 2; off >= 1; off >>= 1) {
-            const uint64_t o = __shfl_xor(m, off);
-            m = o < m ? o : m;
+            const uint64_t x = __shfl_xor(m, off);
+            m = x < m ? x : m;
         }
         const int slot = __builtin_ctzll(__ballot(op && seq == m));
-        int cnt = 0, first = 0;
-        sp::Req rec;
-        if (lane == 0) cnt = Proto::claim(a.dev, slot, kClaimTiles, &first, &rec);
-        cnt = __shfl(cnt, 0);
+        // up to kClaimTiles tiles, fewer while the request's tiles left do not
+        // give every worker that many: a small request is spread over the chip
+        const int64_t slot_left = __shfl(left, slot);
+        const int64_t per_worker = slot_left / (int64_t)(gridDim.x - 1);
+        const int k = (int)(per_worker < 1 ? 1 : per_worker > kClaimTiles ? kClaimTiles : per_worker);
+        sp::Claim c = {0, 0, 0, 0, 0};
+        int cnt = 0;
+        if (lane == 0) cnt = Proto::claim(a.dev, slot, k, &c);
+        cnt = __builtin_amdgcn_readfirstlane(cnt);
         if (cnt == 0) {
-            ++idle_iters;
+            ++idle_units;
             continue;
         }
-        first = __shfl(first, 0);
-        // the record, from lane 0 to every lane
-        uint32_t* rw = reinterpret_cast<uint32_t*>(&rec);
-        for (int k = 0; k < sp::kReqWords; ++k) rw[k] = (uint32_t)__shfl((int)rw[k], 0);
-        const int W = rec.width, H = rec.height;
+        c.first = __builtin_amdgcn_readfirstlane(c.first);
+        c.count = cnt;
+        c.n_tiles = __builtin_amdgcn_readfirstlane(c.n_tiles);
+        c.gen = __builtin_amdgcn_readfirstlane(c.gen);
+        // the claimed request's record, which stays in the slot while the claim is outstanding
+        DevEnv::dev_fence_acquire();
+        const uint32_t* rw = reinterpret_cast<const uint32_t*>(&a.dev->slots[slot]);
+        auto word = [&](size_t off) { return __builtin_amdgcn_readfirstlane(DevEnv::word_load(rw + off / 4)); };
+        float rot[9], pos[3];
+        for (int k = 0; k < 9; ++k) rot[k] = __uint_as_float(word(offsetof(sp::Req, rot) + 4 * k));
+        for (int k = 0; k < 3; ++k) pos[k] = __uint_as_float(word(offsetof(sp::Req, pos) + 4 * k));
+        const int model = (int)word(offsetof(sp::Req, model));
+        const float focal = __uint_as_float(word(offsetof(sp::Req, focal)));
+        const int W = (int)word(offsetof(sp::Req, width)), H = (int)word(offsetof(sp::Req, height));
+        const int start = (int)word(offsetof(sp::Req, start));
+        const int64_t out_off = (int64_t)(((uint64_t)word(offsetof(sp::Req, out_offset_hi)) << 32) |
+                                          word(offsetof(sp::Req, out_offset_lo)));
         const int tiles_x = (W + 7) / 8;
-        float* out_base = a.pool + sp::req_out_offset(rec);
+        float* out_base = a.pool + out_off;
         for (int j = 0; j < cnt; ++j) {
-            const int local = first + j;
+            const int local = c.first + j;
             const int px = (local % tiles_x) * 8 + (lane & 7);
             const int py = (local / tiles_x) * 8 + (lane >> 3);
             if (px < W && py < H) {
                 float d[3], tmax;
-                camera_ray(rec.rot, rec.pos, rec.model, rec.focal, W, H, px, py, a.bound_kind, a.bound, d, &tmax);
+                camera_ray(rot, pos, model, focal, W, H, px, py, a.bound_kind, a.bound, d, &tmax);
                 RayResult res;
-                walk_forward<DEG, BF16, false>(a.s, rec.pos[0], rec.pos[1], rec.pos[2], d[0], d[1], d[2], tmax,
-                                               rec.start, a.eps, a.max_steps, nullptr, nullptr, 0, res);
+                walk_forward<DEG, BF16, false>(a.s, pos[0], pos[1], pos[2], d[0], d[1], d[2], tmax, start, a.eps,
+                                               a.max_steps, nullptr, nullptr, 0, res);
                 float4* out = reinterpret_cast<float4*>(out_base) + ((int64_t)py * W + px);
                 *out = make_float4(res.C[0], res.C[1], res.C[2], res.T);
             }
-            // this tile's pixels visible to the host before it counts as done
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-            __builtin_amdgcn_wave_barrier();
-            if (lane == 0) (void)Proto::tile_done(a.dev, a.host, rec);
         }
+        // the claim's pixels visible to the host before its tiles count as done
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) (void)Proto::tiles_done(a.dev, a.host, slot, c);
         last = wall_clock64();
-        idle_iters = 0;
+        idle_units = 0;
     }
 }
 
 template <int DEG, bool BF16>
-__global__ __launch_bounds__(kWave) void k_serve_persistent(PersistArgs a)
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_serve_persistent(PersistArgs a)
 {
     const int lane = threadIdx.x;
     if (blockIdx.x == 0)

@@ -5,19 +5,33 @@
 // coherent host memory and publishes their count (n_requests) with a release
 // store. One dispatcher wavefront reads each new record (acquire on the
 // count), copies it into the request's slot in device memory, resets the
-// slot's done counter and opens the slot for claims with a release store of
-// its claim word. Dispatcher -> workers: a slot's claim word is
-// (generation << 32 | tiles claimed); a request's generation is nonzero and
-// unique among the requests a slot has held. Workers claim tiles with
-// fetch-and-add on the claim word and keep a claim only if it hit the
-// generation of the record they then read and lies below its tile count: a
-// claim that lands on a finished or recycled generation claims nothing. A
-// worker renders its tiles, releases their pixels to the host, and adds one
-// per tile to the slot's done counter (generation << 32 | tiles done); the
-// tile that completes the request stores the request's sequence number into
-// the slot's completion word in host memory (release), which the host polls.
-// A slot is recycled only after its request completed, so every claim that
-// counted has been rendered before the slot's record changes.
+// slot's done counter, opens the slot for claims with a release store of its
+// claim word and counts the opening in `opened`. Dispatcher -> workers: a
+// slot's claim word is (generation << 32 | tiles claimed); a request's
+// generation is nonzero and unique among the requests a slot has held.
+// Workers claim tiles with fetch-and-add on the claim word and keep a claim
+// only if it hit the generation the slot's record still holds and lies below
+// its tile count: a claim that lands on a finished or recycled generation
+// claims nothing. A worker renders the tiles of its claim, releases their
+// pixels to the host, and adds their number to the slot's done counter
+// (generation << 32 | tiles done); the claim that completes the request
+// stores the request's sequence number into the slot's completion word in
+// host memory (release), which the host polls. A slot is recycled only after
+// its request completed, so the record of a claim that counted stays in its
+// slot until that claim is done.
+//
+// A claim that lands after completion can still read the slot while the
+// dispatcher writes the next record into it, so a record is written as a
+// sequence lock on its generation word: the dispatcher clears the word,
+// writes the other words, then stores the new generation; a claimer reads
+// the record's tile count after its claim, fences, and reads the generation,
+// and keeps the claim only if the generation equals the claim word's
+// (generations of a slot never repeat, so a read that saw any word of a newer
+// record fails the check).
+//
+// Idle workers poll `opened` alone, and scan the slots only when it has
+// changed since their last scan that found nothing open: a slot opens only
+// by an activation, and tiles once claimed stay claimed.
 //
 // Every shared word is accessed with atomic operations of explicit order and
 // scope (records word by word, relaxed, ordered by the claim word's release
@@ -61,9 +75,17 @@ struct HostCtl {              // coherent host memory
 struct DevCtl {               // device memory
     uint64_t claim[kSlots];
     uint64_t done[kSlots];
+    uint64_t opened;          // activations so far (dispatcher, release)
     int32_t stop;             // dispatcher: no more requests in this launch
     int32_t pad;
     Req slots[kSlots];
+};
+
+// What a worker holds of a claim (the rest of the record stays in the slot).
+struct Claim {
+    int32_t first, count, n_tiles;
+    uint32_t gen;
+    uint64_t seq;
 };
 
 inline __host__ __device__ int64_t req_out_offset(const Req& r)
@@ -73,22 +95,45 @@ inline __host__ __device__ int64_t req_out_offset(const Req& r)
 inline __host__ __device__ uint64_t req_seq(const Req& r) { return ((uint64_t)r.seq_hi << 32) | r.seq_lo; }
 
 // Env supplies the atomics: dev_* at the scope shared by the workers (the
-// device), sys_* at the scope shared with the host, and word copies.
+// device), sys_* at the scope shared with the host, and relaxed word loads
+// and stores at device scope.
 template <class Env>
 struct Protocol {
-    // Dispatcher, after copying record `rec` into d->slots[slot]: reset the
-    // done counter and open the slot to claims of generation rec.gen.
+    // Dispatcher, before writing the words of a new record into slot s
+    // (the generation word excluded): mark the slot's record as being written.
+    static __host__ __device__ void begin_record(DevCtl* d, int s)
+    {
+        Env::word_store_relaxed(&d->slots[s].gen, 0u);
+        Env::dev_fence_release();
+    }
+
+    // Dispatcher, after writing them: publish the record's generation.
+    static __host__ __device__ void end_record(DevCtl* d, int s, uint32_t gen)
+    {
+        Env::dev_fence_release();
+        Env::word_store_relaxed(&d->slots[s].gen, gen);
+    }
+
+    // Dispatcher, after end_record: reset the done counter, open the slot to
+    // claims of generation gen, and count the opening.
     static __host__ __device__ void activate(DevCtl* d, int slot, uint32_t gen)
     {
         Env::dev_store_relaxed(&d->done[slot], (uint64_t)gen << 32);
         Env::dev_fence_release();
         Env::dev_store_release(&d->claim[slot], (uint64_t)gen << 32);
+        (void)Env::dev_fetch_add_acq_rel(&d->opened, (uint64_t)1);
     }
 
-    // Worker: is slot s open with tiles left? (its sequence number in *seq)
-    static __host__ __device__ bool open(DevCtl* d, int s, uint64_t* seq)
+    // Worker: activations so far. Before a scan of the slots the worker reads
+    // this, then fences (acquire): the scan sees every opening counted.
+    static __host__ __device__ uint64_t opened(DevCtl* d) { return Env::dev_load_relaxed(&d->opened); }
+
+    // Worker: is slot s open with tiles left? (its sequence number in *seq,
+    // the tiles not yet claimed in *left) A hint only, read without
+    // ordering: claim() validates what it takes.
+    static __host__ __device__ bool open(DevCtl* d, int s, uint64_t* seq, int64_t* left)
     {
-        const uint64_t c = Env::dev_load_acquire(&d->claim[s]);
+        const uint64_t c = Env::dev_load_relaxed(&d->claim[s]);
         const uint32_t g = (uint32_t)(c >> 32);
         if (g == 0) return false;
         const Req* r = &d->slots[s];
@@ -96,31 +141,44 @@ struct Protocol {
         const int32_t n = (int32_t)Env::word_load((const uint32_t*)&r->n_tiles);
         if ((int64_t)(c & kCountMask) >= (int64_t)n) return false;
         *seq = ((uint64_t)Env::word_load(&r->seq_hi) << 32) | Env::word_load(&r->seq_lo);
+        *left = (int64_t)n - (int64_t)(c & kCountMask);
         return true;
     }
 
     // Worker: claims up to k tiles of slot s. Returns the number of tiles
-    // claimed (0: none) with the first in *first and the record in *rec.
-    static __host__ __device__ int claim(DevCtl* d, int s, int k, int32_t* first, Req* rec)
+    // claimed (0: none), described in *out. While the claim is outstanding the
+    // slot keeps the claimed request's record: every lane may then read it
+    // (after an acquire fence of its own).
+    static __host__ __device__ int claim(DevCtl* d, int s, int k, Claim* out)
     {
         const uint64_t old = Env::dev_fetch_add_acq_rel(&d->claim[s], (uint64_t)k);
-        Env::copy_record(rec, &d->slots[s]);
-        if ((uint32_t)(old >> 32) != rec->gen) return 0;  // a generation that is gone
+        const uint32_t g = (uint32_t)(old >> 32);
+        if (g == 0) return 0;
+        const Req* r = &d->slots[s];
+        const int64_t n = (int32_t)Env::word_load((const uint32_t*)&r->n_tiles);
+        const uint64_t seq = ((uint64_t)Env::word_load(&r->seq_hi) << 32) | Env::word_load(&r->seq_lo);
+        Env::dev_fence_acquire();
+        // the generation after the reads: any word of a newer record read above shows here
+        if (Env::word_load(&r->gen) != g) return 0;
         const int64_t c = (int64_t)(old & kCountMask);
-        if (c >= rec->n_tiles) return 0;                   // nothing left
-        *first = (int32_t)c;
-        const int64_t left = rec->n_tiles - c;
-        return (int)(left < k ? left : k);
+        if (c >= n) return 0;  // nothing left
+        const int64_t left = n - c;
+        out->first = (int32_t)c;
+        out->count = (int32_t)(left < k ? left : k);
+        out->n_tiles = (int32_t)n;
+        out->gen = g;
+        out->seq = seq;
+        return out->count;
     }
 
-    // Worker: one tile of `rec` done (its pixels already released to the
-    // host). Returns true if it completed the request.
-    static __host__ __device__ bool tile_done(DevCtl* d, HostCtl* h, const Req& rec)
+    // Worker: the tiles of claim `c` in slot s done (their pixels already
+    // released to the host). Returns true if it completed the request.
+    static __host__ __device__ bool tiles_done(DevCtl* d, HostCtl* h, int s, const Claim& c)
     {
-        const uint64_t old = Env::dev_fetch_add_acq_rel(&d->done[rec.slot], (uint64_t)1);
-        if ((uint32_t)(old >> 32) != rec.gen) return false;  // cannot happen: the slot is not recycled before
-        if ((int64_t)(old & kCountMask) + 1 != rec.n_tiles) return false;
-        Env::sys_store_release(&h->done_seq[rec.slot], req_seq(rec));
+        const uint64_t old = Env::dev_fetch_add_acq_rel(&d->done[s], (uint64_t)c.count);
+        if ((uint32_t)(old >> 32) != c.gen) return false;  // cannot happen: the slot is not recycled before
+        if ((int64_t)(old & kCountMask) + c.count != c.n_tiles) return false;
+        Env::sys_store_release(&h->done_seq[s], c.seq);
         return true;
     }
 

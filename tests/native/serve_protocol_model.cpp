@@ -7,7 +7,9 @@
 // is running. Built with ThreadSanitizer by the test suite.
 //
 // Checks: every request completes exactly once; every tile is rendered
-// exactly once; every pixel the host reads after a completion was written by
+// exactly once; the record a claim renders from is its request's, whole,
+// for as long as the claim is outstanding (not torn by the next record's
+// write into the slot); every pixel the host reads after a completion was written by
 // its worker (ordered by the protocol's release and acquire); the launches
 // leave by themselves (idle and hard limits) and on shutdown.
 
@@ -15,7 +17,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
+#include <cstddef>
 #include <chrono>
 #include <random>
 #include <thread>
@@ -26,24 +30,51 @@
 using namespace rf::sp;
 using Clock = std::chrono::steady_clock;
 
+// Each operation may be delayed (a yield, now and then a pause of up to
+// 50 us): the threads interleave at every step of the protocol, as
+// wavefronts that are descheduled or wait on memory do.
+static void jitter()
+{
+    thread_local std::mt19937 rng(std::hash<std::thread::id>()(std::this_thread::get_id()));
+    const uint32_t r = rng();
+    if (r % 16 == 0) std::this_thread::yield();
+    if (r % 512 == 1) std::this_thread::sleep_for(std::chrono::microseconds(r % 50));
+}
+
 struct HostEnv {
-    static uint64_t dev_load_acquire(const uint64_t* p) { return __atomic_load_n(p, __ATOMIC_ACQUIRE); }
-    static void dev_store_relaxed(uint64_t* p, uint64_t v) { __atomic_store_n(p, v, __ATOMIC_RELAXED); }
-    static void dev_store_release(uint64_t* p, uint64_t v) { __atomic_store_n(p, v, __ATOMIC_RELEASE); }
+    static uint64_t dev_load_acquire(const uint64_t* p) { jitter(); return __atomic_load_n(p, __ATOMIC_ACQUIRE); }
+    static uint64_t dev_load_relaxed(const uint64_t* p) { jitter(); return __atomic_load_n(p, __ATOMIC_RELAXED); }
+    static void dev_fence_acquire() { __atomic_thread_fence(__ATOMIC_ACQUIRE); }
+    static void word_store_relaxed(uint32_t* p, uint32_t v) { jitter(); __atomic_store_n(p, v, __ATOMIC_RELAXED); }
+    static void dev_store_relaxed(uint64_t* p, uint64_t v) { jitter(); __atomic_store_n(p, v, __ATOMIC_RELAXED); }
+    static void dev_store_release(uint64_t* p, uint64_t v) { jitter(); __atomic_store_n(p, v, __ATOMIC_RELEASE); }
     static void dev_fence_release() { __atomic_thread_fence(__ATOMIC_RELEASE); }
-    static uint64_t dev_fetch_add_acq_rel(uint64_t* p, uint64_t v) { return __atomic_fetch_add(p, v, __ATOMIC_ACQ_REL); }
-    static void sys_store_release(uint64_t* p, uint64_t v) { __atomic_store_n(p, v, __ATOMIC_RELEASE); }
-    static uint32_t word_load(const uint32_t* p) { return __atomic_load_n(p, __ATOMIC_RELAXED); }
-    static void copy_record(Req* dst, const Req* src)
+    static uint64_t dev_fetch_add_acq_rel(uint64_t* p, uint64_t v)
     {
-        const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
-        uint32_t* d = reinterpret_cast<uint32_t*>(dst);
-        for (int k = 0; k < kReqWords; ++k) d[k] = word_load(s + k);
+        jitter();
+        return __atomic_fetch_add(p, v, __ATOMIC_ACQ_REL);
     }
+    static void sys_store_release(uint64_t* p, uint64_t v) { jitter(); __atomic_store_n(p, v, __ATOMIC_RELEASE); }
+    static uint32_t word_load(const uint32_t* p) { jitter(); return __atomic_load_n(p, __ATOMIC_RELAXED); }
 };
 using P = Protocol<HostEnv>;
 
-constexpr int kRequests = 1500;
+// A record read word by word as a wavefront's lanes read it: in a random
+// order, with pauses (a record may change while it is being read).
+static void read_record(Req* dst, const Req* src, std::mt19937& rng)
+{
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
+    uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+    int order[kReqWords];
+    for (int k = 0; k < kReqWords; ++k) order[k] = k;
+    std::shuffle(order, order + kReqWords, rng);
+    for (int j = 0; j < kReqWords; ++j) {
+        d[order[j]] = HostEnv::word_load(s + order[j]);
+        if (rng() % 4 == 0) std::this_thread::sleep_for(std::chrono::microseconds(rng() % 40));
+    }
+}
+
+constexpr int kRequests = 12000;
 constexpr int kMaxInflight = 3;
 constexpr int kWorkers = 6;
 constexpr int kClaim = 3;
@@ -55,6 +86,20 @@ static DevCtl* D;
 static std::vector<std::vector<std::atomic<int>>> rendered;  // [request][tile] render count
 static std::vector<std::vector<uint64_t>> pixels;            // [request][tile] plain "pixels"
 static std::atomic<int> dev_stop_seen{0};
+static std::atomic<int> torn{0};
+
+// The words of request r's record that the protocol does not use: each a
+// distinct function of r, so that a copy mixing two records shows.
+static uint32_t fill_word(int r, int k) { return (uint32_t)r * 2654435761u + (uint32_t)k * 40503u + 1u; }
+static bool is_fill_word(int k)
+{
+    const int proto[] = {(int)(offsetof(Req, slot) / 4), (int)(offsetof(Req, seq_lo) / 4),
+                         (int)(offsetof(Req, seq_hi) / 4), (int)(offsetof(Req, gen) / 4),
+                         (int)(offsetof(Req, n_tiles) / 4)};
+    for (int p : proto)
+        if (k == p) return false;
+    return true;
+}
 
 static const auto kIdle = std::chrono::microseconds(300);
 static const auto kHard = std::chrono::milliseconds(200);
@@ -73,7 +118,20 @@ static void dispatcher(int64_t consumed)
             for (int k = 0; k < kReqWords; ++k) w[k] = __atomic_load_n(src + k, __ATOMIC_RELAXED);
             if (rec.slot >= 0 && rec.slot < kSlots && rec.gen != 0) {
                 uint32_t* dst = reinterpret_cast<uint32_t*>(&D->slots[rec.slot]);
-                for (int k = 0; k < kReqWords; ++k) __atomic_store_n(dst + k, w[k], __ATOMIC_RELAXED);
+                const int gen_word = (int)(offsetof(Req, gen) / 4);
+                P::begin_record(D, rec.slot);
+                // the words in any order (a wavefront's store lands in no fixed
+                // order), with pauses, while late claims may read the slot
+                int order[kReqWords];
+                for (int k = 0; k < kReqWords; ++k) order[k] = k;
+                std::shuffle(order, order + kReqWords, rng);
+                for (int j = 0; j < kReqWords; ++j) {
+                    const int k = order[j];
+                    if (k == gen_word) continue;
+                    __atomic_store_n(dst + k, w[k], __ATOMIC_RELAXED);
+                    if (rng() % 16 == 0) std::this_thread::sleep_for(std::chrono::microseconds(rng() % 20));
+                }
+                P::end_record(D, rec.slot, rec.gen);
                 // a slow dispatcher: the new record sits in the slot before the slot reopens
                 if (rng() % 3 == 0) std::this_thread::sleep_for(std::chrono::microseconds(rng() % 60));
                 P::activate(D, rec.slot, rec.gen);
@@ -103,18 +161,11 @@ static void worker(unsigned seed)
     std::mt19937 rng(seed);
     auto last = Clock::now();
     uint32_t idle = 0;
+    uint64_t seen = ~0ull;  // openings counted before the last scan that found nothing open
     while (idle < kIdleCap) {
-        int best = -1;
-        uint64_t best_seq = ~0ull;
-        for (int s = 0; s < kSlots; ++s) {
-            uint64_t seq;
-            if (P::open(D, s, &seq) && seq < best_seq) {
-                best_seq = seq;
-                best = s;
-            }
-        }
-        if (best < 0) {
-            if (__atomic_load_n(&D->stop, __ATOMIC_ACQUIRE)) {
+        const uint64_t o = P::opened(D);
+        if (o == seen) {
+            if (__atomic_load_n(&D->stop, __ATOMIC_RELAXED)) {
                 dev_stop_seen.fetch_add(1);
                 break;
             }
@@ -123,25 +174,55 @@ static void worker(unsigned seed)
             std::this_thread::yield();
             continue;
         }
+        HostEnv::dev_fence_acquire();
+        int best = -1;
+        uint64_t best_seq = ~0ull;
+        for (int s = 0; s < kSlots; ++s) {
+            uint64_t seq;
+            int64_t left;
+            if (P::open(D, s, &seq, &left) && seq < best_seq) {
+                best_seq = seq;
+                best = s;
+            }
+        }
+        if (best < 0) {
+            seen = o;
+            ++idle;
+            continue;
+        }
+        seen = ~0ull;
         // a worker may stall between seeing a slot open and claiming (the
         // slot can finish and be recycled meanwhile: the claim must notice)
         if (rng() % 4 == 0) std::this_thread::sleep_for(std::chrono::microseconds(rng() % 80));
-        int32_t first = 0;
-        Req rec;
-        const int cnt = P::claim(D, best, kClaim, &first, &rec);
+        Claim c;
+        const int cnt = P::claim(D, best, kClaim, &c);
         if (cnt == 0) {
             ++idle;
             continue;
         }
-        const uint64_t seq = req_seq(rec);
+        // the record as the lanes read it while the claim is outstanding
+        HostEnv::dev_fence_acquire();
+        Req rec;
+        read_record(&rec, &D->slots[best], rng);
+        const uint64_t seq = c.seq;
+        const uint32_t* rw = reinterpret_cast<const uint32_t*>(&rec);
+        bool whole = seq >= 1 && seq <= (uint64_t)kRequests && c.gen == (uint32_t)seq && rec.gen == c.gen &&
+                     req_seq(rec) == seq && rec.n_tiles == c.n_tiles && c.first + cnt <= c.n_tiles;
+        for (int k = 0; whole && k < kReqWords; ++k) whole = !is_fill_word(k) || rw[k] == fill_word((int)seq - 1, k);
+        if (!whole || c.first + cnt > (int)rendered[seq - 1].size()) {
+            if (torn.fetch_add(1) == 0)
+                fprintf(stderr, "claim of %d tiles with a torn or changed record (seq %llu, gen %u, first %d)\n", cnt,
+                        (unsigned long long)seq, c.gen, c.first);
+            continue;
+        }
         for (int j = 0; j < cnt; ++j) {
-            const int tile = first + j;
+            const int tile = c.first + j;
             rendered[seq - 1][tile].fetch_add(1, std::memory_order_relaxed);
             pixels[seq - 1][tile] = seq * 1000003ull + tile;  // plain write, published by the protocol
             if (rng() % 7 == 0) std::this_thread::yield();
-            __atomic_thread_fence(__ATOMIC_RELEASE);
-            P::tile_done(D, H, rec);
         }
+        __atomic_thread_fence(__ATOMIC_RELEASE);
+        P::tiles_done(D, H, best, c);
         last = Clock::now();
         idle = 0;
     }
@@ -177,7 +258,17 @@ int main()
         return running && running->left.load() > 0;
     };
     const auto t_end = Clock::now() + std::chrono::seconds(60);
+    auto t_progress = Clock::now();
+    int completed_before = 0;
     while (completed < kRequests && Clock::now() < t_end) {
+        // a request left waiting with nothing else happening: an opening that no worker saw
+        if (completed != completed_before) {
+            completed_before = completed;
+            t_progress = Clock::now();
+        } else if (submitted > completed && Clock::now() - t_progress > std::chrono::seconds(3)) {
+            fprintf(stderr, "no request completed for 3 s with %d in flight\n", submitted - completed);
+            return 1;
+        }
         // submit while slots are free (bursts, then pauses so that launches idle out)
         int inflight = 0;
         for (int s = 0; s < kMaxInflight; ++s) inflight += slot_req[s] >= 0;
@@ -191,6 +282,9 @@ int main()
             q.seq_lo = (uint32_t)(r + 1);
             q.gen = (uint32_t)(r + 1);
             q.n_tiles = tiles[r];
+            uint32_t* qw = reinterpret_cast<uint32_t*>(&q);
+            for (int k = 0; k < kReqWords; ++k)
+                if (is_fill_word(k)) qw[k] = fill_word(r, k);
             uint32_t* dst = reinterpret_cast<uint32_t*>(&H->ring[written % kReqRing]);
             const uint32_t* src = reinterpret_cast<const uint32_t*>(&q);
             for (int k = 0; k < kReqWords; ++k) __atomic_store_n(dst + k, src[k], __ATOMIC_RELAXED);
@@ -239,6 +333,10 @@ int main()
         delete running;
     }
     const double stop_ms = std::chrono::duration<double, std::milli>(Clock::now() - t_stop).count();
+    if (torn.load()) {
+        fprintf(stderr, "%d claims read a torn record\n", torn.load());
+        return 1;
+    }
     for (int r = 0; r < kRequests; ++r)
         if (done_count[r] != 1) {
             fprintf(stderr, "request %d completed %d times\n", r, done_count[r]);
