@@ -164,7 +164,8 @@ def test_full_frame_forward_backward(name, dtype):
     print(f"gradient error ratios, recomputing backward (inf-norm, per element): "
           f"{check_gradients(grads, ref_g)}", flush=True)
     # the training step with a walk log
-    log = rf.WalkLog(R, 256, od.device)
+    cap = 512  # reflected paths run longer than refracted ones
+    log = rf.WalkLog(R, cap, od.device)
     rgb_l, tf_l, _ = rf.render_forward(p, od, dd, td, sd, log=log)
     assert torch.equal(rgb_l, rgb_d) and torch.equal(tf_l, tf_d)
     grads = rf.render_backward(p, od, dd, td, sd, rgb_l, tf_l, _dv(gm), log=log)
@@ -232,11 +233,12 @@ def test_shell_3m_eight_cameras_sampled():
     print(f"gradient error ratios (inf-norm, per element): {check_gradients(grads, ref_g)}", flush=True)
 
 
-def test_bent_full_frame_glass_sphere():
-    """The clustered_1m frame with the benchmark's glass sphere (index 1.5,
-    radius 0.3 at the centre), against the oracle's exact legs: every ray's
-    colour, transmittance, visited cells and crossings (from the walk log), and
-    the full-frame gradients of the logged backward."""
+@pytest.mark.parametrize("kind", ["glass", "mirror"])
+def test_bent_full_frame_sphere(kind):
+    """The clustered_1m frame with the benchmark's sphere (radius 0.3 at the
+    centre; glass of index 1.5, or a mirror), against the oracle's exact legs:
+    every ray's colour, transmittance, visited cells and crossings (from the
+    walk log), and the full-frame gradients of the logged backward."""
     import torch
 
     import paper_2502_01157_amd as rf
@@ -249,12 +251,13 @@ def test_bent_full_frame_glass_sphere():
     bound = synth.CONFIGS["clustered_1m"]["bound"]
     # the sphere in FP32, as the library takes it; exact legs
     radius = float(np.float32(0.3))
-    osf = oracle.Surface("glass", (0.0, 0.0, 0.0), radius, bound, ior=1.5, max_bounces=8)
+    osf = oracle.Surface(kind, (0.0, 0.0, 0.0), radius, bound, ior=1.5, max_bounces=8)
     osc = oracle.OracleScene.from_scene(scene, surface=osf)
     p = rf.PackedScene(*map(_dv, (scene.sites, scene.off, scene.idx, scene.density, scene.sh)), 3, "f32")
     od, dd, td, sd = map(_dv, (o, d, t, s))
-    sf = rf.Surface("glass", (0.0, 0.0, 0.0), radius, bound, ior=1.5, max_bounces=8)
-    log = rf.WalkLog(R, 256, od.device)
+    sf = rf.Surface(kind, (0.0, 0.0, 0.0), radius, bound, ior=1.5, max_bounces=8)
+    cap = 512  # reflected paths run longer than refracted ones
+    log = rf.WalkLog(R, cap, od.device)
     rgb, tf, steps = rf.render_forward(p, od, dd, td, sd, log=log, surface=sf)
     torch.cuda.synchronize()
     tail = log.tail.cpu().numpy()
@@ -265,25 +268,25 @@ def test_bent_full_frame_glass_sphere():
     def gpu_cells(rq):
         c = (code[:, rq].T & 0x1FFFFFFF).astype(np.int32)
         n = tail[rq, 2]
-        c = np.where(np.arange(256)[None, :] < n[:, None], c, -1)
+        c = np.where(np.arange(cap)[None, :] < n[:, None], c, -1)
         return c, n
 
     t1 = time.time()
     full = oracle.trace(osc, o, d, t, s, eps=1e-4, max_len=1)
     surf_ok = full["surf_margin"] > KAPPA_SURF
-    print(f"\nglass: oracle frame in {time.time() - t1:.1f}s; surface decisions clear for {surf_ok.mean():.5f}",
+    print(f"\n{kind}: oracle frame in {time.time() - t1:.1f}s; surface decisions clear for {surf_ok.mean():.5f}",
           flush=True)
     # rays whose surface decisions are near ties are not resolved by the alternatives
-    sel = np.nonzero(surf_ok & (tail[:, 2] <= 256))[0]
+    sel = np.nonzero(surf_ok & (tail[:, 2] <= cap))[0]
     assert len(sel) >= 0.995 * R
     ref, dec = frame_check(rf, p, osc, (o, d, t, s), sel, rgb.cpu().numpy(), tf.cpu().numpy(),
-                           steps.cpu().numpy(), max_len=256, gpu_cells=gpu_cells, label="glass")
+                           steps.cpu().numpy(), max_len=cap, gpu_cells=gpu_cells, label=kind)
     keep = np.zeros(R, dtype=bool)
     keep[sel] = gradient_decidable(ref, 1e-4)
     gm = np.where(keep[:, None], g, 0.0).astype(np.float32)
     t2 = time.time()
     ref_g = oracle.backward(osc, o, d, t, s, gm, eps=1e-4)
-    print(f"oracle bent backward in {time.time() - t2:.1f}s; gradients on {keep.mean():.4%} of the rays", flush=True)
+    print(f"oracle {kind} backward in {time.time() - t2:.1f}s; gradients on {keep.mean():.4%} of the rays", flush=True)
     grads = rf.render_backward(p, od, dd, td, sd, rgb, tf, _dv(gm), log=log, surface=sf)
     torch.cuda.synchronize()
     print(f"bent gradient error ratios: {check_gradients(grads, ref_g)}", flush=True)
@@ -312,7 +315,8 @@ def test_full_frame_quantiles():
     print(f"\noracle quantiles of {R} rays in {time.time() - t1:.1f}s", flush=True)
     p = rf.PackedScene(*map(_dv, (scene.sites, scene.off, scene.idx, scene.density, scene.sh)), 3, "f32")
     od, dd, td, sd = map(_dv, (o, d, t, s))
-    log = rf.WalkLog(R, 256, od.device)
+    cap = 512  # reflected paths run longer than refracted ones
+    log = rf.WalkLog(R, cap, od.device)
     rgb, tf, _ = rf.render_forward(p, od, dd, td, sd, log=log)
     q, loss = rf.quantile_forward(p, od, dd, td, sd, tf, log, _dv(u))
     torch.cuda.synchronize()
