@@ -80,6 +80,15 @@ def measured_traffic(workload: str, dtype: str, label: str):
     return int(round((float(m.group(1)) + float(m.group(2))) * 1e6))
 
 
+def site_count(n: int) -> str:
+    """1M, 3M, 200k or the count itself."""
+    if n % 1_000_000 == 0:
+        return f"{n // 1_000_000}M"
+    if n % 1_000 == 0:
+        return f"{n // 1_000}k"
+    return f"{n:,}"
+
+
 def visit_bytes(mean_deg: float, B: int, dt: str, kind: str = "forward") -> float:
     """Bytes the method touches per visited cell, with no reuse: its row offsets
     (4), neighbour ids (4 per face) and positions (12 per face), and its SH and
@@ -297,7 +306,9 @@ def main() -> int:
         log(f"bf16 colour error against the fp32-attribute frame: max {bf16_err['max_rel']:.2e}, "
             f"p99 {bf16_err['p99_rel']:.2e}, mean {bf16_err['mean_rel']:.2e} of the largest colour")
 
-    main_dt = "f32" if args.only is None else args.only
+    # the attribute precision each workload is specified with (the 3M-site
+    # multi-camera workload stores its attributes in BF16)
+    main_dt = args.only or {"shell_3m": "bf16"}.get(args.config, "f32")
     dts = sorted({k[0] for k in results}, key=lambda x: x != "f32")
     ms, kern, lat = results[(main_dt, "fwd_bwd")]
     value = R / (ms * 1e-3) / 1e6
@@ -335,8 +346,9 @@ def main() -> int:
                 f"raygen+pack+forward+backward (the backward recomputes each walk from the saved colour "
                 f"and transmittance)")
     out = {
-        "metric": "Mrays/s fwd+bwd at 1M sites (FP32 attributes, recomputing backward); fwd, walk-log and BF16 "
-                  "rates and p50/p99 step latency in added fields",
+        "metric": f"Mrays/s fwd+bwd at {site_count(scene.n_sites)} sites ({main_dt.upper().replace('F32', 'FP32')} "
+                  f"attributes, recomputing backward); fwd, walk-log and "
+                  f"{'FP32' if main_dt == 'bf16' else 'BF16'} rates and p50/p99 step latency in added fields",
         "value": round(value, 3),
         "unit": "Mrays/s",
         "n_gpus": 1,
