@@ -553,9 +553,12 @@ rf_status rf_packed_attributes(const rf_packed_scene *scene, float *density, flo
  * the server is created) before the request's first tiles run.
  * rf_server_poll lists finished requests not yet collected; rf_server_result
  * copies one into `rgba` (host memory, >= W*H*16 bytes; NULL discards it) and
- * frees its slot and pool range. rf_server_destroy finishes admitted requests,
- * stops the scheduler and frees the server. All calls may come from any host
- * thread; they serialise on the server's lock.
+ * frees its slot and pool range; the copy runs outside the server's lock, so
+ * the server keeps scheduling while a result is copied (a second call for the
+ * same request meanwhile fails with RF_ERR_BUSY). rf_server_destroy finishes
+ * admitted requests, stops the scheduler and frees the server. Every call but
+ * rf_server_destroy may come from any host thread at any time (they serialise
+ * on the server's lock); rf_server_destroy must not overlap another call.
  * ---------------------------------------------------------------------- */
 typedef struct rf_server rf_server;
 

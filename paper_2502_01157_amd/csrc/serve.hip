@@ -452,7 +452,7 @@ struct rf_server {
     uint64_t idle_ticks = 0, hard_ticks = 0;
     std::chrono::steady_clock::time_point stop_deadline;  // destroy stops waiting for admitted requests then
 
-    enum State { FREE = 0, QUEUED, DONE };
+    enum State { FREE = 0, QUEUED, DONE, COPYING };  // COPYING: its result is being copied out
     struct Slot {
         State state = FREE;
         bool uploaded = false;
@@ -965,27 +965,39 @@ rf_status rf_server_poll(rf_server* s, uint64_t* done_ids, int32_t cap, int32_t*
     return RF_OK;
 }
 
+// The copy runs outside the server's lock (a 1080p result is 33 MB): the
+// slot is marked COPYING, which keeps it and its pool range out of every
+// other call's reach, and freed afterwards, so the scheduler keeps launching
+// and observing completions while a result is copied.
 rf_status rf_server_result(rf_server* s, uint64_t req_id, float* rgba, size_t bytes)
 {
     if (!s) return sfail(RF_ERR_INVALID_ARG, "NULL server");
-    std::lock_guard<std::mutex> lock(s->mu);
-    for (int k = 0; k < s->max_inflight; ++k) {
-        rf_server::Slot& sl = s->slots[k];
-        if (sl.state == rf_server::FREE || sl.seq != req_id) continue;
-        if (sl.state != rf_server::DONE)
-            return sfail(RF_ERR_BUSY, "request %llu not finished", (unsigned long long)req_id);
-        const size_t need = (size_t)sl.floats * 4;
-        if (rgba) {
-            if (bytes < need) return sfail(RF_ERR_INVALID_ARG, "result buffer of %zu bytes < %zu", bytes, need);
-            memcpy(rgba, s->pool + sl.offset, need);
+    rf_server::Slot* sl = nullptr;
+    size_t need = 0;
+    {
+        std::lock_guard<std::mutex> lock(s->mu);
+        for (int k = 0; k < s->max_inflight && !sl; ++k) {
+            rf_server::Slot& c = s->slots[k];
+            if (c.state == rf_server::FREE || c.seq != req_id) continue;
+            if (c.state == rf_server::COPYING)
+                return sfail(RF_ERR_BUSY, "request %llu is being collected", (unsigned long long)req_id);
+            if (c.state != rf_server::DONE)
+                return sfail(RF_ERR_BUSY, "request %llu not finished", (unsigned long long)req_id);
+            need = (size_t)c.floats * 4;
+            if (rgba && bytes < need)
+                return sfail(RF_ERR_INVALID_ARG, "result buffer of %zu bytes < %zu", bytes, need);
+            c.state = rf_server::COPYING;
+            sl = &c;
         }
-        pool_free(s, sl.offset, sl.floats);
-        s->stats.pool_used_bytes -= (int64_t)need;
-        s->stats.inflight--;
-        sl.state = rf_server::FREE;
-        return RF_OK;
+        if (!sl) return sfail(RF_ERR_INVALID_ARG, "unknown request %llu", (unsigned long long)req_id);
     }
-    return sfail(RF_ERR_INVALID_ARG, "unknown request %llu", (unsigned long long)req_id);
+    if (rgba) memcpy(rgba, s->pool + sl->offset, need);
+    std::lock_guard<std::mutex> lock(s->mu);
+    pool_free(s, sl->offset, sl->floats);
+    s->stats.pool_used_bytes -= (int64_t)need;
+    s->stats.inflight--;
+    sl->state = rf_server::FREE;
+    return RF_OK;
 }
 
 rf_status rf_server_stats_get(rf_server* s, rf_server_stats* out)
