@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_pack_faces(PackArgs a)
         }
         const int bq = __shfl(beg, q), dq = __shfl(deg, q);
         int owner = (k >= bq && k < bq + dq) ? q : -1;
-        if (__ballot(k < hi_e && owner < 0)) {
+        if (ballot(k < hi_e && owner < 0)) {
             // (wavefront-uniform, so every lane takes part in the shuffles)
             int scan = -1;
             for (int r = 0; r < kWave; ++r) {

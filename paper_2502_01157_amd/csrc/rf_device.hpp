@@ -66,6 +66,11 @@ __device__ inline uint32_t f32_to_bf16_rne(float f)
     return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
 }
 
+// Mask of the active lanes whose predicate holds. The builtin takes the
+// predicate as the compare's lane mask; HIP's __ballot(int) widens it to an
+// integer and compares that again (two more VALU instructions per ballot).
+__device__ inline uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
 __device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 

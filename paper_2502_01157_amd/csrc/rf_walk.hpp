@@ -211,7 +211,7 @@ __device__ inline void stage_cells(const SceneView& s, bool want, uint2 ref, lds
     using R = Rec<DEG, BF16>;
     const int lane = __lane_id();
     const uint32_t lane16 = 16u * (uint32_t)lane;
-    uint64_t pend = __ballot(want);
+    uint64_t pend = ballot(want);
     int off = 0, nrec = 0;
     face_slot = -1;
     rec_slot = -1;
@@ -221,7 +221,11 @@ __device__ inline void stage_cells(const SceneView& s, bool want, uint2 ref, lds
         const uint32_t kx = __builtin_amdgcn_readlane(ref.x, leader);
         const int gbeg = __builtin_amdgcn_readlane(ref.y, leader);
         const int key = (int)(kx & 0xffffffu), gdeg = (int)(kx >> 24);
-        const uint64_t members = __ballot(want && ref.x == kx);
+        // the lanes still pending with this cell (a ballot of the bare
+        // compare, masked in scalar registers); kept per lane as well, as
+        // testing the mask's bit costs five VALU instructions
+        const bool mine = want && ref.x == kx;
+        const uint64_t members = ballot(ref.x == kx) & pend;
         pend &= ~members;
         if (off + gdeg > SL::kFaces || nrec == SL::kRecs) continue;
         for (int k0 = 0; k0 < gdeg; k0 += kWave)
@@ -229,7 +233,7 @@ __device__ inline void stage_cells(const SceneView& s, bool want, uint2 ref, lds
                 copy16_to_lds(s.planes + gbeg + k0, 16u * kWave, lane16, region + (off + k0) * 16);
         if (lane < R::CHUNKS)
             copy16_to_lds(s.rec + (size_t)key * R::BYTES, R::BYTES, lane16, region + SL::kRecOff + nrec * SL::kRecStride);
-        if ((members >> lane) & 1) {
+        if (mine) {
             face_slot = off;
             rec_slot = nrec;
         }
@@ -529,7 +533,7 @@ __device__ inline void walk_forward_staged(const SceneView& s, bool live, float 
     if constexpr (SURF) {
         if (live) leg_start(*sf, ox, oy, oz, dx, dy, dz, tmax, leg);
     }
-    while (__ballot(live)) {
+    while (ballot(live)) {
         if (live) {
             if (!cont && !(T > eps)) {
                 res.status = n;

@@ -251,7 +251,7 @@ __device__ void persistent_dispatcher(const PersistArgs& a, int lane)
         const uint64_t quiet = wall_clock64() - last;
         if (quiet > a.idle_ticks) {
             const bool idle = Proto::slot_idle(a.dev, lane);  // lane = slot (kSlots == kWave)
-            if (__ballot(!idle) == 0) break;                 // everything admitted is done
+            if (ballot(!idle) == 0) break;                 // everything admitted is done
             if (quiet > a.hard_ticks) break;                 // no request for long: the host relaunches
         }
         ++idle_iters;
@@ -292,7 +292,7 @@ __device__ void persistent_worker(const PersistArgs& a, int lane)
         int64_t left = 0;
         const bool op = Proto::open(a.dev, lane, &seq, &left);  // lane = slot
         if (!op) seq = ~0ull;
-        const uint64_t open_lanes = __ballot(op);
+        const uint64_t open_lanes = ballot(op);
         if (open_lanes == 0) {
             seen = o;
             ++idle_units;
@@ -307,7 +307,7 @@ __device__ void persistent_worker(const PersistArgs& a, int lane)
             const uint64_t x = __shfl_xor(m, off);
             m = x < m ? x : m;
         }
-        const int slot = __builtin_ctzll(__ballot(op && seq == m));
+        const int slot = __builtin_ctzll(ballot(op && seq == m));
         // up to kClaimTiles tiles, fewer while the request's tiles left do not
         // give every worker that many: a small request is spread over the chip
         const int64_t slot_left = __shfl(left, slot);

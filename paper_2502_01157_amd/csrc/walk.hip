@@ -217,7 +217,8 @@ struct Emitter {
     // (flushing) the oldest row when the cell has none.
     __device__ void accumulate(int key, float acc)
     {
-        const uint64_t hit = __ballot(lane < E::kSlots && slot_key == key);
+        // (lanes past kSlots hold no key: slot_key stays -1 there, and keys are cells >= 0)
+        const uint64_t hit = ballot(slot_key == key);
         if (hit) {
             // each lane owns its column, so the add needs no result and no wait
             const int slot = __builtin_ctzll(hit);
@@ -241,7 +242,7 @@ struct Emitter {
     __device__ void emit(bool has, const Package& p, const float* Y)
     {
         constexpr int B = E::B;
-        uint64_t pend = __ballot(has);
+        uint64_t pend = ballot(has);
         if (pend == 0) return;
         const int key_cell = has ? p.cell : -1;
         // each member's row: the groups in the order of their lowest lane,
@@ -252,7 +253,7 @@ struct Emitter {
             int first = 0;
             while (rest) {
                 const int key = __builtin_amdgcn_readlane(key_cell, __builtin_ctzll(rest));
-                const uint64_t ma = __ballot(key_cell == key) & rest;
+                const uint64_t ma = ballot(key_cell == key) & rest;
                 rest &= ~ma;
                 if (key_cell == key)
                     pos = first + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32),
@@ -284,7 +285,7 @@ struct Emitter {
         int first = 0;
         while (pend) {
             const int key = __builtin_amdgcn_readlane(key_cell, __builtin_ctzll(pend));
-            const uint64_t ma = __ballot(key_cell == key) & pend;
+            const uint64_t ma = ballot(key_cell == key) & pend;
             pend &= ~ma;
             const int m = __popcll(ma);
             const float acc = column_sum(first, m);
@@ -453,7 +454,7 @@ void k_backward(WalkArgs a)
     bool entry_valid = false;
 
     int status = 0;  // the recomputed walk's status, as the forward reports it in steps
-    while (__ballot(state != 3)) {
+    while (ballot(state != 3)) {
         bool has = false;
         Package out = prev;
         bool stop = false;
@@ -651,7 +652,7 @@ void k_backward(WalkArgs a)
             // a crossing's package is complete when its visit ends (its exit
             // does not move), so it goes out now, with the old leg's basis,
             // and the lane's basis turns with the leg
-            if (__ballot(turned)) {
+            if (ballot(turned)) {
                 em.emit(turned, prev, Y);
                 if (turned) {
                     sh_basis<DEG>(dx, dy, dz, Y);
