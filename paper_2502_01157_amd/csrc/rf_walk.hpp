@@ -252,7 +252,6 @@ __device__ inline void visit_cell_staged(const SceneView& s, uint2 ref, int face
                                          const double* hi = nullptr)
 {
     using SL = StageLayout<DEG, BF16>;
-    using R = Rec<DEG, BF16>;
     const int cell = ref_cell(ref), beg = ref_beg(ref), deg = ref_deg(ref);
     lds_f32x4* lrow = reinterpret_cast<lds_f32x4*>(region) + face_slot;
     if (face_slot >= 0)
