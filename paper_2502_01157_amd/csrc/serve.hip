@@ -149,10 +149,6 @@ struct DevEnv {
         return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __device__ static void dev_fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
-    __device__ static void word_store_relaxed(uint32_t* p, uint32_t v)
-    {
-        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
     __device__ static void dev_store_relaxed(uint64_t* p, uint64_t v)
     {
         __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -166,6 +162,17 @@ struct DevEnv {
     {
         return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     }
+    __device__ static uint64_t dev_fetch_add_acquire(uint64_t* p, uint64_t v)
+    {
+        return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // a release at system scope: a release fence of that scope before the
+    // addition (the word itself is only ever shared by the device)
+    __device__ static uint64_t sys_fetch_add_release(uint64_t* p, uint64_t v)
+    {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __device__ static void sys_store_release(uint64_t* p, uint64_t v)
     {
         __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -176,6 +183,13 @@ struct DevEnv {
     }
 };
 using Proto = sp::Protocol<DevEnv>;
+
+__device__ inline int64_t uniform(int64_t v)
+{
+    const uint64_t u = (uint64_t)v;
+    return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u));
+}
 
 struct PersistArgs {
     SceneView s;
@@ -202,7 +216,8 @@ __device__ void persistent_dispatcher(const PersistArgs& a, int lane)
     while (idle_iters < kIdleIterCap) {
         // polled relaxed (an acquire at system scope would invalidate this
         // XCD's L2 on every poll); acquired once a record is there
-        const int64_t n_req = __hip_atomic_load(&a.host->n_requests, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        // (lane 0's value for the whole wavefront: the control flow below stays uniform)
+        const int64_t n_req = uniform(__hip_atomic_load(&a.host->n_requests, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
         // the host never has more than kSlots records unconsumed; anything else is not a count it wrote
         if (n_req < consumed || n_req - consumed > sp::kReqRing) break;
         if (consumed < n_req) {
@@ -226,19 +241,16 @@ __device__ void persistent_dispatcher(const PersistArgs& a, int lane)
                 start = __shfl(start, 0);
                 if (lane == (int)(offsetof(sp::Req, start) / 4)) w = (uint32_t)start;
             }
-            if (slot >= 0 && slot < sp::kSlots && gen != 0) {
-                // the record under its generation word's sequence lock (every
-                // lane runs the lock's stores and fences; they store one value)
+            const int n_tiles = __shfl((int)w, (int)(offsetof(sp::Req, n_tiles) / 4));
+            if (slot >= 0 && slot < sp::kSlots && gen != 0 && n_tiles > 0) {
+                // the record, one word per lane (no claim reads the slot
+                // before the activation below: its last request completed)
                 uint32_t* dst = reinterpret_cast<uint32_t*>(&a.dev->slots[slot]);
-                constexpr int kGenWord = (int)(offsetof(sp::Req, gen) / 4);
-                Proto::begin_record(a.dev, slot);
-                if (lane < sp::kReqWords && lane != kGenWord)
+                if (lane < sp::kReqWords)
                     __hip_atomic_store(dst + lane, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                Proto::end_record(a.dev, slot, gen);
-                // every lane's words of the record before the slot opens
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                __builtin_amdgcn_wave_barrier();
-                if (lane == 0) Proto::activate(a.dev, slot, gen);
+                // every lane's words ordered before lane 0's release of the slot
+                __syncthreads();
+                if (lane == 0) Proto::activate(a.dev, slot, gen, n_tiles);
             }
             ++consumed;
             if (lane == 0)
@@ -247,7 +259,9 @@ __device__ void persistent_dispatcher(const PersistArgs& a, int lane)
             idle_iters = 0;
             continue;
         }
-        if (__hip_atomic_load(&a.host->shutdown, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+        if (__builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(&a.host->shutdown, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)))
+            break;
         const uint64_t quiet = wall_clock64() - last;
         if (quiet > a.idle_ticks) {
             const bool idle = Proto::slot_idle(a.dev, lane);  // lane = slot (kSlots == kWave)
@@ -267,12 +281,14 @@ __device__ void persistent_worker(const PersistArgs& a, int lane)
     uint32_t idle_units = 0;  // idle polls, in units of ~1 us
     uint32_t naps = 0;        // consecutive polls that found nothing new
     uint64_t seen = ~0ull;    // openings counted before the last scan that found nothing open
+    bool fenced = true;       // the next scan follows an acquire fence
     while (idle_units < kIdleIterCap) {
         // the count's low 32 bits (an idle nap does not span 2^32 openings)
         const uint64_t o = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)Proto::opened(a.dev));
         if (o == seen) {
             // nothing opened since a scan found every slot closed or fully claimed
-            if (__hip_atomic_load(&a.dev->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            if (__builtin_amdgcn_readfirstlane(__hip_atomic_load(&a.dev->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+                break;
             if (wall_clock64() - last > a.hard_ticks) break;
             // short naps first, then ~50 us between polls: a few thousand idle
             // wavefronts polling at once would crowd the memory channel of
@@ -287,18 +303,23 @@ __device__ void persistent_worker(const PersistArgs& a, int lane)
             ++naps;
             continue;
         }
-        DevEnv::dev_fence_acquire();
+        // a working wavefront scans without a fence (claim() validates what
+        // the scan picks); a scan that finds nothing open is trusted only
+        // after one that followed a fence
+        if (fenced) DevEnv::dev_fence_acquire();
         uint64_t seq = ~0ull;
         int64_t left = 0;
         const bool op = Proto::open(a.dev, lane, &seq, &left);  // lane = slot
         if (!op) seq = ~0ull;
         const uint64_t open_lanes = ballot(op);
         if (open_lanes == 0) {
-            seen = o;
+            if (fenced) seen = o;
+            fenced = true;
             ++idle_units;
             continue;
         }
         seen = ~0ull;
+        fenced = false;
         naps = 0;
         // the oldest open request
         uint64_t m = seq;
@@ -323,10 +344,9 @@ __device__ void persistent_worker(const PersistArgs& a, int lane)
         }
         c.first = __builtin_amdgcn_readfirstlane(c.first);
         c.count = cnt;
-        c.n_tiles = __builtin_amdgcn_readfirstlane(c.n_tiles);
-        c.gen = __builtin_amdgcn_readfirstlane(c.gen);
-        // the claimed request's record, which stays in the slot while the claim is outstanding
-        DevEnv::dev_fence_acquire();
+        // the claimed request's record, which stays in the slot while the
+        // claim is outstanding: lane 0's loads (ordered by its claim's
+        // acquire), broadcast to the wavefront
         const uint32_t* rw = reinterpret_cast<const uint32_t*>(&a.dev->slots[slot]);
         auto word = [&](size_t off) { return __builtin_amdgcn_readfirstlane(DevEnv::word_load(rw + off / 4)); };
         float rot[9], pos[3];
@@ -354,9 +374,8 @@ __device__ void persistent_worker(const PersistArgs& a, int lane)
                 *out = make_float4(res.C[0], res.C[1], res.C[2], res.T);
             }
         }
-        // the claim's pixels visible to the host before its tiles count as done
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-        __builtin_amdgcn_wave_barrier();
+        // every lane's pixels ordered before lane 0's release of the claim
+        __syncthreads();
         if (lane == 0) (void)Proto::tiles_done(a.dev, a.host, slot, c);
         last = wall_clock64();
         idle_units = 0;

@@ -5,33 +5,36 @@
 // coherent host memory and publishes their count (n_requests) with a release
 // store. One dispatcher wavefront reads each new record (acquire on the
 // count), copies it into the request's slot in device memory, resets the
-// slot's done counter, opens the slot for claims with a release store of its
-// claim word and counts the opening in `opened`. Dispatcher -> workers: a
-// slot's claim word is (generation << 32 | tiles claimed); a request's
-// generation is nonzero and unique among the requests a slot has held.
-// Workers claim tiles with fetch-and-add on the claim word and keep a claim
-// only if it hit the generation the slot's record still holds and lies below
-// its tile count: a claim that lands on a finished or recycled generation
-// claims nothing. A worker renders the tiles of its claim, releases their
-// pixels to the host, and adds their number to the slot's done counter
-// (generation << 32 | tiles done); the claim that completes the request
-// stores the request's sequence number into the slot's completion word in
-// host memory (release), which the host polls. A slot is recycled only after
-// its request completed, so the record of a claim that counted stays in its
-// slot until that claim is done.
+// slot's done counter, opens the slot with a release store of its claim word
+// and counts the opening in `opened`.
 //
-// A claim that lands after completion can still read the slot while the
-// dispatcher writes the next record into it, so a record is written as a
-// sequence lock on its generation word: the dispatcher clears the word,
-// writes the other words, then stores the new generation; a claimer reads
-// the record's tile count after its claim, fences, and reads the generation,
-// and keeps the claim only if the generation equals the claim word's
-// (generations of a slot never repeat, so a read that saw any word of a newer
-// record fails the check).
+// Dispatcher -> workers: a slot's claim word is (tile count << 32 | tiles
+// claimed); a tile count of 0 means the slot has never been opened. Workers
+// claim tiles with an acquiring fetch-and-add on the claim word: the value it
+// returns tells, in one atomic step, whether the claim counts (tiles claimed
+// before it below the tile count of the request the word belongs to). A claim
+// that counts holds the request open, since the request completes only once
+// every counted claim is done, and a slot is rewritten only after its request
+// completed; so the slot keeps the claim's record, which the acquire made
+// visible, for as long as the claim is outstanding. A claim that lands after
+// the slot reopened claims the new request's tiles, under the same rule. A
+// claim that does not count (the request fully claimed or finished) reads
+// nothing from the slot. A worker lands at most one such claim per opening of
+// a slot (its next read of the word sees its own addition), so the claimed
+// count stays far below 2^32.
+//
+// Workers -> host: a worker renders its claim's tiles into host memory and
+// adds their number to the slot's done counter (generation << 32 | tiles
+// done) with a release at system scope. The claim that completes the request
+// acquires every other claim's release (all additions after the reset are
+// read-modify-writes, so each one's release sequence reaches the last) and
+// stores the request's sequence number into the slot's completion word in
+// host memory (release), which the host polls (acquire).
 //
 // Idle workers poll `opened` alone, and scan the slots only when it has
 // changed since their last scan that found nothing open: a slot opens only
-// by an activation, and tiles once claimed stay claimed.
+// by an activation, and tiles once claimed stay claimed. The scan is a hint:
+// claim() validates what it takes.
 //
 // Every shared word is accessed with atomic operations of explicit order and
 // scope (records word by word, relaxed, ordered by the claim word's release
@@ -58,7 +61,7 @@ struct Req {
     int32_t out_offset_lo, out_offset_hi;  // floats from the pool base
     uint32_t seq_lo, seq_hi;               // 1-based request sequence number
     uint32_t gen;                          // nonzero generation of the slot
-    int32_t n_tiles;
+    int32_t n_tiles;                       // 1 .. 2^31 - 1
 };
 constexpr int kReqWords = (int)(sizeof(Req) / 4);
 static_assert(sizeof(Req) % 4 == 0 && kReqWords <= 64, "a record is read one word per lane");
@@ -96,100 +99,82 @@ inline __host__ __device__ uint64_t req_seq(const Req& r) { return ((uint64_t)r.
 
 // Env supplies the atomics: dev_* at the scope shared by the workers (the
 // device), sys_* at the scope shared with the host, and relaxed word loads
-// and stores at device scope.
+// at device scope.
 template <class Env>
 struct Protocol {
-    // Dispatcher, before writing the words of a new record into slot s
-    // (the generation word excluded): mark the slot's record as being written.
-    static __host__ __device__ void begin_record(DevCtl* d, int s)
-    {
-        Env::word_store_relaxed(&d->slots[s].gen, 0u);
-        Env::dev_fence_release();
-    }
-
-    // Dispatcher, after writing them: publish the record's generation.
-    static __host__ __device__ void end_record(DevCtl* d, int s, uint32_t gen)
-    {
-        Env::dev_fence_release();
-        Env::word_store_relaxed(&d->slots[s].gen, gen);
-    }
-
-    // Dispatcher, after end_record: reset the done counter, open the slot to
-    // claims of generation gen, and count the opening.
-    static __host__ __device__ void activate(DevCtl* d, int slot, uint32_t gen)
+    // Dispatcher, once the words of a new record are in slot s (relaxed
+    // stores, ordered before this call): reset the done counter, open the
+    // slot to claims of the record's n_tiles tiles, and count the opening.
+    static __host__ __device__ void activate(DevCtl* d, int slot, uint32_t gen, int32_t n_tiles)
     {
         Env::dev_store_relaxed(&d->done[slot], (uint64_t)gen << 32);
         Env::dev_fence_release();
-        Env::dev_store_release(&d->claim[slot], (uint64_t)gen << 32);
+        Env::dev_store_release(&d->claim[slot], (uint64_t)(uint32_t)n_tiles << 32);
         (void)Env::dev_fetch_add_acq_rel(&d->opened, (uint64_t)1);
     }
 
-    // Worker: activations so far. Before a scan of the slots the worker reads
-    // this, then fences (acquire): the scan sees every opening counted.
+    // Worker: activations so far. Before a scan of the slots that is to be
+    // trusted when it finds nothing open, the worker reads this, then fences
+    // (acquire): the scan sees every opening counted.
     static __host__ __device__ uint64_t opened(DevCtl* d) { return Env::dev_load_relaxed(&d->opened); }
 
     // Worker: is slot s open with tiles left? (its sequence number in *seq,
     // the tiles not yet claimed in *left) A hint only, read without
-    // ordering: claim() validates what it takes.
+    // ordering (the sequence number may even be another request's).
     static __host__ __device__ bool open(DevCtl* d, int s, uint64_t* seq, int64_t* left)
     {
         const uint64_t c = Env::dev_load_relaxed(&d->claim[s]);
-        const uint32_t g = (uint32_t)(c >> 32);
-        if (g == 0) return false;
+        const int64_t n = (int64_t)(c >> 32), claimed = (int64_t)(c & kCountMask);
+        if (claimed >= n) return false;
         const Req* r = &d->slots[s];
-        if (Env::word_load(&r->gen) != g) return false;
-        const int32_t n = (int32_t)Env::word_load((const uint32_t*)&r->n_tiles);
-        if ((int64_t)(c & kCountMask) >= (int64_t)n) return false;
         *seq = ((uint64_t)Env::word_load(&r->seq_hi) << 32) | Env::word_load(&r->seq_lo);
-        *left = (int64_t)n - (int64_t)(c & kCountMask);
+        *left = n - claimed;
         return true;
     }
 
     // Worker: claims up to k tiles of slot s. Returns the number of tiles
-    // claimed (0: none), described in *out. While the claim is outstanding the
-    // slot keeps the claimed request's record: every lane may then read it
-    // (after an acquire fence of its own).
+    // claimed (0: none), described in *out. While a claim that counted is
+    // outstanding the slot keeps its request's record, visible to the
+    // claiming thread.
     static __host__ __device__ int claim(DevCtl* d, int s, int k, Claim* out)
     {
-        const uint64_t old = Env::dev_fetch_add_acq_rel(&d->claim[s], (uint64_t)k);
-        const uint32_t g = (uint32_t)(old >> 32);
-        if (g == 0) return 0;
+        const uint64_t old = Env::dev_fetch_add_acquire(&d->claim[s], (uint64_t)k);
+        const int64_t n = (int64_t)(old >> 32), c = (int64_t)(old & kCountMask);
+        if (c >= n) return 0;  // nothing left, or never opened
         const Req* r = &d->slots[s];
-        const int64_t n = (int32_t)Env::word_load((const uint32_t*)&r->n_tiles);
-        const uint64_t seq = ((uint64_t)Env::word_load(&r->seq_hi) << 32) | Env::word_load(&r->seq_lo);
-        Env::dev_fence_acquire();
-        // the generation after the reads: any word of a newer record read above shows here
-        if (Env::word_load(&r->gen) != g) return 0;
-        const int64_t c = (int64_t)(old & kCountMask);
-        if (c >= n) return 0;  // nothing left
         const int64_t left = n - c;
         out->first = (int32_t)c;
         out->count = (int32_t)(left < k ? left : k);
         out->n_tiles = (int32_t)n;
-        out->gen = g;
-        out->seq = seq;
+        out->gen = Env::word_load(&r->gen);
+        out->seq = ((uint64_t)Env::word_load(&r->seq_hi) << 32) | Env::word_load(&r->seq_lo);
         return out->count;
     }
 
-    // Worker: the tiles of claim `c` in slot s done (their pixels already
-    // released to the host). Returns true if it completed the request.
+    // Worker: the tiles of claim `c` in slot s done. Every pixel of the claim
+    // must be ordered before this call (they are released here at system
+    // scope). Returns true if it completed the request.
     static __host__ __device__ bool tiles_done(DevCtl* d, HostCtl* h, int s, const Claim& c)
     {
-        const uint64_t old = Env::dev_fetch_add_acq_rel(&d->done[s], (uint64_t)c.count);
+        const uint64_t old = Env::sys_fetch_add_release(&d->done[s], (uint64_t)c.count);
         if ((uint32_t)(old >> 32) != c.gen) return false;  // cannot happen: the slot is not recycled before
         if ((int64_t)(old & kCountMask) + c.count != c.n_tiles) return false;
+        // the last claim: acquire the other claims' releases (this reads our
+        // own addition, the end of each of their release sequences)
+        (void)Env::dev_load_acquire(&d->done[s]);
         Env::sys_store_release(&h->done_seq[s], c.seq);
         return true;
     }
 
-    // Dispatcher: has every request activated in a slot completed? (s: one slot)
+    // Dispatcher: has the request last activated in slot s completed? (only
+    // the dispatcher activates, so the done counter it reads is that request's)
     static __host__ __device__ bool slot_idle(DevCtl* d, int s)
     {
         const uint64_t c = Env::dev_load_acquire(&d->claim[s]);
-        if ((uint32_t)(c >> 32) == 0) return true;
+        const int64_t n = (int64_t)(c >> 32);
+        if (n == 0) return true;
         const uint64_t dn = Env::dev_load_acquire(&d->done[s]);
-        const int32_t n = (int32_t)Env::word_load((const uint32_t*)&d->slots[s].n_tiles);
-        return (uint32_t)(dn >> 32) == (uint32_t)(c >> 32) && (int64_t)(dn & kCountMask) >= (int64_t)n;
+        return (int64_t)(dn & kCountMask) >= n;
     }
 };
 

@@ -45,7 +45,6 @@ struct HostEnv {
     static uint64_t dev_load_acquire(const uint64_t* p) { jitter(); return __atomic_load_n(p, __ATOMIC_ACQUIRE); }
     static uint64_t dev_load_relaxed(const uint64_t* p) { jitter(); return __atomic_load_n(p, __ATOMIC_RELAXED); }
     static void dev_fence_acquire() { __atomic_thread_fence(__ATOMIC_ACQUIRE); }
-    static void word_store_relaxed(uint32_t* p, uint32_t v) { jitter(); __atomic_store_n(p, v, __ATOMIC_RELAXED); }
     static void dev_store_relaxed(uint64_t* p, uint64_t v) { jitter(); __atomic_store_n(p, v, __ATOMIC_RELAXED); }
     static void dev_store_release(uint64_t* p, uint64_t v) { jitter(); __atomic_store_n(p, v, __ATOMIC_RELEASE); }
     static void dev_fence_release() { __atomic_thread_fence(__ATOMIC_RELEASE); }
@@ -53,6 +52,16 @@ struct HostEnv {
     {
         jitter();
         return __atomic_fetch_add(p, v, __ATOMIC_ACQ_REL);
+    }
+    static uint64_t dev_fetch_add_acquire(uint64_t* p, uint64_t v)
+    {
+        jitter();
+        return __atomic_fetch_add(p, v, __ATOMIC_ACQUIRE);
+    }
+    static uint64_t sys_fetch_add_release(uint64_t* p, uint64_t v)
+    {
+        jitter();
+        return __atomic_fetch_add(p, v, __ATOMIC_RELEASE);
     }
     static void sys_store_release(uint64_t* p, uint64_t v) { jitter(); __atomic_store_n(p, v, __ATOMIC_RELEASE); }
     static uint32_t word_load(const uint32_t* p) { jitter(); return __atomic_load_n(p, __ATOMIC_RELAXED); }
@@ -116,25 +125,21 @@ static void dispatcher(int64_t consumed)
             const uint32_t* src = reinterpret_cast<const uint32_t*>(&H->ring[consumed % kReqRing]);
             uint32_t* w = reinterpret_cast<uint32_t*>(&rec);
             for (int k = 0; k < kReqWords; ++k) w[k] = __atomic_load_n(src + k, __ATOMIC_RELAXED);
-            if (rec.slot >= 0 && rec.slot < kSlots && rec.gen != 0) {
+            if (rec.slot >= 0 && rec.slot < kSlots && rec.gen != 0 && rec.n_tiles > 0) {
                 uint32_t* dst = reinterpret_cast<uint32_t*>(&D->slots[rec.slot]);
-                const int gen_word = (int)(offsetof(Req, gen) / 4);
-                P::begin_record(D, rec.slot);
                 // the words in any order (a wavefront's store lands in no fixed
-                // order), with pauses, while late claims may read the slot
+                // order), with pauses, while late claims land on the slot
                 int order[kReqWords];
                 for (int k = 0; k < kReqWords; ++k) order[k] = k;
                 std::shuffle(order, order + kReqWords, rng);
                 for (int j = 0; j < kReqWords; ++j) {
                     const int k = order[j];
-                    if (k == gen_word) continue;
                     __atomic_store_n(dst + k, w[k], __ATOMIC_RELAXED);
                     if (rng() % 16 == 0) std::this_thread::sleep_for(std::chrono::microseconds(rng() % 20));
                 }
-                P::end_record(D, rec.slot, rec.gen);
                 // a slow dispatcher: the new record sits in the slot before the slot reopens
                 if (rng() % 3 == 0) std::this_thread::sleep_for(std::chrono::microseconds(rng() % 60));
-                P::activate(D, rec.slot, rec.gen);
+                P::activate(D, rec.slot, rec.gen, rec.n_tiles);
             }
             ++consumed;
             __atomic_store_n(&H->consumed, consumed, __ATOMIC_RELEASE);
@@ -162,6 +167,7 @@ static void worker(unsigned seed)
     auto last = Clock::now();
     uint32_t idle = 0;
     uint64_t seen = ~0ull;  // openings counted before the last scan that found nothing open
+    bool fenced = true;     // the next scan follows an acquire fence
     while (idle < kIdleCap) {
         const uint64_t o = P::opened(D);
         if (o == seen) {
@@ -174,7 +180,7 @@ static void worker(unsigned seed)
             std::this_thread::yield();
             continue;
         }
-        HostEnv::dev_fence_acquire();
+        if (fenced) HostEnv::dev_fence_acquire();
         int best = -1;
         uint64_t best_seq = ~0ull;
         for (int s = 0; s < kSlots; ++s) {
@@ -186,11 +192,13 @@ static void worker(unsigned seed)
             }
         }
         if (best < 0) {
-            seen = o;
+            if (fenced) seen = o;  // a scan without a fence is not trusted to find nothing
+            fenced = true;
             ++idle;
             continue;
         }
         seen = ~0ull;
+        fenced = false;
         // a worker may stall between seeing a slot open and claiming (the
         // slot can finish and be recycled meanwhile: the claim must notice)
         if (rng() % 4 == 0) std::this_thread::sleep_for(std::chrono::microseconds(rng() % 80));
@@ -200,8 +208,7 @@ static void worker(unsigned seed)
             ++idle;
             continue;
         }
-        // the record as the lanes read it while the claim is outstanding
-        HostEnv::dev_fence_acquire();
+        // the record as lane 0 reads it while the claim is outstanding
         Req rec;
         read_record(&rec, &D->slots[best], rng);
         const uint64_t seq = c.seq;
@@ -221,7 +228,6 @@ static void worker(unsigned seed)
             pixels[seq - 1][tile] = seq * 1000003ull + tile;  // plain write, published by the protocol
             if (rng() % 7 == 0) std::this_thread::yield();
         }
-        __atomic_thread_fence(__ATOMIC_RELEASE);
         P::tiles_done(D, H, best, c);
         last = Clock::now();
         idle = 0;
