@@ -23,7 +23,15 @@ struct FaceHit {
 // an immediate instead of a register move per face (the plain forward's
 // staged scan: 3 % faster there; the kernels that keep more registers live
 // lose a wavefront per SIMD to it).
-template <bool UNROLL = false, typename P>
+// The face's offset from the ray origin, c - n.o (FP32, always this sequence).
+__device__ inline float face_num(float4 p, float ox, float oy, float oz)
+{
+    return p.w - fmaf(p.z, oz, fmaf(p.y, oy, p.x * ox));
+}
+
+// NUM = true: the row's fourth component already holds face_num for this
+// ray's origin (staged rows of a wavefront whose rays share their origin).
+template <bool UNROLL = false, bool NUM = false, typename P>
 __device__ inline FaceHit scan_row(P row, int deg, float ox, float oy, float oz, float dx, float dy, float dz)
 {
     float bn = 1.0f, bd = 0.0f;
@@ -35,7 +43,7 @@ __device__ inline FaceHit scan_row(P row, int deg, float ox, float oy, float oz,
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const float den = fmaf(p[u].z, dz, fmaf(p[u].y, dy, p[u].x * dx));
-            const float num = p[u].w - fmaf(p[u].z, oz, fmaf(p[u].y, oy, p[u].x * ox));
+            const float num = NUM ? p[u].w : face_num(p[u], ox, oy, oz);
             const bool better = (k + u < deg) && (den > 0.0f) && (num * bd < bn * den);
             bn = better ? num : bn;
             bd = better ? den : bd;
@@ -179,19 +187,18 @@ __device__ inline double face_den(const float* xi, const float* xj, double dx, d
 // ---------------------------------------------------------------------------
 // Each wavefront's region is 10 KiB, so that sixteen one-wavefront blocks
 // fill the 160 KiB of LDS (four wavefronts per SIMD, what the registers
-// allow). The split between face and record slots is chosen on traces of
-// the clustered 1M-site frame, where a wavefront step touches 9.5 distinct
-// cells on average (p90: 17). A staged record takes only its used bytes (208
-// of the 256 of an FP32 record at degree 3, 112 of 128 in BF16), which leaves
-// room for 380 faces beside 20 FP32 records (472 beside 24 in BF16). With
-// 320 faces and 256-byte record slots, 6.7 % of the FP32 steps had a lane
-// whose cell did not fit (then the wavefront also runs the scan from global
-// memory); the larger face region made the FP32 forward 4 % faster.
+// allow). A wavefront step touches 9.5 distinct cells on average on the
+// clustered 1M-site frame (p90: 17), and the region keeps cells from step to
+// step (StageCache). A staged record takes only its used bytes (208 of the
+// 256 of an FP32 record at degree 3, 112 of 128 in BF16). The split between
+// record and face slots, 22 records beside 352 faces in FP32 and 28 beside
+// 444 in BF16, was the fastest measured there (20 / 24 records: 2 % slower
+// forwards; 16 or 18 FP32 records: 4-8 % slower).
 template <int DEG, bool BF16>
 struct StageLayout {
     using R = Rec<DEG, BF16>;
     static constexpr int kBudget = 10240;
-    static constexpr int kRecs = BF16 ? 24 : 20;                       // record slots
+    static constexpr int kRecs = BF16 ? 28 : 22;                       // record slots
     static constexpr int kRecStride = R::CHUNKS * 16;                         // the record's used bytes
     static constexpr int kFaces = (kBudget - kRecs * kRecStride) / 16 / 4 * 4;  // face slots (16 B each)
     static constexpr int kRecOff = kFaces * 16;
@@ -200,61 +207,123 @@ struct StageLayout {
 };
 
 
-// Called with every lane of the wavefront active. Lanes with `want` stage the
-// row and record of their cell `ref`; on return face_slot / rec_slot give the
-// position of the copy in `region` (-1: not staged, read from global memory).
+// The cells a wavefront has staged, kept from step to step: the lanes of a
+// tile reach many cells a step or two after other lanes of the tile left
+// them (on the clustered 1M-site frame 80 % of a step's cells were staged
+// the step before), so a cell found here needs no copy. Entry e (lane e of
+// `key` and `face`, e < n) is cell `key` (its ref.x), its row at face slot
+// `face` and its record in record slot e. Slots are handed out in order and
+// all freed together when a step starts with less room left than a step
+// usually needs.
+struct StageCache {
+    uint32_t key = 0;
+    int face = 0;
+    uint64_t valid = 0;  // entries in use (wavefront-uniform): bit e for e < n
+    int n = 0;
+    int faces = 0;       // face slots in use
+};
+
+// Called with every lane of the wavefront active. Lanes with `want` need the
+// row and record of their cell `ref` in `region`; each distinct cell is
+// looked up in the cache, and copied in (direct global-to-LDS loads) if it is
+// not there. On return face_slot / rec_slot give the position of the copy
+// (-1: the cell did not fit, read from global memory).
+// With `num` (wavefront-uniform: every walking lane's ray has the origin
+// (sx, sy, sz), bit for bit, for as long as the cache lives) each staged
+// plane's offset c is replaced by face_num for that origin, computed once
+// per staged face instead of once per lane, face and step: the scans then
+// read the same bits they would have computed.
 template <int DEG, bool BF16>
-__device__ inline void stage_cells(const SceneView& s, bool want, uint2 ref, lds_u8* region, int& face_slot,
-                                   int& rec_slot)
+__device__ inline void stage_cells(const SceneView& s, bool want, uint2 ref, lds_u8* region, StageCache& cache,
+                                   int& face_slot, int& rec_slot, bool num = false, float sx = 0.0f,
+                                   float sy = 0.0f, float sz = 0.0f)
 {
     using SL = StageLayout<DEG, BF16>;
     using R = Rec<DEG, BF16>;
     const int lane = __lane_id();
     const uint32_t lane16 = 16u * (uint32_t)lane;
+    // start afresh only once the region is (nearly) full: the longer cells
+    // stay, the more steps find them (flushing with room for ~5 cells left
+    // made the forward 5 % slower, with ~3 left 3 %); a step whose new cells
+    // do not all fit reads those from global memory
+    if (cache.faces > SL::kFaces - 16 || cache.n == SL::kRecs) {
+        cache.n = 0;
+        cache.faces = 0;
+        cache.valid = 0;
+    }
+    const int first_new = cache.faces, first_entry = cache.n;
     uint64_t pend = ballot(want);
-    int off = 0, nrec = 0;
     face_slot = -1;
     rec_slot = -1;
     while (pend) {
         const int leader = __builtin_ctzll(pend);
         // ref.x = cell | deg << 24 identifies the cell
         const uint32_t kx = __builtin_amdgcn_readlane(ref.x, leader);
-        const int gbeg = __builtin_amdgcn_readlane(ref.y, leader);
-        const int key = (int)(kx & 0xffffffu), gdeg = (int)(kx >> 24);
         // the lanes still pending with this cell (a ballot of the bare
         // compare, masked in scalar registers); kept per lane as well, as
         // testing the mask's bit costs five VALU instructions
         const bool mine = want && ref.x == kx;
         const uint64_t members = ballot(ref.x == kx) & pend;
         pend &= ~members;
-        if (off + gdeg > SL::kFaces || nrec == SL::kRecs) continue;
-        for (int k0 = 0; k0 < gdeg; k0 += kWave)
-            if (k0 + lane < gdeg)
-                copy16_to_lds(s.planes + gbeg + k0, 16u * kWave, lane16, region + (off + k0) * 16);
-        if (lane < R::CHUNKS)
-            copy16_to_lds(s.rec + (size_t)key * R::BYTES, R::BYTES, lane16, region + SL::kRecOff + nrec * SL::kRecStride);
-        if (mine) {
-            face_slot = off;
-            rec_slot = nrec;
+        const uint64_t hit = ballot(cache.key == kx) & cache.valid;
+        int e, fo;
+        if (hit) {
+            e = __builtin_ctzll(hit);
+            fo = __builtin_amdgcn_readlane(cache.face, e);
+        } else {
+            const int gdeg = (int)(kx >> 24);
+            if (cache.faces + gdeg > SL::kFaces || cache.n == SL::kRecs) continue;
+            const int gbeg = __builtin_amdgcn_readlane(ref.y, leader);
+            const int key = (int)(kx & 0xffffffu);
+            e = cache.n;
+            fo = cache.faces;
+            for (int k0 = 0; k0 < gdeg; k0 += kWave)
+                if (k0 + lane < gdeg)
+                    copy16_to_lds(s.planes + gbeg + k0, 16u * kWave, lane16, region + (fo + k0) * 16);
+            if (lane < R::CHUNKS)
+                copy16_to_lds(s.rec + (size_t)key * R::BYTES, R::BYTES, lane16, region + SL::kRecOff + e * SL::kRecStride);
+            if (lane == e) {
+                cache.key = kx;
+                cache.face = fo;
+            }
+            cache.valid |= 1ull << e;
+            ++cache.n;
+            cache.faces += gdeg;
         }
-        off += gdeg;
-        ++nrec;
+        if (mine) {
+            face_slot = fo;
+            rec_slot = e;
+        }
     }
-    __builtin_amdgcn_s_waitcnt(0);  // the copies have landed in LDS
-    __builtin_amdgcn_wave_barrier();
+    if (cache.n != first_entry) {
+        __builtin_amdgcn_s_waitcnt(0);  // the copies have landed in LDS
+        __builtin_amdgcn_wave_barrier();
+        if (num) {
+            for (int f = first_new + lane; f < cache.faces; f += kWave) {
+                const f32x4 p = *(reinterpret_cast<lds_f32x4*>(region) + f);
+                reinterpret_cast<__attribute__((address_space(3))) float*>(region)[4 * f + 3] =
+                    face_num(make_float4(p.x, p.y, p.z, p.w), sx, sy, sz);
+            }
+            // (one wavefront's LDS accesses complete in order: the scans read the new values)
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
 }
 
 // visit_cell reading the staged copies where there are any.
+// `num`: the staged rows hold face_num for this ray's origin (wavefront-uniform).
 template <int DEG, bool BF16, bool UNROLL = false>
 __device__ inline void visit_cell_staged(const SceneView& s, uint2 ref, int face_slot, int rec_slot,
                                          lds_u8* region, double t0, float tmax, float ox, float oy, float oz,
                                          float dx, float dy, float dz, const float* Y, Visit<DEG>& v,
-                                         const double* hi = nullptr)
+                                         const double* hi = nullptr, bool num = false)
 {
     using SL = StageLayout<DEG, BF16>;
     const int cell = ref_cell(ref), beg = ref_beg(ref), deg = ref_deg(ref);
     lds_f32x4* lrow = reinterpret_cast<lds_f32x4*>(region) + face_slot;
-    if (face_slot >= 0)
+    if (face_slot >= 0 && num)
+        v.h = scan_row<UNROLL, true>(lrow, deg, ox, oy, oz, dx, dy, dz);
+    else if (face_slot >= 0)
         v.h = scan_row<UNROLL>(lrow, deg, ox, oy, oz, dx, dy, dz);
     else
         v.h = nearest_front_face(s.planes, beg, deg, ox, oy, oz, dx, dy, dz);
@@ -532,6 +601,25 @@ __device__ inline void walk_forward_staged(const SceneView& s, bool live, float 
     if constexpr (SURF) {
         if (live) leg_start(*sf, ox, oy, oz, dx, dy, dz, tmax, leg);
     }
+    // Rays of one camera share their origin: then the staging computes each
+    // face's offset from it once (bent legs have origins of their own)
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+    bool shared = false;
+    if constexpr (!SURF) {
+        const uint64_t lv = ballot(live);
+        if (lv) {
+            const int l0 = __builtin_ctzll(lv);
+            const uint32_t bx = __builtin_amdgcn_readlane(__float_as_uint(ox), l0);
+            const uint32_t by = __builtin_amdgcn_readlane(__float_as_uint(oy), l0);
+            const uint32_t bz = __builtin_amdgcn_readlane(__float_as_uint(oz), l0);
+            shared = ballot(live && (__float_as_uint(ox) != bx || __float_as_uint(oy) != by ||
+                                     __float_as_uint(oz) != bz)) == 0;
+            sx = __uint_as_float(bx);
+            sy = __uint_as_float(by);
+            sz = __uint_as_float(bz);
+        }
+    }
+    StageCache cache;
     while (ballot(live)) {
         if (live) {
             if (!cont && !(T > eps)) {
@@ -543,7 +631,7 @@ __device__ inline void walk_forward_staged(const SceneView& s, bool live, float 
             }
         }
         int face_slot, rec_slot;
-        stage_cells<DEG, BF16>(s, live, ref, region, face_slot, rec_slot);
+        stage_cells<DEG, BF16>(s, live, ref, region, cache, face_slot, rec_slot, shared, sx, sy, sz);
         if (live) {
             if constexpr (LOG) {
                 if (n == lg->cap) tail = ref;
@@ -560,7 +648,8 @@ __device__ inline void walk_forward_staged(const SceneView& s, bool live, float 
             }
             Visit<DEG> v;
             visit_cell_staged<DEG, BF16, !TRACE && !LOG && !SURF>(s, ref, face_slot, rec_slot, region, t0, tmax, ox,
-                                                                  oy, oz, dx, dy, dz, Y, v, SURF ? leg.hi : nullptr);
+                                                                  oy, oz, dx, dy, dz, Y, v, SURF ? leg.hi : nullptr,
+                                                                  shared);
             bool cross = false;
             if constexpr (SURF) {
                 if (leg.ts < v.te) {
@@ -608,7 +697,7 @@ __device__ inline void walk_forward_staged(const SceneView& s, bool live, float 
                 t0 = v.te;
             }
         }
-        // the next round's copies overwrite this round's: every lane has read its own
+        // the next round's copies may overwrite this round's: every lane has read its own
         __builtin_amdgcn_wave_barrier();
     }
     res.T = T;

@@ -58,8 +58,11 @@ __device__ inline int64_t ray_index()
     return xcd_block<32>(blockIdx.x, gridDim.x) * kWalkBlock + threadIdx.x;
 }
 
+// The staging region (10 KiB per wavefront) allows four wavefronts per SIMD;
+// the walks that do not bend keep their registers within that (the logged
+// FP32 walk needs 130 and would run three), the bent ones (150-160) run three.
 template <int DEG, bool BF16, bool TRACE, bool LOG, bool SURF = false>
-__global__ __launch_bounds__(kWalkBlock) void k_forward(WalkArgs a)
+__global__ __launch_bounds__(kWalkBlock) __attribute__((amdgpu_waves_per_eu(SURF ? 3 : 4))) void k_forward(WalkArgs a)
 {
     using SL = StageLayout<DEG, BF16>;
     __shared__ __align__(16) unsigned char stage_mem[(kWalkBlock / kWave) * SL::kBytes];
