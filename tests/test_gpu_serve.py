@@ -150,6 +150,35 @@ def test_bf16_scene_served_equals_batch_path(setup, mode):
                 np.testing.assert_array_equal(out["images"][i], alone[i], err_msg=f"{label} request {i}")
 
 
+def test_large_launches_stage_and_equal_batch_path(setup):
+    """Launches of 8,192 tiles (the most a launch takes) walk with the cells
+    staged in LDS (the batch forward's walk), smaller ones without: the images
+    are the batch path's bit for bit either way. A 1021x519 request alone is
+    128 x 65 = 8,320 tiles (edge tiles with lanes past the image): a staged
+    launch of 8,192 tiles and a plain one of 128, so both walks render parts
+    of one image; a burst of three such requests and a small one fills staged
+    launches that mix requests."""
+    rf, scene, packed, reqs, alone = setup
+    from paper_2502_01157_amd.serve import Server, replay
+
+    W, H = 1021, 519
+    big = [dict(r, width=W, height=H, arrival=0.0) for r in reqs[:3]] + [dict(reqs[0], arrival=0.0)]
+    ref = []
+    for r in big:
+        o, d, t, s, px = rf.raygen(r["pose12"], r["fov_deg"], r["width"], r["height"], scene.bound,
+                                   r["start_cell"])
+        rgb, tf, _ = rf.render_forward(packed, o, d, t, s)
+        img = np.zeros((r["height"] * r["width"], 4), dtype=np.float32)
+        img[px.cpu().numpy()] = np.concatenate([rgb.cpu().numpy(), tf.cpu().numpy()[:, None]], 1)
+        ref.append(img.reshape(r["height"], r["width"], 4))
+    with Server(packed, scene.bound, pool_bytes=64 << 20, max_inflight=8, mode="launches") as srv:
+        one = replay(srv, big[:1], keep=[0], timeout_s=30)
+        np.testing.assert_array_equal(one["images"][0], ref[0])
+        out = replay(srv, big, keep=range(len(big)), timeout_s=30)
+    for i in range(len(big)):
+        np.testing.assert_array_equal(out["images"][i], ref[i], err_msg=f"request {i}")
+
+
 def test_admission_by_memory_and_fifo(setup):
     rf, scene, packed, reqs, alone = setup
     from paper_2502_01157_amd.serve import Server, replay
