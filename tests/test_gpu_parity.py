@@ -133,6 +133,13 @@ def test_pack_planes_and_records(rf, clustered, dtype):
     np.testing.assert_allclose(planes[:, :3], ref[:, :3], rtol=2 ** -24, atol=0)
     scale = np.linalg.norm(ref[:, :3], axis=1) * np.linalg.norm(scene.sites, axis=1).max()
     assert np.all(np.abs(planes[:, 3] - ref[:, 3]) <= 4e-7 * scale + 1e-30)
+    # each face's neighbour row (j | deg_j << 24, row start of j), exactly
+    a0 = p.desc.off_adj
+    adj = p.workspace[a0:a0 + 8 * scene.n_edges].cpu().numpy().view(np.uint32).reshape(-1, 2)
+    j = scene.idx.astype(np.int64)
+    deg = np.diff(scene.off).astype(np.int64)
+    np.testing.assert_array_equal(adj[:, 0], (j | (deg[j] << 24)).astype(np.uint32))
+    np.testing.assert_array_equal(adj[:, 1], scene.off[j].astype(np.uint32))
     dens, sh = (t.cpu().numpy() for t in p.attributes())
     if dtype == "f32":
         np.testing.assert_array_equal(dens, scene.density)
