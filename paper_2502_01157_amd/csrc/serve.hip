@@ -48,6 +48,7 @@ constexpr int kLaunchesInFlight = 2;
 constexpr int kLocalTileBits = 25;      // descriptor = slot << 25 | tile within the request
 constexpr int kSeedGrid = 16;           // seed grid for locating camera cells on the device
 constexpr int kStagedMinTiles = 8192;   // launches of at least this many tiles use the staged walk
+constexpr int kPersistStagedMinTiles = 8192;  // persistent form: requests of at least this many tiles
 
 struct ReqRecord {
     float rot[9];
@@ -296,7 +297,7 @@ __device__ void persistent_dispatcher(const PersistArgs& a, int lane)
 }
 
 template <int DEG, bool BF16>
-__device__ void persistent_worker(const PersistArgs& a, int lane)
+__device__ void persistent_worker(const PersistArgs& a, int lane, lds_u8* region)
 {
     uint64_t last = wall_clock64();
     uint32_t idle_units = 0;  // idle polls, in units of ~1 us
@@ -381,16 +382,28 @@ __device__ void persistent_worker(const PersistArgs& a, int lane)
                                           word(offsetof(sp::Req, out_offset_lo)));
         const int tiles_x = (W + 7) / 8;
         float* out_base = a.pool + out_off;
+        // a large request's tiles walk with their cells staged in LDS, as
+        // the launches' full launches do (the same bits either way); the
+        // staged walk needs the whole wavefront, so the choice is lane 0's
+        const bool staged = __builtin_amdgcn_readfirstlane(c.n_tiles) >= kPersistStagedMinTiles;
         for (int j = 0; j < cnt; ++j) {
             const int local = c.first + j;
             const int px = (local % tiles_x) * 8 + (lane & 7);
             const int py = (local / tiles_x) * 8 + (lane >> 3);
-            if (px < W && py < H) {
-                float d[3], tmax;
+            const bool live = px < W && py < H;
+            float d[3], tmax;
+            RayResult res;
+            if (staged) {
                 camera_ray(rot, pos, model, focal, W, H, px, py, a.bound_kind, a.bound, d, &tmax);
-                RayResult res;
+                walk_forward_staged<DEG, BF16, false, false>(a.s, live, pos[0], pos[1], pos[2], d[0], d[1], d[2], tmax,
+                                                             start, a.eps, a.max_steps, nullptr, nullptr, 0, res,
+                                                             nullptr, 0, region);
+            } else if (live) {
+                camera_ray(rot, pos, model, focal, W, H, px, py, a.bound_kind, a.bound, d, &tmax);
                 walk_forward<DEG, BF16, false>(a.s, pos[0], pos[1], pos[2], d[0], d[1], d[2], tmax, start, a.eps,
                                                a.max_steps, nullptr, nullptr, 0, res);
+            }
+            if (live) {
                 float4* out = reinterpret_cast<float4*>(out_base) + ((int64_t)py * W + px);
                 *out = make_float4(res.C[0], res.C[1], res.C[2], res.T);
             }
@@ -407,10 +420,11 @@ template <int DEG, bool BF16>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_serve_persistent(PersistArgs a)
 {
     const int lane = threadIdx.x;
+    __shared__ __align__(16) unsigned char stage_mem[StageLayout<DEG, BF16>::kBytes];
     if (blockIdx.x == 0)
         persistent_dispatcher<DEG, BF16>(a, lane);
     else
-        persistent_worker<DEG, BF16>(a, lane);
+        persistent_worker<DEG, BF16>(a, lane, (lds_u8*)stage_mem);
 }
 
 static const void* persistent_kernel(int deg, bool bf16)

@@ -150,14 +150,18 @@ def test_bf16_scene_served_equals_batch_path(setup, mode):
                 np.testing.assert_array_equal(out["images"][i], alone[i], err_msg=f"{label} request {i}")
 
 
-def test_large_launches_stage_and_equal_batch_path(setup):
+@pytest.mark.parametrize("mode", ["launches", "persistent"])
+def test_large_requests_stage_and_equal_batch_path(setup, mode):
     """Launches of 8,192 tiles (the most a launch takes) walk with the cells
-    staged in LDS (the batch forward's walk), smaller ones without: the images
-    are the batch path's bit for bit either way. A 1021x519 request alone is
-    128 x 65 = 8,320 tiles (edge tiles with lanes past the image): a staged
-    launch of 8,192 tiles and a plain one of 128, so both walks render parts
-    of one image; a burst of three such requests and a small one fills staged
-    launches that mix requests."""
+    staged in LDS (the batch forward's walk), smaller ones without; the
+    persistent workers stage the tiles of requests of 8,192 tiles or more.
+    The images are the batch path's bit for bit either way. A 1021x519
+    request is 128 x 65 = 8,320 tiles (edge tiles with lanes past the
+    image): alone in the launches form, a staged launch of 8,192 tiles and a
+    plain one of 128, so both walks render parts of one image; a burst of
+    three such requests and a small one fills staged launches that mix
+    requests (in the persistent form, workers move between staged and plain
+    tiles)."""
     rf, scene, packed, reqs, alone = setup
     from paper_2502_01157_amd.serve import Server, replay
 
@@ -171,7 +175,7 @@ def test_large_launches_stage_and_equal_batch_path(setup):
         img = np.zeros((r["height"] * r["width"], 4), dtype=np.float32)
         img[px.cpu().numpy()] = np.concatenate([rgb.cpu().numpy(), tf.cpu().numpy()[:, None]], 1)
         ref.append(img.reshape(r["height"], r["width"], 4))
-    with Server(packed, scene.bound, pool_bytes=64 << 20, max_inflight=8, mode="launches") as srv:
+    with Server(packed, scene.bound, pool_bytes=64 << 20, max_inflight=8, mode=mode) as srv:
         one = replay(srv, big[:1], keep=[0], timeout_s=30)
         np.testing.assert_array_equal(one["images"][0], ref[0])
         out = replay(srv, big, keep=range(len(big)), timeout_s=30)
